@@ -1,0 +1,204 @@
+/*
+ * rac.h — Recurrent Arc Consistency (RAC) enforcement on AMD Instinct MI355X
+ * (gfx950). C ABI.
+ *
+ * The operation (Section 3 of the paper): given a binary CSP — variables
+ * x = 0..n-1 with values 0..d-1, current domains D = {(x,a)}, and binary
+ * constraints c_xy with allowed-pair relations rel(c_xy) (Section 2) —
+ * compute the arc-consistency closure D_ac, the union of all arc-consistent
+ * subsets of D. It is computed by the recurrence of Eq. (1): in every step,
+ * every value (x,a) that has, on some constraint c_xy, no allowed partner b
+ * left in the current dom(y) is removed, all at once; steps repeat until one
+ * removes nothing (Proposition 1). After the first step only constraints into
+ * variables whose domain changed in the previous step are re-examined
+ * (Proposition 2; Algorithm 1's @changed). On a GPU each step is one pass over
+ * the relation rows with a device-side change flag, so no host round trip
+ * happens between steps.
+ *
+ * Conventions shared by every entry point
+ *   Domains    uint64 per variable: bit a is set iff a is in dom(x). Bits >= d
+ *              must be zero (RAC_EINVAL). 1 <= d <= 64.
+ *   Edges      int32 [m][2]; edge e constrains x = edges[2e] and
+ *              y = edges[2e+1]; x != y; at most one constraint per unordered
+ *              pair (a duplicate, including (y,x) after (x,y), is RAC_EINVAL).
+ *              Edge (x,y) with relation R yields the arc x->y with R and the
+ *              arc y->x with R transposed.
+ *   Result     dom is replaced by the closure; iters is the number of steps
+ *              executed, the last of which removed nothing (1 if D was
+ *              already arc consistent); status is RAC_WIPEOUT iff some domain
+ *              is empty at the end. A wipe-out is a result, not an error: the
+ *              paper's enforcer throws / returns None there (Algorithm 1).
+ *   Modes      RAC_RUN_TO_FIXPOINT (default) keeps stepping after a wipe-out,
+ *              so dom is always the closure D_ac; RAC_STOP_ON_WIPEOUT stops
+ *              after the first step that leaves a domain empty, as Algorithm 1
+ *              does, and returns the state after that step.
+ *   Ownership  create copies every input; the caller keeps its arrays. A net
+ *              owns its device memory until rac_destroy. Host-pointer entry
+ *              points are synchronous. Device-pointer entry points enqueue on
+ *              the given HIP stream and return; their buffers must stay valid
+ *              until the stream reaches the end of the call. Calls on one net
+ *              (or group) must not overlap in time.
+ *   Errors     negative return codes; on error, outputs are unspecified.
+ *              rac_strerror() names a code; rac_last_error() gives a message
+ *              for the calling thread's last failure.
+ */
+#ifndef RAC_H
+#define RAC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rac_net rac_net;
+typedef struct rac_group rac_group;
+
+enum {
+    RAC_OK = 0,
+    RAC_EINVAL = -1,          /* bad argument, layout or value */
+    RAC_ENOMEM = -2,          /* host or device allocation failed */
+    RAC_EHIP = -3,            /* a HIP runtime call failed */
+    RAC_EUNSUPPORTED = -4,    /* valid input outside what a path supports */
+    RAC_ENOTCONVERGED = -5,   /* max_sweeps reached while values were still being removed */
+    RAC_ENODEV = -6,          /* no usable gfx950 device */
+    RAC_ETIMEOUT = -7         /* the device scheduler's bounded wait expired (internal error) */
+};
+
+enum { RAC_CONSISTENT = 0, RAC_WIPEOUT = 1 };
+enum { RAC_RUN_TO_FIXPOINT = 0, RAC_STOP_ON_WIPEOUT = 1 };
+
+/* Which kernels compute the support tests. */
+enum {
+    RAC_PATH_AUTO = 0,   /* the autotuner chooses per call */
+    RAC_PATH_BITS = 1,   /* relation rows as bit masks; support = (row & dom(y)) != 0 */
+    RAC_PATH_INT8 = 2,   /* relation as 0/1 int8 blocks; support count = int32 dot product */
+    RAC_PATH_MFMA = 3    /* batched states: int8 x int8 -> int32 matrix-core products */
+};
+
+typedef struct rac_options {
+    int32_t mode;         /* RAC_RUN_TO_FIXPOINT or RAC_STOP_ON_WIPEOUT */
+    int32_t max_sweeps;   /* 0: n*d + 1, the bound of Proposition 1 */
+    int32_t path;         /* RAC_PATH_* */
+    int32_t use_graph;    /* 1 (default): replay captured HIP graphs; 0: direct launches */
+    int32_t item_bytes;   /* 0: autotuned; else target relation bytes per work item */
+    int32_t reserved[3];  /* must be zero */
+} rac_options;
+
+/* Per-call counters of the last enforcement on a net or group. */
+typedef struct rac_stats {
+    int64_t support_checks;  /* sum over steps and states of d*d per re-examined arc
+                                (arcs x->y with y changed in the previous step) */
+    int64_t sweeps;          /* sum over states of the steps executed */
+    int64_t relation_bytes;  /* relation bytes the kernels were asked to stream */
+    double device_ms;        /* device time of the enforcement kernels (HIP events) */
+    int32_t path;            /* RAC_PATH_* actually used */
+    int32_t item_bytes;      /* work-item size used by the bit / int8 path */
+    int32_t reserved[4];
+} rac_stats;
+
+/* Fills *opt with the defaults. */
+void rac_default_options(rac_options *opt);
+
+/*
+ * Creates a network from 0/1 bytes: rel is [m][d][d], rel[e][a][b] = 1 iff
+ * (x_e = a, y_e = b) is allowed (any nonzero byte counts as 1). The relation
+ * tensor of the paper (Algorithm 2, init) restricted to its constrained pairs.
+ * opt may be NULL (defaults). On success *out receives the net.
+ */
+int rac_create(int32_t n, int32_t d, int64_t m, const int32_t *edges, const uint8_t *rel,
+               const rac_options *opt, rac_net **out);
+
+/*
+ * Same, with each relation row packed: rel_rows is [m][d] uint64, bit b of
+ * rel_rows[e][a] = 1 iff (x_e = a, y_e = b) is allowed. Bits >= d must be 0.
+ */
+int rac_create_bits(int32_t n, int32_t d, int64_t m, const int32_t *edges,
+                    const uint64_t *rel_rows, const rac_options *opt, rac_net **out);
+
+/*
+ * Same, from the dense relation tensor R[x][a][y][b] (uint8, n*d*n*d bytes,
+ * the Cons tensor of Algorithm 2 in [x,a,y,b] order) plus the edge list that
+ * says which pairs are constrained. Blocks of unconstrained pairs are never
+ * read. The block R[y,.,x,.] must equal the transpose of R[x,.,y,.] for every
+ * edge (RAC_EINVAL otherwise).
+ */
+int rac_create_dense(int32_t n, int32_t d, const uint8_t *R, int64_t m, const int32_t *edges,
+                     const rac_options *opt, rac_net **out);
+
+void rac_destroy(rac_net *net);
+
+/*
+ * Enforces arc consistency on one domain state (tensorAC of Algorithm 1).
+ * dom: [n] host uint64, in/out. changed: NULL = every variable changed (the
+ * first call); else n_changed variable indices forming the initial @changed
+ * set, with the precondition that D without those variables' reductions was
+ * already arc consistent (Proposition 2) — the caller's promise, not checked.
+ * iters, status: host int32, may be NULL.
+ */
+int rac_enforce(rac_net *net, uint64_t *dom, const int32_t *changed, int32_t n_changed,
+                int32_t *iters, int32_t *status);
+
+/*
+ * Enforces arc consistency on B independent domain states of one network
+ * (e.g. search nodes under different partial assignments). dom: [B][n] host
+ * uint64, in/out; iters, status: [B] host int32 (may be NULL). Every state
+ * starts with @changed = all variables.
+ */
+int rac_enforce_batch(rac_net *net, int32_t B, uint64_t *dom, int32_t *iters, int32_t *status);
+
+/*
+ * Device-pointer form of rac_enforce_batch: d_dom_in [B][n] and d_dom_out
+ * [B][n] uint64 (may be the same buffer), d_iters and d_status [B] int32, all
+ * in device memory of the net's device; enqueued on `stream` (a hipStream_t,
+ * NULL = the null stream). Returns after enqueueing; per-call errors detected
+ * on the device (max_sweeps reached, scheduler timeout) are reported by the
+ * next call or by rac_sync_status().
+ */
+int rac_enforce_batch_device(rac_net *net, int32_t B, const uint64_t *d_dom_in,
+                             uint64_t *d_dom_out, int32_t *d_iters, int32_t *d_status,
+                             void *stream);
+
+/* Waits for the net's last device-pointer call and returns its error code. */
+int rac_sync_status(rac_net *net);
+
+/*
+ * Many independent networks of uneven n, d and density, one domain state
+ * each, enforced together in one persistent launch. dom[i] is [n_i] host
+ * uint64 for nets[i], in/out; iters, status: [k] host int32 (may be NULL).
+ * Equivalent to k calls of rac_enforce, each with @changed = all.
+ */
+int rac_enforce_multi(int32_t k, rac_net *const *nets, uint64_t *const *dom, int32_t *iters,
+                      int32_t *status);
+
+/*
+ * A group fixes a list of nets once (device descriptor tables, work items,
+ * the autotuned choice per net and a captured graph), so repeated calls
+ * avoid that set-up. rac_group_enforce has the semantics of
+ * rac_enforce_multi. The nets must outlive the group.
+ */
+int rac_group_create(int32_t k, rac_net *const *nets, const rac_options *opt, rac_group **out);
+int rac_group_enforce(rac_group *g, uint64_t *const *dom, int32_t *iters, int32_t *status);
+/* Device-pointer form: d_dom is [sum_i n_i] uint64 in device memory, the
+ * states of nets[0..k-1] back to back, in/out; d_iters, d_status [k]. */
+int rac_group_enforce_device(rac_group *g, uint64_t *d_dom, int32_t *d_iters,
+                             int32_t *d_status, void *stream);
+int rac_group_sync_status(rac_group *g);
+void rac_group_destroy(rac_group *g);
+
+/* Counters of the last call on a net / group (host-pointer calls, or after a
+ * rac_sync_status / rac_group_sync_status). */
+int rac_net_stats(const rac_net *net, rac_stats *out);
+int rac_group_stats(const rac_group *g, rac_stats *out);
+
+/* Sizes of a net (any pointer may be NULL). */
+int rac_net_info(const rac_net *net, int32_t *n, int32_t *d, int64_t *m, int64_t *arcs);
+
+const char *rac_strerror(int code);
+const char *rac_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAC_H */

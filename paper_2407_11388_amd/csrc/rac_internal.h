@@ -1,0 +1,124 @@
+// Internal types shared by the host code and the gfx950 kernels of librac.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rac {
+
+constexpr int kWave = 64;                  // CDNA wavefront width
+constexpr int kStageMax = 2048;            // networks up to this many variables are staged in LDS
+
+// How the relation rows of a network are stored for one path.
+//
+// Bit rows (ROW32 / ROW64): the arcs of each variable are padded to a
+// multiple of 64 and stored in groups of 64 arcs. Within a group, the rows of
+// one arc are cut into 16-byte quads (4 uint32 rows or 2 uint64 rows), and
+// quad q of the 64 arcs is stored contiguously: quad q of arc l of group g is
+// at byte g*qpa*1024 + q*1024 + l*16. A wave reads one group with lane = arc,
+// each of its loads covering 1 KiB of consecutive memory.
+//
+// int8 rows (ROWI8): arcs unpadded, arc j holds d rows of dp bytes (0/1).
+enum RowKind : int32_t {
+    ROW32 = 0,  // uint32 rows (d <= 32); dp = d rounded up to 4 rows; qpa = dp/4
+    ROW64 = 1,  // uint64 rows (d <= 64); dp = d rounded up to 8 rows; qpa = dp/2
+    ROWI8 = 2   // 0/1 int8 rows (d <= 32); dp = bytes per row = d rounded up to 16
+};
+
+constexpr int kGroup = 64;        // arcs per group of the bit-row layout
+
+// One network as seen by the sweep kernel (device memory, read-only).
+// Arcs leaving x: row_ptr[x] .. row_ptr[x+1]-1 (to nbr[j]); in the padded
+// group layout, groups gptr[x] .. gptr[x+1]-1 with nbrp[g*64 + l] the
+// neighbour of arc l of group g, or -1 for padding.
+struct NetDesc {
+    const int32_t *row_ptr;   // [n+1]
+    const int32_t *nbr;       // [arcs]
+    const int32_t *gptr;      // [n+1] group offsets (bit rows)
+    const int32_t *nbrp;      // [groups*64] (bit rows)
+    const int32_t *deg;       // [n]
+    const void *rows;
+    const int4 *items;        // [nitems] {x_begin, x_end, unit_begin, unit_end}; units are
+                              // groups for bit rows, arcs for int8 rows
+    const int32_t *pieces;    // [nitems] 0: whole variables; k >= 1: one piece of x split in k
+    int32_t n, d, dp, kind;
+    int32_t nitems, qpa;
+    int64_t arcs;
+};
+
+// Fixpoint control block of one problem (one domain state of one network).
+// A step's work items are split into `nlanes` contiguous lanes, each with its
+// own claim ticket and completion counter on its own cache line, so that no
+// single address takes every item's atomics.
+struct Ctrl {
+    unsigned long long degsum[2];  // sum of deg(x) over variables changed in steps of that parity
+    long long checks;              // support checks so far (d*d per re-examined arc)
+    int32_t lanes_done;            // lanes whose items all completed in the current step
+    int32_t nlanes;
+    int32_t last_change;           // last step that removed a value (0 = none yet)
+    int32_t wiped;                 // a domain is empty (domains only shrink: sticky)
+    int32_t done;                  // 1 once the problem has stopped
+    int32_t iters, status, rc;
+    int32_t pad[20];               // 128 bytes
+};
+
+struct Lane {
+    unsigned long long ticket;     // (step << 32) | next unclaimed item of the lane
+    int32_t finish;                // items of the lane completed in the current step
+    int32_t start, count;          // the lane's items: start .. start+count-1
+    int32_t pad[27];               // 128 bytes
+};
+
+struct Global {
+    int32_t active;   // problems not yet done
+    int32_t error;    // nonzero: a bounded wait expired; every workgroup leaves
+    int32_t pad[2];
+};
+
+// Device workspace of a set of problems; variable v of problem p lives at off[p] + v.
+struct Workspace {
+    uint64_t *dom[2];     // double buffer: sweep k reads dom[(k-1)&1], writes dom[k&1]
+    uint32_t *chg[2];     // chg[k&1][v] = 1 iff step k shrank dom(v); chg[0] starts as @changed
+    uint64_t *failacc;    // OR of the values failing on pieces of a split variable
+    int32_t *xcnt;        // pieces of a split variable finished in the current sweep
+    Ctrl *ctrl;           // [nprob]
+    Lane *lanes;          // [nprob * lanes_per_prob]
+    Global *global;
+};
+
+// Everything one enforcement launch needs (passed by value).
+struct Launch {
+    const NetDesc *nets;      // [nnet]
+    const int32_t *prob_net;  // [nprob]
+    const int64_t *prob_off;  // [nprob + 1]
+    const int64_t *item_off;  // [nprob + 1] prefix sums of the problems' item counts
+    int32_t nprob;
+    int32_t mode;             // RAC_RUN_TO_FIXPOINT / RAC_STOP_ON_WIPEOUT
+    int32_t max_sweeps;       // 0: per network n*d + 1
+    int32_t spin_limit;       // bounded wait (polls) of an idle workgroup
+    int32_t lanes_per_prob;   // lane slots reserved per problem (a power of two <= 64)
+    int32_t stage_vars;       // LDS staging capacity in variables (0: none)
+    Workspace ws;
+    const uint64_t *din;      // [prob_off[nprob]] initial domains
+    uint64_t *dout;           // [prob_off[nprob]] results
+    int32_t *iters_out;       // [nprob] or null
+    int32_t *status_out;      // [nprob] or null
+    const uint8_t *changed0;  // [prob_off[nprob]] initial @changed flags, or null (= all)
+    long long *checks_out;    // [nprob] or null
+    long long checks1;        // support checks of step 1 when changed0 is given (else 2m*d*d)
+    int32_t *rc_out;          // [1]: worst per-problem return code of the call
+};
+
+// Records a message for rac_last_error() and returns `code` (rac_host.hip).
+int set_error(int code, const char *fmt, ...);
+
+// Kernel entry points (defined in sweep.hip), launched by rac_host.hip.
+__global__ void init_kernel(Launch L);
+__global__ void sweep_kernel(Launch L);
+__global__ void finish_kernel(Launch L);
+__global__ void pack_bits_kernel(const uint64_t *rel, const int32_t *src_p, int64_t groups,
+                                 int32_t d, int32_t qpa, int32_t kind, uint4 *out);
+__global__ void pack_i8_kernel(const uint64_t *rel, const int32_t *arc_src, int64_t arcs,
+                               int32_t d, int32_t rows_per_arc, int32_t dp, int8_t *out);
+
+}  // namespace rac

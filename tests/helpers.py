@@ -76,3 +76,21 @@ def clique_neq(n, d):
     allowed = [(a, b) for a in range(d) for b in range(d) if a != b]
     cons = [(x, y, allowed) for x in range(n) for y in range(x + 1, n)]
     return instance_from_pairs(n, d, cons)
+
+
+def oracle_expect(n, d, edges, rel_u8, dom_masks, mode=0, changed=None, max_steps=0):
+    """What the oracle says for one state: (dom masks [n], iters, status, checks, converged).
+
+    Run-to-fixpoint: domains and status from AC-3 (the closure D_ac), the step
+    count from the Eq. (1) recurrence; the two must agree on the domains.
+    Stop-on-wipe-out: everything from the recurrence."""
+    import oracle
+
+    dom_u8 = masks_to_u8(dom_masks, d)
+    r = oracle.rac_sync(n, d, edges, rel_u8, dom_u8, changed0=changed, mode=mode,
+                        max_steps=max_steps)
+    if mode == 0 and changed is None and r["converged"]:
+        dac, status, _, _ = oracle.ac3(n, d, edges, rel_u8, dom_u8)
+        assert np.array_equal(dac, r["dom"]), "oracle disagrees with itself"
+        assert status == r["status"]
+    return u8_to_masks(r["dom"]), r["iters"], r["status"], r["checks"], r["converged"]

@@ -1,0 +1,210 @@
+"""GPU parity: every result of the HIP paths equals the CPU oracle bit for bit
+(domains, step count, wipe-out status and support-check count), on the tiny,
+golden and medium instances, for the bit-row and int8-row paths, both stop
+modes, forced item splitting, graph and direct launches, incremental starts,
+the step cap, batched states and groups of networks."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2407_11388_amd import gen
+
+from helpers import (golden_cases, golden_instance, masks_to_u8, oracle_expect, u8_to_masks)
+
+pytestmark = pytest.mark.gpu
+
+rac = pytest.importorskip("paper_2407_11388_amd.rac")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_vs_oracle(name, n, d, edges, rel_u8, dom_masks, path, mode=0, item_bytes=0,
+                  use_graph=True, changed=None):
+    say(f"[gpu] {name} n={n} d={d} m={len(edges)} path={path} mode={mode} "
+        f"item_bytes={item_bytes} graph={use_graph}")
+    net = rac.Net.from_u8(n, d, edges, rel_u8, path=path, mode=mode, item_bytes=item_bytes,
+                          use_graph=use_graph)
+    got, iters, status = net.enforce(dom_masks, changed=changed)
+    st = net.stats()
+    exp, e_iters, e_status, e_checks, _ = oracle_expect(n, d, edges, rel_u8, dom_masks, mode,
+                                                        changed)
+    assert np.array_equal(got, exp), f"{name}: domains differ"
+    assert iters == e_iters, f"{name}: iters {iters} != {e_iters}"
+    assert status == e_status
+    assert st.support_checks == e_checks, f"{name}: checks {st.support_checks} != {e_checks}"
+    net.close()
+
+
+PATHS = [rac.PATH_BITS, rac.PATH_INT8]
+CASES = golden_cases()
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("case", CASES, ids=[c["name"] for c in CASES])
+def test_golden(case, mode, path):
+    n, d, edges, rel, dom = golden_instance(case)
+    gpu_vs_oracle(case["name"], n, d, edges, rel, u8_to_masks(dom), path, mode)
+
+
+def _tiny(seed):
+    n = 2 + seed % 6
+    d = 1 + (seed // 6) % 6
+    p1 = [0.4, 0.7, 1.0][seed % 3]
+    p2 = [0.2, 0.45, 0.7][(seed // 3) % 3]
+    keep = [1.0, 0.75][(seed // 9) % 2]
+    inst, dom = gen.random_tiny(5000 + seed, n, d, p1, p2, keep)
+    return inst, dom
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("seed", range(0, 72, 3))
+def test_tiny_random(seed, path):
+    inst, dom = _tiny(seed)
+    for mode in (0, 1):
+        gpu_vs_oracle(f"tiny{seed}", inst.n, inst.d, inst.edges, inst.rel_u8(), dom, path, mode)
+
+
+MEDIUM_D = [1, 3, 4, 5, 10, 17, 20, 31, 32, 33, 40, 63, 64]
+
+
+@pytest.mark.parametrize("d", MEDIUM_D)
+@pytest.mark.parametrize("item_bytes", [0, 256])
+def test_medium_bits(d, item_bytes):
+    n = 60
+    p2 = 0.5 if d <= 4 else (0.62 if d <= 12 else 0.8)
+    inst = gen.model_b(900 + d, n, d, 0.35, p2)
+    dom = gen.preremove(901 + d, n, d, (n * d) // 6)
+    for mode in (0, 1):
+        gpu_vs_oracle(f"medium-d{d}", n, d, inst.edges, inst.rel_u8(), dom, rac.PATH_BITS, mode,
+                      item_bytes=item_bytes, use_graph=(d % 2 == 0))
+
+
+@pytest.mark.parametrize("d", [d for d in MEDIUM_D if d <= 32])
+def test_medium_int8(d):
+    n = 50
+    p2 = 0.5 if d <= 4 else (0.62 if d <= 12 else 0.8)
+    inst = gen.model_b(700 + d, n, d, 0.4, p2)
+    dom = gen.preremove(701 + d, n, d, (n * d) // 5)
+    for mode in (0, 1):
+        for ib in (0, 512):
+            gpu_vs_oracle(f"medium-int8-d{d}", n, d, inst.edges, inst.rel_u8(), dom,
+                          rac.PATH_INT8, mode, item_bytes=ib)
+
+
+def test_incremental_start():
+    n, d = 80, 8
+    inst = gen.model_b(31, n, d, 0.2, 0.45)
+    rel = inst.rel_u8()
+    base, status, _, _ = oracle.ac3(n, d, inst.edges, rel, np.ones((n, d), np.uint8))
+    assert status == 0
+    for x in range(0, n, 11):
+        st = base.copy()
+        vals = np.nonzero(st[x])[0]
+        st[x] = 0
+        st[x, vals[0]] = 1
+        gpu_vs_oracle(f"incremental-x{x}", n, d, inst.edges, rel, u8_to_masks(st),
+                      rac.PATH_BITS, 0, changed=[x])
+
+
+def test_step_cap_reports_not_converged():
+    L, d = 9, 12
+    allowed = [(a, b) for a in range(d) for b in range(d) if a < b]
+    edges = np.array([[i, i + 1] for i in range(L)], np.int32)
+    rel = np.zeros((L, d, d), np.uint8)
+    for a, b in allowed:
+        rel[:, a, b] = 1
+    dom = np.full(L + 1, (1 << d) - 1, np.uint64)
+    say("[gpu] step cap")
+    net = rac.Net.from_u8(L + 1, d, edges, rel, max_sweeps=4)
+    with pytest.raises(rac.RacError) as ei:
+        net.enforce(dom)
+    assert ei.value.code == rac.RAC_ENOTCONVERGED
+    net.close()
+    # resume: the full run equals a capped run then a second run
+    net = rac.Net.from_u8(L + 1, d, edges, rel)
+    full, it_full, _ = net.enforce(dom)
+    exp = oracle.rac_sync(L + 1, d, edges, rel, masks_to_u8(dom, d), trace=True)
+    mid = u8_to_masks(exp["trace"][3])
+    rest, it_rest, _ = net.enforce(mid)
+    assert np.array_equal(full, rest) and it_full == 4 + it_rest == L + 1
+    net.close()
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_states_bits(use_graph):
+    n, d, B = 40, 6, 37
+    inst = gen.model_b(12, n, d, 0.5, 0.4)
+    doms, _ = gen.partial_assign_states(13, n, d, B, 8)
+    rel = inst.rel_u8()
+    say(f"[gpu] batch bits B={B} graph={use_graph}")
+    net = rac.Net.from_u8(n, d, inst.edges, rel, path=rac.PATH_BITS, use_graph=use_graph)
+    for rep in range(2):
+        got, iters, status = net.enforce_batch(doms)
+        total_checks = 0
+        for s in range(B):
+            exp, e_it, e_st, e_ch, _ = oracle_expect(n, d, inst.edges, rel, doms[s])
+            assert np.array_equal(got[s], exp), f"state {s}"
+            assert iters[s] == e_it and status[s] == e_st
+            total_checks += e_ch
+        assert net.stats().support_checks == total_checks
+    net.close()
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_group_of_networks(use_graph):
+    rng = np.random.default_rng(5)
+    nets, doms, insts = [], [], []
+    for i in range(23):
+        n = int(rng.integers(2, 70))
+        d = int(rng.integers(1, 65))
+        inst = gen.model_b(100 + i, n, d, float(rng.uniform(0.1, 1.0)), float(rng.uniform(0.1, 0.8)))
+        insts.append(inst)
+        nets.append(rac.Net.from_instance(inst))
+        doms.append(gen.preremove(200 + i, n, d, (n * d) // 7))
+    say(f"[gpu] group k={len(nets)} graph={use_graph}")
+    grp = rac.Group(nets, use_graph=use_graph)
+    for rep in range(2):
+        outs, iters, status = grp.enforce(doms)
+        for i, inst in enumerate(insts):
+            exp, e_it, e_st, _, _ = oracle_expect(inst.n, inst.d, inst.edges, inst.rel_u8(), doms[i])
+            assert np.array_equal(outs[i], exp), f"instance {i}"
+            assert iters[i] == e_it and status[i] == e_st
+    outs2, it2, st2 = rac.enforce_multi(nets, doms)
+    for i in range(len(nets)):
+        assert np.array_equal(outs2[i], outs[i]) and it2[i] == iters[i]
+    grp.close()
+    for n_ in nets:
+        n_.close()
+
+
+def test_empty_domains_and_isolated_variables():
+    n, d = 7, 5
+    edges = np.array([[0, 1], [1, 2], [4, 5]], np.int32)
+    rel = np.ones((3, d, d), np.uint8)
+    dom = np.array([31, 31, 31, 0, 31, 0, 31], np.uint64)   # x3 isolated & empty, x5 empty
+    for mode in (0, 1):
+        gpu_vs_oracle("empty-isolated", n, d, edges, rel, dom, rac.PATH_BITS, mode)
+    # no constraints at all
+    gpu_vs_oracle("no-edges", n, d, np.zeros((0, 2), np.int32), np.zeros((0, d, d), np.uint8),
+                  dom, rac.PATH_BITS, 0)
+
+
+def test_dense_create_matches():
+    inst = gen.model_b(3, 12, 5, 0.5, 0.5)
+    n, d = 12, 5
+    u8 = inst.rel_u8()
+    R = np.zeros((n, d, n, d), np.uint8)
+    for e, (x, y) in enumerate(inst.edges):
+        R[x, :, y, :] = u8[e]
+        R[y, :, x, :] = u8[e].T
+    dom = gen.full_domains(n, d)
+    say("[gpu] dense create")
+    a = rac.Net.from_dense(n, d, R, inst.edges).enforce(dom)
+    b = rac.Net.from_bits(n, d, inst.edges, inst.rel).enforce(dom)
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1]
