@@ -1,0 +1,246 @@
+"""Benchmark of the RAC fixpoint on one MI355X.
+
+A step is one enforcement of the whole hot path over one batch of synthetic
+input already resident in HBM. The default workload is the batched-state
+configuration: one model-B network (n=1000, d=32, p1=0.8, p2=0.25) and 1024
+domain states, each a random partial assignment of 0..20 variables; every
+state is run to its arc-consistency fixpoint in one call of
+rac_enforce_batch_device (matrix-core path chosen by the autotuner).
+
+Printed (one JSON line): support checks/s of the batched call (value),
+fixpoints/s, the same states through the plain per-state loop (1024
+sequential rac_enforce calls, each with its own host round trip), the
+roofline of the dominant kernel (HIP events around each of its launches),
+the CPU oracle timed on a bounded sample of the same states, and secondary
+single-instance measurements.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 matrix-core peak, TOP/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batch-states",
+                    choices=["batch-states", "single-large", "single-mid", "single-small"])
+    ap.add_argument("--B", type=int, default=1024)
+    ap.add_argument("--plain-states", type=int, default=1024,
+                    help="states timed through the plain per-state loop")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="approximate budget of the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline_batch(inst, doms, budget_s):
+    """The CPU oracle on the first states of the batch until the time budget
+    is used (one thread): its Eq. (1) recurrence (the same steps and support
+    checks as the GPU path) gives support checks/s and fixpoints/s; AC-3 is
+    timed on the same states as well."""
+    import oracle
+
+    n, d = inst.n, inst.d
+    rel = inst.rel_u8()
+    t_rec = t_ac3 = 0.0
+    checks = 0
+    done = 0
+    for s in range(doms.shape[0]):
+        du8 = oracle.dom_masks_to_u8(doms[s], d)
+        t0 = time.perf_counter()
+        r = oracle.rac_sync(n, d, inst.edges, rel, du8)
+        t_rec += time.perf_counter() - t0
+        checks += r["checks"]
+        t0 = time.perf_counter()
+        oracle.ac3(n, d, inst.edges, rel, du8)
+        t_ac3 += time.perf_counter() - t0
+        done += 1
+        if t_rec >= budget_s:
+            break
+    return dict(value=checks / t_rec, unit="support checks/s", cores=1, kind="oracle",
+                sample=f"oracle Eq. (1) recurrence on the first {done} of {doms.shape[0]} "
+                       f"states, one thread, {t_rec:.1f} s",
+                fixpoints_per_s=done / t_rec, ac3_fixpoints_per_s=done / t_ac3)
+
+
+def cpu_baseline_single(inst, dom, budget_s):
+    import oracle
+
+    n, d = inst.n, inst.d
+    rel = inst.rel_u8()
+    du8 = oracle.dom_masks_to_u8(dom, d)
+    t0 = time.perf_counter()
+    reps = 0
+    checks = 0
+    while True:
+        checks = oracle.rac_sync(n, d, inst.edges, rel, du8)["checks"]
+        reps += 1
+        if time.perf_counter() - t0 >= budget_s or reps >= 5:
+            break
+    t = (time.perf_counter() - t0) / reps
+    t1 = time.perf_counter()
+    oracle.ac3(n, d, inst.edges, rel, du8)
+    t_ac3 = time.perf_counter() - t1
+    return dict(value=checks / t, unit="support checks/s", cores=1, kind="oracle",
+                sample=f"oracle Eq. (1) recurrence, one thread, {reps} run(s) of the instance",
+                fixpoints_per_s=1.0 / t, ac3_fixpoints_per_s=1.0 / t_ac3)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the batched "
+              "states and instances shard across GPUs without communication, but this "
+              "build runs and reports a single MI355X.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2407_11388_amd import rac
+    from paper_2407_11388_amd.gen import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    out = dict(metric="support checks/s + AC fixpoints/s, batched int8-MFMA vs plain, bit-exact",
+               unit="support checks/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               higher_is_better=True, scaling="weak", vs_baseline=None,
+               data="synthetic (seeded model-B random CSPs)")
+
+    if args.workload == "batch-states":
+        w = workloads.batch_states(B=args.B)
+        inst, doms = w.instances[0], w.domains[0]
+        B, n, d = doms.shape[0], inst.n, inst.d
+        net = rac.Net.from_instance(inst, profile=True)
+        d_in = torch.from_numpy(doms.view(np.int64)).to(dev)
+        d_out = torch.empty_like(d_in)
+        d_it = torch.empty(B, dtype=torch.int32, device=dev)
+        d_st = torch.empty(B, dtype=torch.int32, device=dev)
+        stream = torch.cuda.current_stream().cuda_stream
+
+        def step():
+            net.enforce_batch_device(d_in, d_out, d_it, d_st, stream)
+
+        for _ in range(args.warmup):
+            step()
+        net.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kms, klaunch, ops = 0.0, 0, 0
+        for _ in range(args.steps):
+            step()
+            net.sync()          # collects the step's per-launch kernel timings
+            st = net.stats()
+            kms += st.kernel_ms
+            klaunch += st.kernel_launches
+            ops += st.algo_ops
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / args.steps
+        st = net.stats()
+        checks = st.support_checks
+        iters = d_it.cpu().numpy()
+        status = d_st.cpu().numpy()
+        path = rac.PATH_NAMES.get(st.path, str(st.path))
+
+        # plain per-state loop: sequential rac_enforce calls on the same states
+        P = min(args.plain_states, B)
+        net_plain = rac.Net.from_instance(inst, path=rac.PATH_BITS)
+        for s in range(min(8, P)):
+            net_plain.enforce(doms[s])
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        for s in range(P):
+            net_plain.enforce(doms[s])
+        tp = (time.perf_counter() - tp0) / P
+        net_plain.close()
+
+        fix_s = B / t
+        plain_fix_s = 1.0 / tp
+        achieved = ops / (kms * 1e-3) / 1e12 if kms > 0 else None
+        out.update(
+            value=checks / t, ms_per_step=t * 1e3, dtype="i8",
+            config=dict(workload="batch-states: model-B n=1000 d=32 p1=0.8 p2=0.25, "
+                                 f"B={B} partial-assignment states (0..20 singletons)",
+                        B=B, n=n, d=d, arcs=int(2 * inst.m), path=path,
+                        mode="run-to-fixpoint"),
+            fixpoints_per_s=fix_s,
+            plain_loop=dict(fixpoints_per_s=plain_fix_s, states=P, path="bits",
+                            note="sequential rac_enforce calls, host round trip each"),
+            batched_vs_plain=fix_s / plain_fix_s,
+            steps_hist=np.bincount(iters).tolist(), wiped_states=int(status.sum()),
+            roofline=dict(kernel="mfma_sweep_kernel", bound="mfma", achieved=achieved,
+                          peak=INT8_PEAK_TOPS, unit="TOP/s",
+                          frac=(achieved / INT8_PEAK_TOPS) if achieved else None,
+                          traffic=None, launches=klaunch,
+                          avg_launch_ms=kms / klaunch if klaunch else None,
+                          per_unit="2*d*d int8 ops per (arc, active state, step)"),
+        )
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline_batch(inst, doms, args.cpu_seconds)
+        net.close()
+    else:
+        name = args.workload.replace("-", "_")
+        w = getattr(workloads, name)()
+        inst, dom = w.instances[0], w.domains[0]
+        net = rac.Net.from_instance(inst, profile=True, path=rac.PATH_BITS)
+        for _ in range(args.warmup):
+            net.enforce(dom)
+        kms, t_host = 0.0, 0.0
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            net.enforce(dom)
+            t_host += time.perf_counter() - t0
+            kms += net.stats().kernel_ms
+        st = net.stats()
+        t = kms / args.steps * 1e-3
+        gbs = st.relation_bytes / t / 1e9
+        out.update(value=st.support_checks / t, ms_per_step=t * 1e3, dtype="u32 bit rows",
+                   config=dict(workload=w.name, path="bits"),
+                   fixpoints_per_s=1.0 / t, host_ms_per_call=t_host / args.steps * 1e3,
+                   roofline=dict(kernel="sweep_kernel", bound="hbm", achieved=gbs,
+                                 peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS,
+                                 traffic=None, per_unit="relation bytes of every re-examined arc"))
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline_single(inst, dom, args.cpu_seconds)
+        net.close()
+
+    if not args.no_secondary and args.workload == "batch-states":
+        sec = {}
+        wl = workloads.single_large()
+        inst, dom = wl.instances[0], wl.domains[0]
+        for pname, p in (("bits", rac.PATH_BITS), ("int8", rac.PATH_INT8)):
+            net = rac.Net.from_instance(inst, path=p, profile=True)
+            for _ in range(3):
+                net.enforce(dom)
+            best = 1e9
+            for _ in range(10):
+                net.enforce(dom)
+                best = min(best, net.stats().kernel_ms)
+            stt = net.stats()
+            gbs = stt.relation_bytes / (best * 1e-3) / 1e9
+            sec[f"single-large n=2000 d=32 p1=0.9 p2=0.2 [{pname}]"] = dict(
+                kernel_ms=best, relation_GBs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
+                support_checks_per_s=stt.support_checks / (best * 1e-3), steps=int(stt.sweeps))
+            net.close()
+        out["secondary"] = sec
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -82,7 +82,9 @@ typedef struct rac_options {
     int32_t path;         /* RAC_PATH_* */
     int32_t use_graph;    /* 1 (default): replay captured HIP graphs; 0: direct launches */
     int32_t item_bytes;   /* 0: autotuned; else target relation bytes per work item */
-    int32_t reserved[3];  /* must be zero */
+    int32_t profile;      /* 1: time every launch of the dominant kernel with HIP events
+                             (rac_stats.kernel_ms / kernel_launches); 0 (default): off */
+    int32_t reserved[2];  /* must be zero */
 } rac_options;
 
 /* Per-call counters of the last enforcement on a net or group. */
@@ -92,9 +94,15 @@ typedef struct rac_stats {
     int64_t sweeps;          /* sum over states of the steps executed */
     int64_t relation_bytes;  /* relation bytes the kernels were asked to stream */
     double device_ms;        /* device time of the enforcement kernels (HIP events) */
+    double kernel_ms;        /* with options.profile: summed duration of the dominant
+                                kernel's launches that had work (persistent sweep kernel,
+                                or the matrix-core step kernel) */
+    int64_t kernel_launches; /* with options.profile: number of those launches */
+    int64_t algo_ops;        /* algorithmic int8 operations of the matrix-core step kernel:
+                                2*d*d per (arc, active state, step); 0 on other paths */
     int32_t path;            /* RAC_PATH_* actually used */
     int32_t item_bytes;      /* work-item size used by the bit / int8 path */
-    int32_t reserved[4];
+    int32_t reserved[2];
 } rac_stats;
 
 /* Fills *opt with the defaults. */

@@ -1,24 +1,756 @@
-// Batched-state matrix-core path (gfx950 int8 MFMA).
+// Batched-state path on the gfx950 matrix cores.
+//
+// For B domain states of one network, the support counts of one step of
+// Eq. (1) are products of the 0/1 relation matrix R[(x,a),(y,b)] (int8) with
+// the 0/1 domain matrix Dom[(y,b), s] (int8): for a constrained pair (x,y),
+// count(x,a,y,s) = sum_b R[x,a,y,b] * Dom[y,b,s] (tensorRevise of
+// Algorithm 1; at most d <= 32, so int32 accumulation is exact). Unlike a
+// plain GEMM, the counts of different neighbours y are not summed: each
+// neighbour block gets a fresh int32 accumulator, and a value survives only
+// if every neighbour's count is non-zero (Algorithm 1 clamps the counts and
+// tests that the clamped sum equals the number of neighbours). The kernel
+// keeps the running minimum of the counts over y; a value survives iff that
+// minimum is non-zero.
+//
+// Tiling. A workgroup of 8 waves owns 8 variables x (one per wave) and 128
+// states (4 sub-tiles of 32 per wave). It walks y = 0..n-1 in blocks of 8:
+// the domain bytes of the block for its 128 states are staged in LDS (double
+// buffered, shared by the 8 waves), and every wave multiplies its x's
+// relation blocks for the constrained y of the block (arcs sorted by y,
+// fetched one block ahead) with them, one v_mfma_i32_32x32x32_i8 per (arc,
+// sub-tile). Workgroups of one x-tile are placed on one XCD so that the
+// relation blocks they share meet in that XCD's L2.
+//
+// Steps. Each step writes the new domain bytes (double buffer), and per
+// (variable, slot word of 32 states) a change mask and a wipe-out mask. A
+// reduce kernel folds those masks over the variables per state; a one-block
+// finalise kernel applies Algorithm 1's loop test per state and compacts the
+// states that go on into the next step's active list.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
 #include "rac_mfma.h"
 
 namespace rac {
 
-bool mfma_auto_choice(int32_t, int32_t, int64_t, int32_t) { return false; }
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 
-int mfma_ensure(MfmaData &, int32_t, int32_t, int64_t, const int32_t *, const int32_t *,
-                const int32_t *, const uint64_t *, const int32_t *, const std::vector<int32_t> &,
-                hipStream_t) {
-    return set_error(RAC_EUNSUPPORTED, "matrix-core path not available");
+constexpr int kMX = 8;            // variables per workgroup (one per wave)
+constexpr int kMSub = 4;          // 32-state sub-tiles per wave
+constexpr int kMS = 32 * kMSub;   // states per workgroup
+constexpr int kMY = 8;            // neighbours per LDS block
+constexpr int kMThreads = 64 * kMX;
+constexpr int kMaxChunk = 16;     // steps enqueued per group of steps
+
+struct MState {
+    long long checks;     // support checks so far
+    unsigned long long degsum;
+    int32_t changed;      // the current step changed this state
+    int32_t wiped;        // some domain is empty (sticky)
+    int32_t iters, status, rc, done;
+};
+
+struct MArgs {
+    int32_t n, d, N32;                // N32 = n * 32 bytes per state
+    const int32_t *row_ptr;           // [n+1] arcs of x, sorted by neighbour
+    const int32_t *nbr_s;             // [arcs]
+    const int32_t *deg;               // [n]
+    const int8_t *r8;                 // [arcs][32][32]
+    int8_t *dom8[2];                  // [capB][N32]
+    uint32_t *chg, *wipe;             // [n][words]
+    int32_t words;                    // capB / 32
+    int32_t *act[2];                  // active state lists (by step parity)
+    int32_t *cnt;                     // [2] active counts
+    MState *st;                       // [capB]
+    int32_t mode, max_sweeps, B, xcd_map;
+    long long checks1;                // support checks of step 1: 2m * d * d
+    const uint64_t *din;              // [B][n]
+    uint64_t *dout;                   // [B][n]
+    int32_t *iters_out, *status_out, *rc_out;
+    long long *checks_out;
+};
+
+// ---------------------------------------------------------------------------
+
+__global__ void mfma_init_kernel(MArgs A) {
+    const int64_t total = (int64_t)A.B * A.n;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = tid; i < total; i += nth) {
+        const int64_t s = i / A.n;
+        const int32_t x = (int32_t)(i - s * A.n);
+        const uint64_t dm = A.din[i];
+        uint32_t w[8];
+        for (int q = 0; q < 8; ++q) {
+            uint32_t v = 0;
+            for (int t = 0; t < 4; ++t)
+                if ((dm >> (4 * q + t)) & 1ull) v |= 1u << (8 * t);
+            w[q] = v;
+        }
+        uint4 *dst = reinterpret_cast<uint4 *>(A.dom8[0] + s * A.N32 + (int64_t)x * 32);
+        dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+        dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    }
+    for (int64_t s = tid; s < A.B; s += nth) {
+        MState &m = A.st[s];
+        m.checks = A.checks1;
+        m.degsum = 0;
+        m.changed = 0;
+        m.wiped = 0;
+        m.iters = 0;
+        m.status = 0;
+        m.rc = 0;
+        m.done = 0;
+        A.act[0][s] = (int32_t)s;
+    }
+    if (tid == 0) {
+        A.cnt[0] = A.B;
+        A.cnt[1] = 0;
+        if (A.rc_out) *A.rc_out = 0;
+    }
 }
-int mfma_enforce_host(MfmaData &, int32_t, uint64_t *, int32_t *, int32_t *, int32_t, int32_t,
-                      hipStream_t, rac_stats *) {
-    return set_error(RAC_EUNSUPPORTED, "matrix-core path not available");
+
+__global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
+    __shared__ v4i s_b[2][kMY][kMS][2];   // [buffer][y][state][half]: 2 x 32 KiB
+    const int nact = A.cnt[(k - 1) & 1];
+    // workgroup -> (x-tile, state tile); the state tiles of one x-tile share
+    // blockIdx % 8 and so an XCD
+    const int ntiles_s = (A.words * 32 + kMS - 1) / kMS;
+    int xt, stile;
+    if (A.xcd_map) {
+        const int b = blockIdx.x;
+        const int xcd = b & 7, r = b >> 3;
+        stile = r % ntiles_s;
+        xt = (r / ntiles_s) * 8 + xcd;
+    } else {
+        stile = blockIdx.x % ntiles_s;
+        xt = blockIdx.x / ntiles_s;
+    }
+    const int st0 = stile * kMS;
+    if (st0 >= nact || xt * kMX >= A.n) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int32_t *act = A.act[(k - 1) & 1];
+    auto state_of = [&](int i) { return st0 + i < nact ? act[st0 + i] : -1; };
+
+    const int x = xt * kMX + wave;
+    const bool xv = x < A.n;
+    int32_t jb = xv ? A.row_ptr[x] : 0;
+    const int32_t jend = xv ? A.row_ptr[x + 1] : 0;
+    const int8_t *dcur = A.dom8[(k - 1) & 1];
+    const int half = lane >> 5, col = lane & 31;
+
+    // B staging: thread t moves units u = t + 512 i of the block (y, state, half)
+    constexpr int kUnitsPerThread = kMY * kMS * 2 / kMThreads;   // 4
+    auto fetch_b = [&](int yb, v4i (&r)[kUnitsPerThread]) {
+#pragma unroll
+        for (int i = 0; i < kUnitsPerThread; ++i) {
+            const int u = tid + kMThreads * i;
+            const int yl = u / (kMS * 2), rem = u - yl * kMS * 2;
+            const int sl = rem >> 1, h = rem & 1;
+            const int s = state_of(sl);
+            const int y = yb + yl;
+            v4i v = {0, 0, 0, 0};
+            if (s >= 0 && y < A.n)
+                v = *reinterpret_cast<const v4i *>(dcur + (int64_t)s * A.N32 + (int64_t)y * 32 + h * 16);
+            r[i] = v;
+        }
+    };
+    auto store_b = [&](int buf, const v4i (&r)[kUnitsPerThread]) {
+#pragma unroll
+        for (int i = 0; i < kUnitsPerThread; ++i) {
+            const int u = tid + kMThreads * i;
+            const int yl = u / (kMS * 2), rem = u - yl * kMS * 2;
+            s_b[buf][yl][rem >> 1][rem & 1] = r[i];
+        }
+    };
+    // relation blocks of this wave's arcs with neighbours in [yb, yb + kMY)
+    auto fetch_a = [&](int32_t j0, int32_t cnt, v4i (&a)[kMY]) {
+#pragma unroll
+        for (int e = 0; e < kMY; ++e)
+            if (e < cnt)
+                a[e] = *reinterpret_cast<const v4i *>(A.r8 + (int64_t)(j0 + e) * 1024 + col * 32 + half * 16);
+    };
+    auto arcs_below = [&](int32_t j0, int ylim) {
+        int32_t j = j0;
+        while (j < jend && A.nbr_s[j] < ylim) ++j;
+        return j;
+    };
+
+    v16i rm[kMSub];
+#pragma unroll
+    for (int t = 0; t < kMSub; ++t)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) rm[t][v] = 0x7FFFFFFF;
+
+    v4i breg[kUnitsPerThread];
+    v4i acur[kMY], anext[kMY];
+    int32_t je = arcs_below(jb, kMY);
+    fetch_b(0, breg);
+    store_b(0, breg);
+    fetch_a(jb, je - jb, acur);
+    __syncthreads();
+    const int nblk = (A.n + kMY - 1) / kMY;
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int buf = blk & 1;
+        const int yb = blk * kMY;
+        // issue the next block's loads before the products of this one
+        const int32_t je2 = arcs_below(je, yb + 2 * kMY);
+        if (blk + 1 < nblk) {
+            fetch_b(yb + kMY, breg);
+            fetch_a(je, je2 - je, anext);
+        }
+        const int32_t ncur = je - jb;
+#pragma unroll
+        for (int e = 0; e < kMY; ++e) {
+            if (e < ncur) {
+                const int yl = A.nbr_s[jb + e] - yb;
+#pragma unroll
+                for (int t = 0; t < kMSub; ++t) {
+                    const v4i bop = s_b[buf][yl][t * 32 + col][half];
+                    const v16i zero = {0};
+                    const v16i c = __builtin_amdgcn_mfma_i32_32x32x32_i8(acur[e], bop, zero, 0, 0, 0);
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) rm[t][v] = min(rm[t][v], c[v]);
+                }
+            }
+        }
+        if (blk + 1 < nblk) {
+            store_b(buf ^ 1, breg);
+#pragma unroll
+            for (int e = 0; e < kMY; ++e) acur[e] = anext[e];
+        }
+        jb = je;
+        je = je2;
+        __syncthreads();
+    }
+
+    // epilogue: new domain bytes and per-state change / wipe-out masks
+    if (!xv) return;
+    int8_t *dnext = A.dom8[k & 1];
+#pragma unroll
+    for (int t = 0; t < kMSub; ++t) {
+        const int slot = st0 + t * 32 + col;
+        const int s = state_of(t * 32 + col);
+        bool changed = false, nonempty = false;
+        if (s >= 0) {
+            const int8_t *src = dcur + (int64_t)s * A.N32 + (int64_t)x * 32;
+            int8_t *dst = dnext + (int64_t)s * A.N32 + (int64_t)x * 32;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                // rows a = 8g + 4*half + r, r = 0..3, are consecutive bytes
+                const int a0 = 8 * g + 4 * half;
+                const uint32_t old = *reinterpret_cast<const uint32_t *>(src + a0);
+                uint32_t keep = 0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (rm[t][4 * g + r] != 0) keep |= 0xFFu << (8 * r);
+                const uint32_t nw = old & keep;
+                *reinterpret_cast<uint32_t *>(dst + a0) = nw;
+                changed |= nw != old;
+                nonempty |= nw != 0;
+            }
+        }
+        // both lanes of a state column exchange their halves; the shuffles
+        // run in every lane (no short-circuit), as ds_bpermute reads the
+        // source lane's register
+        const int other_changed = __shfl_xor((int)changed, 32, 64);
+        const int other_nonempty = __shfl_xor((int)nonempty, 32, 64);
+        changed = changed || other_changed != 0;
+        nonempty = nonempty || other_nonempty != 0;
+        const bool wiped = s >= 0 && !nonempty;
+        const uint64_t mc = __ballot(changed && s >= 0);
+        const uint64_t mw = __ballot(wiped);
+        if (lane == 0) {
+            const int w = (st0 + t * 32) >> 5;
+            A.chg[(int64_t)x * A.words + w] = (uint32_t)mc;
+            A.wipe[(int64_t)x * A.words + w] = (uint32_t)mw;
+        }
+        (void)slot;
+    }
 }
-int mfma_enforce_device(MfmaData &, int32_t, const uint64_t *, uint64_t *, int32_t *, int32_t *,
-                        int32_t, int32_t, hipStream_t) {
-    return set_error(RAC_EUNSUPPORTED, "matrix-core path not available");
+
+// Per slot word: OR of the change and wipe-out masks over all variables, and
+// the sum of deg(x) over the variables that changed (support checks of the
+// next step: every arc into a changed variable is re-examined).
+__global__ void mfma_reduce_kernel(MArgs A, int k) {
+    __shared__ uint32_t s_or, s_wp;
+    __shared__ unsigned long long s_deg[32];
+    const int nact = A.cnt[(k - 1) & 1];
+    const int w = blockIdx.x;
+    if (w * 32 >= nact) return;
+    if (threadIdx.x == 0) {
+        s_or = 0;
+        s_wp = 0;
+    }
+    if (threadIdx.x < 32) s_deg[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t c_or = 0, w_or = 0;
+    for (int x = threadIdx.x; x < A.n; x += blockDim.x) {
+        const uint32_t c = A.chg[(int64_t)x * A.words + w];
+        c_or |= c;
+        w_or |= A.wipe[(int64_t)x * A.words + w];
+        uint32_t m = c;
+        while (m) {
+            const int b = __ffs(m) - 1;
+            m &= m - 1;
+            atomicAdd(&s_deg[b], (unsigned long long)A.deg[x]);
+        }
+    }
+    if (c_or) atomicOr(&s_or, c_or);
+    if (w_or) atomicOr(&s_wp, w_or);
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        const int slot = w * 32 + threadIdx.x;
+        if (slot < nact) {
+            MState &m = A.st[A.act[(k - 1) & 1][slot]];
+            m.changed = (s_or >> threadIdx.x) & 1u;
+            m.wiped |= (int32_t)((s_wp >> threadIdx.x) & 1u);
+            m.degsum = s_deg[threadIdx.x];
+        }
+    }
 }
-int mfma_sync_status(MfmaData &, rac_stats *) { return RAC_OK; }
-void mfma_release(MfmaData &md) { md.ready = false; }
+
+// Algorithm 1's loop test per state, and the next step's active list.
+__global__ __launch_bounds__(1024) void mfma_finalize_kernel(MArgs A, int k) {
+    __shared__ int32_t s_wave_tot[16];
+    __shared__ int32_t s_base;
+    const int nact = A.cnt[(k - 1) & 1];
+    const int32_t *act = A.act[(k - 1) & 1];
+    int32_t *nxt = A.act[k & 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t maxs = A.max_sweeps > 0 ? A.max_sweeps : A.n * A.d + 1;
+    if (threadIdx.x == 0) s_base = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < nact; c0 += 1024) {
+        const int slot = c0 + threadIdx.x;
+        bool keep = false;
+        int32_t s = -1;
+        if (slot < nact) {
+            s = act[slot];
+            MState &m = A.st[s];
+            const bool changed = m.changed != 0;
+            const bool stop_on_wipe = (A.mode == RAC_STOP_ON_WIPEOUT) && m.wiped;
+            if (changed && !stop_on_wipe && k < maxs) {
+                m.checks += (long long)m.degsum * A.d * A.d;
+                keep = true;
+            } else {
+                m.iters = k;
+                m.status = m.wiped ? RAC_WIPEOUT : RAC_CONSISTENT;
+                m.rc = (changed && !stop_on_wipe) ? RAC_ENOTCONVERGED : 0;
+                m.done = 1;
+            }
+        }
+        const uint64_t bal = __ballot(keep);
+        const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) s_wave_tot[wave] = __popcll(bal);
+        __syncthreads();
+        int off = s_base;
+        for (int w = 0; w < wave; ++w) off += s_wave_tot[w];
+        if (keep) nxt[off + pre] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int w = 0; w < 16; ++w) tot += s_wave_tot[w];
+            s_base += tot;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) A.cnt[k & 1] = s_base;
+}
+
+__global__ void mfma_pack_kernel(MArgs A) {
+    const int64_t total = (int64_t)A.B * A.n;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = tid; i < total; i += nth) {
+        const int64_t s = i / A.n;
+        const int32_t x = (int32_t)(i - s * A.n);
+        const int32_t it = A.st[s].iters;
+        const uint32_t *src =
+            reinterpret_cast<const uint32_t *>(A.dom8[it & 1] + s * A.N32 + (int64_t)x * 32);
+        uint64_t dm = 0;
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t v = src[q];
+            for (int t = 0; t < 4; ++t)
+                if ((v >> (8 * t)) & 0xFFu) dm |= 1ull << (4 * q + t);
+        }
+        A.dout[i] = dm;
+    }
+    for (int64_t s = tid; s < A.B; s += nth) {
+        const MState &m = A.st[s];
+        if (A.iters_out) A.iters_out[s] = m.iters;
+        if (A.status_out) A.status_out[s] = m.status;
+        if (A.checks_out) A.checks_out[s] = m.checks;
+        if (A.rc_out && (m.rc != 0 || !m.done)) atomicOr(A.rc_out, m.done ? 1 : 4);
+    }
+}
+
+// Relation blocks in the matrix-core layout: out[j][a][b] for the arcs in
+// neighbour-sorted order (src_sorted[j] = 2e + flip), 32 x 32 bytes, zero
+// beyond d.
+__global__ void mfma_pack_r8_kernel(const uint64_t *rel, const int32_t *src_sorted, int64_t arcs,
+                                    int32_t d, int8_t *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // one row per thread
+    if (i >= arcs * 32) return;
+    const int64_t j = i >> 5;
+    const int32_t a = (int32_t)(i & 31);
+    uint64_t row = 0;
+    if (a < d) {
+        const int32_t src = src_sorted[j];
+        const uint64_t *R = rel + (int64_t)(src >> 1) * d;
+        if ((src & 1) == 0) {
+            row = R[a];
+        } else {
+            for (int b = 0; b < d; ++b) row |= ((R[b] >> a) & 1ull) << b;
+        }
+    }
+    uint32_t w[8];
+    for (int q = 0; q < 8; ++q) {
+        uint32_t v = 0;
+        for (int t = 0; t < 4; ++t)
+            if ((row >> (4 * q + t)) & 1ull) v |= 1u << (8 * t);
+        w[q] = v;
+    }
+    uint4 *dst = reinterpret_cast<uint4 *>(out + j * 1024 + (int64_t)a * 32);
+    dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+#define HIP_OK(call)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return set_error(e_ == hipErrorOutOfMemory ? RAC_ENOMEM : RAC_EHIP, "%s: %s", \
+                             #call, hipGetErrorString(e_));                             \
+    } while (0)
+
+struct MfmaImpl {
+    int32_t *row_ptr = nullptr, *nbr_s = nullptr;
+    const int32_t *deg = nullptr;
+    int8_t *r8 = nullptr;
+    int32_t capB = 0, words = 0;
+    int8_t *dom8[2] = {nullptr, nullptr};
+    uint32_t *chg = nullptr, *wipe = nullptr;
+    int32_t *act[2] = {nullptr, nullptr};
+    int32_t *cnt = nullptr;
+    MState *st = nullptr;
+    uint64_t *hin = nullptr, *hout = nullptr;   // device staging for host calls
+    int32_t *d_iters = nullptr, *d_status = nullptr, *d_rc = nullptr;
+    long long *d_checks = nullptr;
+    int32_t *h_cnt = nullptr;                    // pinned host copy of the active count
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_cnt = nullptr;
+    hipEvent_t kev[2 * 64] = {};                 // step kernel timing (profiling)
+    bool profiled = false;
+    int32_t last_B = 0;
+    int32_t *last_rc_ptr = nullptr;
+};
+
+static MfmaImpl *impl(MfmaData &md) { return reinterpret_cast<MfmaImpl *>(md.impl); }
+
+template <typename T> static void mfree(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+void mfma_release(MfmaData &md) {
+    MfmaImpl *m = impl(md);
+    if (!m) return;
+    mfree(m->row_ptr);
+    mfree(m->nbr_s);
+    mfree(m->r8);
+    mfree(m->dom8[0]);
+    mfree(m->dom8[1]);
+    mfree(m->chg);
+    mfree(m->wipe);
+    mfree(m->act[0]);
+    mfree(m->act[1]);
+    mfree(m->cnt);
+    mfree(m->st);
+    mfree(m->hin);
+    mfree(m->hout);
+    mfree(m->d_iters);
+    mfree(m->d_status);
+    mfree(m->d_rc);
+    mfree(m->d_checks);
+    if (m->h_cnt) (void)hipHostFree(m->h_cnt);
+    if (m->ev0) (void)hipEventDestroy(m->ev0);
+    if (m->ev1) (void)hipEventDestroy(m->ev1);
+    if (m->ev_cnt) (void)hipEventDestroy(m->ev_cnt);
+    for (auto &e : m->kev)
+        if (e) (void)hipEventDestroy(e);
+    delete m;
+    md.impl = nullptr;
+    md.ready = false;
+}
+
+bool mfma_auto_choice(int32_t d, int32_t n, int64_t arcs, int32_t B) {
+    if (d > 32 || B < 64 || n < 8) return false;
+    const double density = (double)arcs / ((double)n * (double)(n - 1));
+    return density >= 0.25;
+}
+
+int mfma_ensure(MfmaData &md, int32_t n, int32_t d, int64_t arcs, const int32_t *row_ptr,
+                const int32_t *nbr, const int32_t *deg, const uint64_t *rel,
+                const int32_t *arc_src, const std::vector<int32_t> &h_row_ptr,
+                hipStream_t stream) {
+    if (md.ready) return RAC_OK;
+    if (d > 32) return set_error(RAC_EUNSUPPORTED, "the matrix-core path needs d <= 32 (d=%d)", d);
+    MfmaImpl *m = new MfmaImpl();
+    md.impl = m;
+    md.n = n;
+    md.d = d;
+    md.arcs = arcs;
+    m->deg = deg;
+    // arcs of every variable sorted by neighbour
+    std::vector<int32_t> h_nbr((size_t)arcs), h_src((size_t)arcs);
+    if (arcs > 0) {
+        HIP_OK(hipMemcpy(h_nbr.data(), nbr, (size_t)arcs * 4, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(h_src.data(), arc_src, (size_t)arcs * 4, hipMemcpyDeviceToHost));
+    }
+    std::vector<int32_t> nbr_s((size_t)arcs), src_s((size_t)arcs), perm;
+    for (int32_t x = 0; x < n; ++x) {
+        const int32_t j0 = h_row_ptr[x], j1 = h_row_ptr[x + 1];
+        perm.resize((size_t)(j1 - j0));
+        for (int32_t j = j0; j < j1; ++j) perm[(size_t)(j - j0)] = j;
+        std::sort(perm.begin(), perm.end(),
+                  [&](int32_t p, int32_t q) { return h_nbr[(size_t)p] < h_nbr[(size_t)q]; });
+        for (int32_t j = j0; j < j1; ++j) {
+            nbr_s[(size_t)j] = h_nbr[(size_t)perm[(size_t)(j - j0)]];
+            src_s[(size_t)j] = h_src[(size_t)perm[(size_t)(j - j0)]];
+        }
+    }
+    int32_t *d_src = nullptr;
+    HIP_OK(hipMalloc(&m->row_ptr, ((size_t)n + 1) * 4));
+    HIP_OK(hipMalloc(&m->nbr_s, std::max<size_t>(1, (size_t)arcs) * 4));
+    HIP_OK(hipMalloc(&m->r8, std::max<size_t>(1, (size_t)arcs) * 1024));
+    HIP_OK(hipMalloc(&d_src, std::max<size_t>(1, (size_t)arcs) * 4));
+    HIP_OK(hipMemcpy(m->row_ptr, row_ptr, ((size_t)n + 1) * 4, hipMemcpyDeviceToDevice));
+    if (arcs > 0) {
+        HIP_OK(hipMemcpy(m->nbr_s, nbr_s.data(), (size_t)arcs * 4, hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(d_src, src_s.data(), (size_t)arcs * 4, hipMemcpyHostToDevice));
+        const int64_t threads = arcs * 32;
+        hipLaunchKernelGGL(mfma_pack_r8_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
+                           stream, rel, d_src, arcs, d, m->r8);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipStreamSynchronize(stream));
+    }
+    (void)hipFree(d_src);
+    HIP_OK(hipHostMalloc((void **)&m->h_cnt, sizeof(int32_t) * 2, hipHostMallocDefault));
+    HIP_OK(hipEventCreate(&m->ev0));
+    HIP_OK(hipEventCreate(&m->ev1));
+    HIP_OK(hipEventCreateWithFlags(&m->ev_cnt, hipEventDisableTiming));
+    for (auto &e : m->kev) HIP_OK(hipEventCreate(&e));
+    md.ready = true;
+    return RAC_OK;
+}
+
+static int ensure_capacity(MfmaData &md, int32_t B) {
+    MfmaImpl *m = impl(md);
+    const int32_t capB = (B + kMS - 1) / kMS * kMS;
+    if (capB <= m->capB) return RAC_OK;
+    mfree(m->dom8[0]);
+    mfree(m->dom8[1]);
+    mfree(m->chg);
+    mfree(m->wipe);
+    mfree(m->act[0]);
+    mfree(m->act[1]);
+    mfree(m->cnt);
+    mfree(m->st);
+    mfree(m->hin);
+    mfree(m->hout);
+    mfree(m->d_iters);
+    mfree(m->d_status);
+    mfree(m->d_rc);
+    mfree(m->d_checks);
+    const size_t N32 = (size_t)md.n * 32;
+    const int32_t words = capB / 32;
+    HIP_OK(hipMalloc(&m->dom8[0], (size_t)capB * N32));
+    HIP_OK(hipMalloc(&m->dom8[1], (size_t)capB * N32));
+    HIP_OK(hipMalloc(&m->chg, (size_t)md.n * words * 4));
+    HIP_OK(hipMalloc(&m->wipe, (size_t)md.n * words * 4));
+    HIP_OK(hipMalloc(&m->act[0], (size_t)capB * 4));
+    HIP_OK(hipMalloc(&m->act[1], (size_t)capB * 4));
+    HIP_OK(hipMalloc(&m->cnt, 2 * 4));
+    HIP_OK(hipMalloc(&m->st, (size_t)capB * sizeof(MState)));
+    HIP_OK(hipMalloc(&m->hin, (size_t)capB * md.n * 8));
+    HIP_OK(hipMalloc(&m->hout, (size_t)capB * md.n * 8));
+    HIP_OK(hipMalloc(&m->d_iters, (size_t)capB * 4));
+    HIP_OK(hipMalloc(&m->d_status, (size_t)capB * 4));
+    HIP_OK(hipMalloc(&m->d_rc, 4));
+    HIP_OK(hipMalloc(&m->d_checks, (size_t)capB * 8));
+    m->capB = capB;
+    m->words = words;
+    return RAC_OK;
+}
+
+static MArgs make_args(MfmaData &md, int32_t B, const uint64_t *din, uint64_t *dout,
+                       int32_t *it, int32_t *stt, int32_t mode, int32_t max_sweeps) {
+    MfmaImpl *m = impl(md);
+    MArgs A;
+    memset(&A, 0, sizeof(A));
+    A.n = md.n;
+    A.d = md.d;
+    A.N32 = md.n * 32;
+    A.row_ptr = m->row_ptr;
+    A.nbr_s = m->nbr_s;
+    A.deg = m->deg;
+    A.r8 = m->r8;
+    A.dom8[0] = m->dom8[0];
+    A.dom8[1] = m->dom8[1];
+    A.chg = m->chg;
+    A.wipe = m->wipe;
+    A.words = m->words;   // row stride of the mask matrices (capacity / 32)
+    A.act[0] = m->act[0];
+    A.act[1] = m->act[1];
+    A.cnt = m->cnt;
+    A.st = m->st;
+    A.mode = mode;
+    A.max_sweeps = max_sweeps;
+    A.B = B;
+    A.xcd_map = 1;
+    A.checks1 = md.arcs * md.d * md.d;
+    A.din = din;
+    A.dout = dout;
+    A.iters_out = it;
+    A.status_out = stt;
+    A.rc_out = m->d_rc;
+    A.checks_out = m->d_checks;
+    return A;
+}
+
+// Enqueues the whole enforcement; waits on the device only between groups of
+// kMaxChunk steps (to learn whether another group is needed).
+static int run(MfmaData &md, const MArgs &A, bool profile, hipStream_t stream) {
+    MfmaImpl *m = impl(md);
+    m->profiled = profile;
+    const int ntiles_s = (A.words * 32 + kMS - 1) / kMS;
+    const int ntiles_x = (A.n + kMX - 1) / kMX;
+    const int sweep_blocks = ((ntiles_x + 7) / 8) * 8 * ntiles_s;
+    const int init_blocks = (int)std::min<int64_t>(4096, ((int64_t)A.B * A.n + 255) / 256);
+    const int32_t maxs = A.max_sweeps > 0 ? A.max_sweeps : A.n * A.d + 1;
+    HIP_OK(hipEventRecord(m->ev0, stream));
+    hipLaunchKernelGGL(mfma_init_kernel, dim3(init_blocks), dim3(256), 0, stream, A);
+    int k = 1;
+    for (;;) {
+        const int kend = std::min<int>(k + kMaxChunk - 1, maxs);
+        for (; k <= kend; ++k) {
+            const bool timed = profile && k <= 64;
+            if (timed) HIP_OK(hipEventRecord(m->kev[2 * (k - 1)], stream));
+            hipLaunchKernelGGL(mfma_sweep_kernel, dim3(sweep_blocks), dim3(kMThreads), 0, stream, A, k);
+            if (timed) HIP_OK(hipEventRecord(m->kev[2 * (k - 1) + 1], stream));
+            hipLaunchKernelGGL(mfma_reduce_kernel, dim3((A.B + 31) / 32), dim3(256), 0, stream, A, k);
+            hipLaunchKernelGGL(mfma_finalize_kernel, dim3(1), dim3(1024), 0, stream, A, k);
+        }
+        HIP_OK(hipGetLastError());
+        if (k > maxs) break;
+        HIP_OK(hipMemcpyAsync(m->h_cnt, A.cnt + ((k - 1) & 1), 4, hipMemcpyDeviceToHost, stream));
+        HIP_OK(hipEventRecord(m->ev_cnt, stream));
+        HIP_OK(hipEventSynchronize(m->ev_cnt));
+        if (*m->h_cnt == 0) break;
+    }
+    hipLaunchKernelGGL(mfma_pack_kernel, dim3(init_blocks), dim3(256), 0, stream, A);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipEventRecord(m->ev1, stream));
+    return RAC_OK;
+}
+
+static int rc_of(int32_t v) {
+    if (v & 4) return set_error(RAC_ETIMEOUT, "matrix-core path: a state did not finish");
+    if (v & 1) return set_error(RAC_ENOTCONVERGED, "max_sweeps reached before the fixpoint");
+    return RAC_OK;
+}
+
+static void collect_stats(MfmaData &md, int32_t B, const std::vector<long long> &checks,
+                          const std::vector<int32_t> &iters, rac_stats *stats) {
+    MfmaImpl *m = impl(md);
+    memset(stats, 0, sizeof(*stats));
+    int32_t max_it = 0;
+    for (int32_t s = 0; s < B; ++s) {
+        stats->support_checks += checks[(size_t)s];
+        stats->sweeps += iters[(size_t)s];
+        max_it = std::max(max_it, iters[(size_t)s]);
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, m->ev0, m->ev1);
+    stats->device_ms = ms;
+    stats->path = RAC_PATH_MFMA;
+    stats->relation_bytes = md.arcs * 1024;
+    stats->algo_ops = 2ll * md.d * md.d * md.arcs * stats->sweeps;
+    if (m->profiled) {
+        // the step kernels that had work: steps 1..max iters
+        const int32_t kl = std::min(max_it, 64);
+        for (int32_t k = 1; k <= kl; ++k) {
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, m->kev[2 * (k - 1)], m->kev[2 * (k - 1) + 1]);
+            stats->kernel_ms += t;
+        }
+        stats->kernel_launches = kl;
+    }
+}
+
+int mfma_enforce_host(MfmaData &md, int32_t B, uint64_t *dom, int32_t *iters, int32_t *status,
+                      int32_t mode, int32_t max_sweeps, int32_t profile, hipStream_t stream,
+                      rac_stats *stats) {
+    int rc = ensure_capacity(md, B);
+    if (rc) return rc;
+    MfmaImpl *m = impl(md);
+    HIP_OK(hipMemcpyAsync(m->hin, dom, (size_t)B * md.n * 8, hipMemcpyHostToDevice, stream));
+    MArgs A = make_args(md, B, m->hin, m->hout, m->d_iters, m->d_status, mode, max_sweeps);
+    m->last_B = B;
+    rc = run(md, A, profile != 0, stream);
+    if (rc) return rc;
+    std::vector<int32_t> hi((size_t)B), hs((size_t)B);
+    std::vector<long long> hc((size_t)B);
+    int32_t hrc = 0;
+    HIP_OK(hipMemcpyAsync(dom, m->hout, (size_t)B * md.n * 8, hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipMemcpyAsync(hi.data(), m->d_iters, (size_t)B * 4, hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipMemcpyAsync(hs.data(), m->d_status, (size_t)B * 4, hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipMemcpyAsync(hc.data(), m->d_checks, (size_t)B * 8, hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipMemcpyAsync(&hrc, m->d_rc, 4, hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    if (iters) memcpy(iters, hi.data(), (size_t)B * 4);
+    if (status) memcpy(status, hs.data(), (size_t)B * 4);
+    collect_stats(md, B, hc, hi, stats);
+    return rc_of(hrc);
+}
+
+int mfma_enforce_device(MfmaData &md, int32_t B, const uint64_t *d_in, uint64_t *d_out,
+                        int32_t *d_iters, int32_t *d_status, int32_t mode, int32_t max_sweeps,
+                        int32_t profile, hipStream_t stream) {
+    int rc = ensure_capacity(md, B);
+    if (rc) return rc;
+    MfmaImpl *m = impl(md);
+    MArgs A = make_args(md, B, d_in, d_out, d_iters, d_status, mode, max_sweeps);
+    m->last_B = B;
+    return run(md, A, profile != 0, stream);
+}
+
+int mfma_sync_status(MfmaData &md, rac_stats *stats) {
+    MfmaImpl *m = impl(md);
+    if (!m) return RAC_OK;
+    const int32_t B = m->last_B;
+    HIP_OK(hipEventSynchronize(m->ev1));
+    std::vector<long long> hc((size_t)B);
+    std::vector<int32_t> hi((size_t)B);
+    int32_t hrc = 0;
+    // iteration counts of the device call live in the per-state table
+    std::vector<MState> hs((size_t)B);
+    HIP_OK(hipMemcpy(hs.data(), m->st, (size_t)B * sizeof(MState), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(&hrc, m->d_rc, 4, hipMemcpyDeviceToHost));
+    for (int32_t s = 0; s < B; ++s) {
+        hc[(size_t)s] = hs[(size_t)s].checks;
+        hi[(size_t)s] = hs[(size_t)s].iters;
+    }
+    collect_stats(md, B, hc, hi, stats);
+    return rc_of(hrc);
+}
 
 }  // namespace rac

@@ -75,7 +75,8 @@ static int check_options(const rac_options *o) {
     if (o->path < RAC_PATH_AUTO || o->path > RAC_PATH_MFMA)
         return set_error(RAC_EINVAL, "options.path out of range");
     if (o->item_bytes < 0) return set_error(RAC_EINVAL, "options.item_bytes must be >= 0");
-    for (int i = 0; i < 3; ++i)
+    if (o->profile != 0 && o->profile != 1) return set_error(RAC_EINVAL, "options.profile must be 0 or 1");
+    for (int i = 0; i < 2; ++i)
         if (o->reserved[i] != 0) return set_error(RAC_EINVAL, "options.reserved must be zero");
     return RAC_OK;
 }
@@ -184,7 +185,8 @@ struct Runner {
     int32_t *iters = nullptr, *status = nullptr, *rc = nullptr;
     long long *checks = nullptr;
     uint8_t *changed = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, evk0 = nullptr, evk1 = nullptr;
+    bool profiled = false;
     // graph of (init, sweep, finish)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -258,7 +260,9 @@ static void release_runner(Runner &r) {
     dfree(r.changed);
     if (r.ev0) (void)hipEventDestroy(r.ev0);
     if (r.ev1) (void)hipEventDestroy(r.ev1);
-    r.ev0 = r.ev1 = nullptr;
+    if (r.evk0) (void)hipEventDestroy(r.evk0);
+    if (r.evk1) (void)hipEventDestroy(r.evk1);
+    r.ev0 = r.ev1 = r.evk0 = r.evk1 = nullptr;
     r.cap_probs = 0;
     r.cap_vars = 0;
 }
@@ -287,6 +291,8 @@ static int ensure_runner(Runner &r, int32_t nprob, int64_t nvars) {
     RAC_TRY(dalloc(&r.changed, nvars));
     HIP_TRY(hipEventCreate(&r.ev0));
     HIP_TRY(hipEventCreate(&r.ev1));
+    HIP_TRY(hipEventCreate(&r.evk0));
+    HIP_TRY(hipEventCreate(&r.evk1));
     r.cap_probs = nprob;
     r.cap_vars = nvars;
     return RAC_OK;
@@ -654,7 +660,7 @@ static dim3 grid_init(int64_t nvars) {
 
 // Enqueues init + persistent sweep + finish on `stream`.
 static int launch_fixpoint(Runner &r, int device, hipStream_t stream, const Launch &L,
-                           int64_t total_items, bool use_graph) {
+                           int64_t total_items, bool use_graph, bool profile = false) {
     const size_t smem = stage_bytes(L.stage_vars);
     int64_t g = 0;
     RAC_TRY(sweep_slots(device, smem, &g));
@@ -666,10 +672,13 @@ static int launch_fixpoint(Runner &r, int device, hipStream_t stream, const Laun
     dim3 grids[3] = {grid_init(r.cap_vars), dim3((unsigned)g), grid_init(r.cap_vars)};
     const void *funcs[3] = {(const void *)init_kernel, (const void *)sweep_kernel,
                             (const void *)finish_kernel};
-    if (!use_graph) {
+    r.profiled = profile;
+    if (!use_graph || profile) {
         HIP_TRY(hipEventRecord(r.ev0, stream));
         hipLaunchKernelGGL(init_kernel, grids[0], dim3(256), 0, stream, L);
+        if (profile) HIP_TRY(hipEventRecord(r.evk0, stream));
         hipLaunchKernelGGL(sweep_kernel, grids[1], dim3(kWave), smem, stream, L);
+        if (profile) HIP_TRY(hipEventRecord(r.evk1, stream));
         hipLaunchKernelGGL(finish_kernel, grids[2], dim3(256), 0, stream, L);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(r.ev1, stream));
@@ -821,7 +830,7 @@ static int run_states(rac_net *net, int32_t B, int32_t path, const uint8_t *d_ch
     L.changed0 = d_changed;
     L.checks1 = checks1;
     RAC_TRY(launch_fixpoint(r, net->device, net->stream, L, (int64_t)pd.nitems * B,
-                            net->opt.use_graph != 0));
+                            net->opt.use_graph != 0, net->opt.profile != 0));
     (void)sync;
     return RAC_OK;
 }
@@ -843,6 +852,12 @@ static int collect_bits(rac_net *net, int32_t B, int32_t path, uint64_t *dom, in
     (void)hipEventElapsedTime(&ms, r.ev0, r.ev1);
     fill_stats_bits(net->last, hc, hi, path, pd, ms);
     net->last.relation_bytes = (int64_t)pd.rows_bytes;
+    if (r.profiled) {
+        float kms = 0.f;
+        (void)hipEventElapsedTime(&kms, r.evk0, r.evk1);
+        net->last.kernel_ms = kms;
+        net->last.kernel_launches = 1;
+    }
     if (iters) memcpy(iters, hi.data(), (size_t)B * 4);
     if (status) memcpy(status, hs.data(), (size_t)B * 4);
     return rc_from_device(hrc);
@@ -893,7 +908,7 @@ extern "C" int rac_enforce_batch(rac_net *net, int32_t B, uint64_t *dom, int32_t
         RAC_TRY(mfma_ensure(net->mfma, net->n, net->d, net->arcs, net->row_ptr, net->nbr,
                             net->deg, net->rel, net->arc_src, net->h_row_ptr, net->stream));
         RAC_TRY(mfma_enforce_host(net->mfma, B, dom, iters, status, net->opt.mode,
-                                  net->opt.max_sweeps, net->stream, &net->last));
+                                  net->opt.max_sweeps, net->opt.profile, net->stream, &net->last));
         return RAC_OK;
     }
     RAC_TRY(ensure_path(net, path, call_target(net, B)));
@@ -921,7 +936,7 @@ extern "C" int rac_enforce_batch_device(rac_net *net, int32_t B, const uint64_t 
         RAC_TRY(mfma_ensure(net->mfma, net->n, net->d, net->arcs, net->row_ptr, net->nbr,
                             net->deg, net->rel, net->arc_src, net->h_row_ptr, net->stream));
         RAC_TRY(mfma_enforce_device(net->mfma, B, d_dom_in, d_dom_out, d_iters, d_status,
-                                    net->opt.mode, net->opt.max_sweeps, s));
+                                    net->opt.mode, net->opt.max_sweeps, net->opt.profile, s));
         net->pending = true;
         net->last.path = RAC_PATH_MFMA;
         return RAC_OK;
@@ -937,7 +952,8 @@ extern "C" int rac_enforce_batch_device(rac_net *net, int32_t B, const uint64_t 
     L.dout = d_dom_out;
     L.iters_out = d_iters;
     L.status_out = d_status;
-    RAC_TRY(launch_fixpoint(r, net->device, s, L, (int64_t)pd.nitems * B, net->opt.use_graph != 0));
+    RAC_TRY(launch_fixpoint(r, net->device, s, L, (int64_t)pd.nitems * B, net->opt.use_graph != 0,
+                            net->opt.profile != 0));
     net->pending = true;
     net->last.path = path;
     net->last.item_bytes = pd.item_bytes;
@@ -957,6 +973,12 @@ extern "C" int rac_sync_status(rac_net *net) {
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, net->run.ev0, net->run.ev1);
     net->last.device_ms = ms;
+    if (net->run.profiled) {
+        float kms = 0.f;
+        (void)hipEventElapsedTime(&kms, net->run.evk0, net->run.evk1);
+        net->last.kernel_ms = kms;
+        net->last.kernel_launches = 1;
+    }
     return rc_from_device(hrc);
 }
 
@@ -1087,7 +1109,8 @@ extern "C" int rac_group_enforce(rac_group *g, uint64_t *const *dom, int32_t *it
     }
     HIP_TRY(hipMemcpyAsync(r.din, h.data(), h.size() * 8, hipMemcpyHostToDevice, g->stream));
     Launch L = group_launch(g, r.din, r.dout, r.iters, r.status);
-    RAC_TRY(launch_fixpoint(r, g->device, g->stream, L, g->total_items, g->opt.use_graph != 0));
+    RAC_TRY(launch_fixpoint(r, g->device, g->stream, L, g->total_items, g->opt.use_graph != 0,
+                            g->opt.profile != 0));
     std::vector<int32_t> hi((size_t)g->k), hs((size_t)g->k);
     std::vector<long long> hc((size_t)g->k);
     int32_t hrc = 0;
@@ -1111,6 +1134,12 @@ extern "C" int rac_group_enforce(rac_group *g, uint64_t *const *dom, int32_t *it
     g->last.device_ms = ms;
     g->last.path = RAC_PATH_BITS;
     g->last.relation_bytes = g->rel_bytes;
+    if (r.profiled) {
+        float kms = 0.f;
+        (void)hipEventElapsedTime(&kms, r.evk0, r.evk1);
+        g->last.kernel_ms = kms;
+        g->last.kernel_launches = 1;
+    }
     return rc_from_device(hrc);
 }
 

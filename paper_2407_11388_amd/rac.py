@@ -53,14 +53,16 @@ class RacError(RuntimeError):
 class rac_options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("path", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("item_bytes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("item_bytes", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class rac_stats(ctypes.Structure):
     _fields_ = [("support_checks", ctypes.c_int64), ("sweeps", ctypes.c_int64),
                 ("relation_bytes", ctypes.c_int64), ("device_ms", ctypes.c_double),
-                ("path", ctypes.c_int32), ("item_bytes", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int64),
+                ("algo_ops", ctypes.c_int64), ("path", ctypes.c_int32),
+                ("item_bytes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 def _load():
@@ -117,11 +119,12 @@ def _ptr(a) -> Optional[int]:
 
 
 def options(mode: int = RAC_RUN_TO_FIXPOINT, max_sweeps: int = 0, path: int = PATH_AUTO,
-            use_graph: bool = True, item_bytes: int = 0) -> rac_options:
+            use_graph: bool = True, item_bytes: int = 0, profile: bool = False) -> rac_options:
     o = rac_options()
     lib.rac_default_options(ctypes.byref(o))
     o.mode, o.max_sweeps, o.path = mode, max_sweeps, path
     o.use_graph, o.item_bytes = 1 if use_graph else 0, item_bytes
+    o.profile = 1 if profile else 0
     return o
 
 

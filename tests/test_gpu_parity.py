@@ -208,3 +208,54 @@ def test_dense_create_matches():
     a = rac.Net.from_dense(n, d, R, inst.edges).enforce(dom)
     b = rac.Net.from_bits(n, d, inst.edges, inst.rel).enforce(dom)
     assert np.array_equal(a[0], b[0]) and a[1] == b[1]
+
+
+MFMA_CASES = [(40, 32, 37, 0.6, 0.3), (45, 10, 130, 0.8, 0.5), (13, 4, 300, 1.0, 0.55),
+              (70, 17, 129, 0.4, 0.7), (9, 1, 64, 0.9, 0.0), (100, 32, 257, 0.8, 0.25)]
+
+
+@pytest.mark.parametrize("n,d,B,p1,p2", MFMA_CASES)
+def test_batch_states_mfma(n, d, B, p1, p2):
+    inst = gen.model_b(40 + n + d, n, d, p1, p2)
+    doms, _ = gen.partial_assign_states(41 + B, n, d, B, min(n, 12))
+    rel = inst.rel_u8()
+    for mode in (0, 1):
+        say(f"[gpu] batch mfma n={n} d={d} B={B} mode={mode}")
+        net = rac.Net.from_u8(n, d, inst.edges, rel, path=rac.PATH_MFMA, mode=mode)
+        for rep in range(2):
+            got, iters, status = net.enforce_batch(doms)
+            st = net.stats()
+            assert st.path == rac.PATH_MFMA
+            total_checks = 0
+            for s in range(B):
+                exp, e_it, e_st, e_ch, _ = oracle_expect(n, d, inst.edges, rel, doms[s], mode)
+                assert np.array_equal(got[s], exp), f"state {s} (mode {mode})"
+                assert iters[s] == e_it, f"state {s}: iters {iters[s]} != {e_it}"
+                assert status[s] == e_st
+                total_checks += e_ch
+            assert st.support_checks == total_checks
+        net.close()
+
+
+def test_mfma_rejects_wide_domains():
+    inst = gen.model_b(3, 10, 40, 0.5, 0.3)
+    net = rac.Net.from_instance(inst, path=rac.PATH_MFMA)
+    doms = np.tile(gen.full_domains(10, 40), (4, 1))
+    with pytest.raises(rac.RacError) as ei:
+        net.enforce_batch(doms)
+    assert ei.value.code == rac.RAC_EUNSUPPORTED
+    net.close()
+
+
+def test_mfma_step_cap():
+    L, d = 9, 12
+    edges = np.array([[i, i + 1] for i in range(L)], np.int32)
+    rel = np.zeros((L, d, d), np.uint8)
+    for a in range(d):
+        rel[:, a, a + 1:] = 1
+    doms = np.tile(np.full(L + 1, (1 << d) - 1, np.uint64), (3, 1))
+    net = rac.Net.from_u8(L + 1, d, edges, rel, path=rac.PATH_MFMA, max_sweeps=4)
+    with pytest.raises(rac.RacError) as ei:
+        net.enforce_batch(doms)
+    assert ei.value.code == rac.RAC_ENOTCONVERGED
+    net.close()
