@@ -45,6 +45,11 @@ def parse():
                     help="approximate budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="skip the 256-instance uneven batch in the secondary results")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a device-to-device copy of BYTES (to calibrate the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
 
 
@@ -117,6 +122,14 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_bytes=args.copy_calibration)), flush=True)
+        return
     out = dict(metric="support checks/s + AC fixpoints/s, batched int8-MFMA vs plain, bit-exact",
                unit="support checks/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                higher_is_better=True, scaling="weak", vs_baseline=None,
@@ -237,6 +250,27 @@ def main():
                 kernel_ms=best, relation_GBs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
                 support_checks_per_s=stt.support_checks / (best * 1e-3), steps=int(stt.sweeps))
             net.close()
+        if not args.no_uneven:
+            wu = workloads.uneven_multi()
+            nets = [rac.Net.from_instance(i, profile=True) for i in wu.instances]
+            grp = rac.Group(nets, profile=True)
+            grp.enforce(wu.domains)
+            best, best_dev = 1e9, 1e9
+            for _ in range(5):
+                _, it_u, st_u = grp.enforce(wu.domains)
+                stg = grp.stats()
+                best = min(best, stg.kernel_ms)
+                best_dev = min(best_dev, stg.device_ms)
+            gbs = stg.relation_bytes / (best * 1e-3) / 1e9
+            sec["uneven-multi 256 instances (one persistent launch)"] = dict(
+                kernel_ms=best, device_ms=best_dev, fixpoints_per_s=len(nets) / (best_dev * 1e-3),
+                relation_bytes=int(stg.relation_bytes), relation_GBs_per_first_step=gbs,
+                support_checks_per_s=stg.support_checks / (best_dev * 1e-3),
+                steps_max=int(it_u.max()), steps_mean=float(it_u.mean()),
+                wiped_instances=int(st_u.sum()))
+            grp.close()
+            for nt in nets:
+                nt.close()
         out["secondary"] = sec
 
     print(json.dumps(out), flush=True)

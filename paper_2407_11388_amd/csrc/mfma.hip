@@ -59,10 +59,14 @@ struct MArgs {
     const int32_t *nbr_s;             // [arcs]
     const int32_t *deg;               // [n]
     const int8_t *r8;                 // [arcs][32][32]
+    const int32_t *bstart;            // [n][nblk+1] first arc of x with neighbour >= 8*b
+    const uint8_t *bmask;             // [n][nblk] bit l: x is constrained with y = 8*b + l
+    int32_t nblk;                     // ceil(n / 8)
     int8_t *dom8[2];                  // [capB][N32]
     uint32_t *chg, *wipe;             // [n][words]
     int32_t words;                    // capB / 32
     int32_t *act[2];                  // active state lists (by step parity)
+    int32_t *prev_slot[2];            // slot each listed state had in the previous step
     int32_t *cnt;                     // [2] active counts
     MState *st;                       // [capB]
     int32_t mode, max_sweeps, B, xcd_map;
@@ -138,8 +142,9 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
 
     const int x = xt * kMX + wave;
     const bool xv = x < A.n;
-    int32_t jb = xv ? A.row_ptr[x] : 0;
-    const int32_t jend = xv ? A.row_ptr[x + 1] : 0;
+    const int nblk = A.nblk;
+    const int32_t *bst = A.bstart + (int64_t)(xv ? x : 0) * (nblk + 1);
+    const uint8_t *bmk = A.bmask + (int64_t)(xv ? x : 0) * nblk;
     const int8_t *dcur = A.dom8[(k - 1) & 1];
     const int half = lane >> 5, col = lane & 31;
 
@@ -167,17 +172,15 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
             s_b[buf][yl][rem >> 1][rem & 1] = r[i];
         }
     };
-    // relation blocks of this wave's arcs with neighbours in [yb, yb + kMY)
-    auto fetch_a = [&](int32_t j0, int32_t cnt, v4i (&a)[kMY]) {
+    // relation blocks of this wave's arcs in one neighbour block, indexed by
+    // the neighbour's position in the block (arcs are sorted by neighbour)
+    auto fetch_a = [&](int32_t j0, uint32_t msk, v4i (&a)[kMY]) {
 #pragma unroll
-        for (int e = 0; e < kMY; ++e)
-            if (e < cnt)
-                a[e] = *reinterpret_cast<const v4i *>(A.r8 + (int64_t)(j0 + e) * 1024 + col * 32 + half * 16);
-    };
-    auto arcs_below = [&](int32_t j0, int ylim) {
-        int32_t j = j0;
-        while (j < jend && A.nbr_s[j] < ylim) ++j;
-        return j;
+        for (int l = 0; l < kMY; ++l)
+            if ((msk >> l) & 1u) {
+                const int32_t j = j0 + __builtin_popcount(msk & ((1u << l) - 1u));
+                a[l] = *reinterpret_cast<const v4i *>(A.r8 + (int64_t)j * 1024 + col * 32 + half * 16);
+            }
     };
 
     v16i rm[kMSub];
@@ -188,43 +191,66 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
 
     v4i breg[kUnitsPerThread];
     v4i acur[kMY], anext[kMY];
-    int32_t je = arcs_below(jb, kMY);
+    // neighbour tables are read two blocks ahead, relation blocks one ahead
+    uint32_t mcur = xv ? bmk[0] : 0u;
+    int32_t jnext = xv && nblk > 1 ? bst[1] : 0;
+    uint32_t mnext = xv && nblk > 1 ? bmk[1] : 0u;
     fetch_b(0, breg);
     store_b(0, breg);
-    fetch_a(jb, je - jb, acur);
+    fetch_a(xv ? bst[0] : 0, mcur, acur);
     __syncthreads();
-    const int nblk = (A.n + kMY - 1) / kMY;
     for (int blk = 0; blk < nblk; ++blk) {
         const int buf = blk & 1;
         const int yb = blk * kMY;
-        // issue the next block's loads before the products of this one
-        const int32_t je2 = arcs_below(je, yb + 2 * kMY);
+        uint32_t mnn = 0u;
+        int32_t jnn = 0;
         if (blk + 1 < nblk) {
             fetch_b(yb + kMY, breg);
-            fetch_a(je, je2 - je, anext);
+            fetch_a(jnext, mnext, anext);
+            if (xv && blk + 2 < nblk) {
+                jnn = bst[blk + 2];
+                mnn = bmk[blk + 2];
+            }
         }
-        const int32_t ncur = je - jb;
+        // products of this block: a fresh accumulator per neighbour, folded
+        // into the running minimum two neighbours at a time
 #pragma unroll
-        for (int e = 0; e < kMY; ++e) {
-            if (e < ncur) {
-                const int yl = A.nbr_s[jb + e] - yb;
+        for (int l = 0; l < kMY; l += 2) {
+            const bool p0 = (mcur >> l) & 1u, p1 = (mcur >> (l + 1)) & 1u;
+            if (p0 || p1) {
 #pragma unroll
                 for (int t = 0; t < kMSub; ++t) {
-                    const v4i bop = s_b[buf][yl][t * 32 + col][half];
                     const v16i zero = {0};
-                    const v16i c = __builtin_amdgcn_mfma_i32_32x32x32_i8(acur[e], bop, zero, 0, 0, 0);
+                    v16i c0, c1;
+                    if (p0) {
+                        const v4i b0 = s_b[buf][l][t * 32 + col][half];
+                        c0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(acur[l], b0, zero, 0, 0, 0);
+                    }
+                    if (p1) {
+                        const v4i b1 = s_b[buf][l + 1][t * 32 + col][half];
+                        c1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(acur[l + 1], b1, zero, 0, 0, 0);
+                    }
+                    if (p0 && p1) {
 #pragma unroll
-                    for (int v = 0; v < 16; ++v) rm[t][v] = min(rm[t][v], c[v]);
+                        for (int v = 0; v < 16; ++v) rm[t][v] = min(rm[t][v], min(c0[v], c1[v]));
+                    } else if (p0) {
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) rm[t][v] = min(rm[t][v], c0[v]);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) rm[t][v] = min(rm[t][v], c1[v]);
+                    }
                 }
             }
         }
         if (blk + 1 < nblk) {
             store_b(buf ^ 1, breg);
 #pragma unroll
-            for (int e = 0; e < kMY; ++e) acur[e] = anext[e];
+            for (int l = 0; l < kMY; ++l) acur[l] = anext[l];
+            mcur = mnext;
+            mnext = mnn;
+            jnext = jnn;
         }
-        jb = je;
-        je = je2;
         __syncthreads();
     }
 
@@ -350,7 +376,10 @@ __global__ __launch_bounds__(1024) void mfma_finalize_kernel(MArgs A, int k) {
         __syncthreads();
         int off = s_base;
         for (int w = 0; w < wave; ++w) off += s_wave_tot[w];
-        if (keep) nxt[off + pre] = s;
+        if (keep) {
+            nxt[off + pre] = s;
+            A.prev_slot[k & 1][off + pre] = slot;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             int tot = 0;
@@ -360,6 +389,71 @@ __global__ __launch_bounds__(1024) void mfma_finalize_kernel(MArgs A, int k) {
         __syncthreads();
     }
     if (threadIdx.x == 0) A.cnt[k & 1] = s_base;
+}
+
+// Hand the P states still active after step k to the bit-row path: their
+// domains D^(k) as masks, the variables step k changed (the @changed set the
+// next step starts from, Proposition 2), and their state ids.
+__global__ void mfma_handoff_kernel(MArgs A, int k, uint64_t *bits, uint8_t *changed,
+                                    int32_t *ids) {
+    const int P = A.cnt[k & 1];
+    const int64_t total = (int64_t)P * A.n;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = tid; i < total; i += nth) {
+        const int64_t q = i / A.n;
+        const int32_t x = (int32_t)(i - q * A.n);
+        const int32_t s = A.act[k & 1][q];
+        const int32_t slot = A.prev_slot[k & 1][q];
+        const uint32_t *src =
+            reinterpret_cast<const uint32_t *>(A.dom8[k & 1] + (int64_t)s * A.N32 + (int64_t)x * 32);
+        uint64_t dm = 0;
+        for (int w = 0; w < 8; ++w) {
+            const uint32_t v = src[w];
+            for (int t = 0; t < 4; ++t)
+                if ((v >> (8 * t)) & 0xFFu) dm |= 1ull << (4 * w + t);
+        }
+        bits[i] = dm;
+        changed[i] = (uint8_t)((A.chg[(int64_t)x * A.words + (slot >> 5)] >> (slot & 31)) & 1u);
+        if (x == 0) ids[q] = s;
+    }
+}
+
+// Results of the bit-row path for the handed-off states: steps continue the
+// count of the matrix-core steps, and the final domains go back to the byte
+// buffer that the pack kernel reads.
+__global__ void mfma_merge_kernel(MArgs A, int k, const uint64_t *bits, const int32_t *ids,
+                                  const int32_t *it, const int32_t *stt, const long long *chk,
+                                  const int32_t *brc) {
+    const int P = A.cnt[k & 1];
+    const int64_t total = (int64_t)P * A.n;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = tid; i < total; i += nth) {
+        const int64_t q = i / A.n;
+        const int32_t x = (int32_t)(i - q * A.n);
+        const int32_t s = ids[q];
+        const int32_t kf = k + it[q];
+        const uint64_t dm = bits[i];
+        uint32_t w[8];
+        for (int qq = 0; qq < 8; ++qq) {
+            uint32_t v = 0;
+            for (int t = 0; t < 4; ++t)
+                if ((dm >> (4 * qq + t)) & 1ull) v |= 1u << (8 * t);
+            w[qq] = v;
+        }
+        uint4 *dst = reinterpret_cast<uint4 *>(A.dom8[kf & 1] + (int64_t)s * A.N32 + (int64_t)x * 32);
+        dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+        dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+        if (x == 0) {
+            MState &m = A.st[s];
+            m.iters = kf;
+            m.status = stt[q];
+            m.checks += chk[q];
+            m.rc = (*brc & 1) ? RAC_ENOTCONVERGED : 0;
+            m.done = (*brc & 2) ? 0 : 1;
+        }
+    }
 }
 
 __global__ void mfma_pack_kernel(MArgs A) {
@@ -436,10 +530,15 @@ struct MfmaImpl {
     int32_t *row_ptr = nullptr, *nbr_s = nullptr;
     const int32_t *deg = nullptr;
     int8_t *r8 = nullptr;
+    int32_t *bstart = nullptr;
+    uint8_t *bmask = nullptr;
+    int32_t nblk = 0;
     int32_t capB = 0, words = 0;
     int8_t *dom8[2] = {nullptr, nullptr};
     uint32_t *chg = nullptr, *wipe = nullptr;
     int32_t *act[2] = {nullptr, nullptr};
+    int32_t *prev_slot[2] = {nullptr, nullptr};
+    int32_t *ids = nullptr;
     int32_t *cnt = nullptr;
     MState *st = nullptr;
     uint64_t *hin = nullptr, *hout = nullptr;   // device staging for host calls
@@ -450,6 +549,8 @@ struct MfmaImpl {
     hipEvent_t kev[2 * 64] = {};                 // step kernel timing (profiling)
     bool profiled = false;
     int32_t last_B = 0;
+    int32_t last_k = 0;
+    MArgs args{};
     int32_t *last_rc_ptr = nullptr;
 };
 
@@ -466,12 +567,17 @@ void mfma_release(MfmaData &md) {
     mfree(m->row_ptr);
     mfree(m->nbr_s);
     mfree(m->r8);
+    mfree(m->bstart);
+    mfree(m->bmask);
     mfree(m->dom8[0]);
     mfree(m->dom8[1]);
     mfree(m->chg);
     mfree(m->wipe);
     mfree(m->act[0]);
     mfree(m->act[1]);
+    mfree(m->prev_slot[0]);
+    mfree(m->prev_slot[1]);
+    mfree(m->ids);
     mfree(m->cnt);
     mfree(m->st);
     mfree(m->hin);
@@ -527,6 +633,27 @@ int mfma_ensure(MfmaData &md, int32_t n, int32_t d, int64_t arcs, const int32_t 
             src_s[(size_t)j] = h_src[(size_t)perm[(size_t)(j - j0)]];
         }
     }
+    // per (variable, block of 8 neighbours): first arc and neighbour mask
+    const int32_t nblk = (n + kMY - 1) / kMY;
+    std::vector<int32_t> bstart((size_t)n * (nblk + 1));
+    std::vector<uint8_t> bmask((size_t)n * nblk, 0);
+    for (int32_t x = 0; x < n; ++x) {
+        int32_t j = h_row_ptr[x];
+        const int32_t j1 = h_row_ptr[x + 1];
+        for (int32_t b = 0; b <= nblk; ++b) {
+            while (j < j1 && nbr_s[(size_t)j] < b * kMY) ++j;
+            bstart[(size_t)x * (nblk + 1) + b] = j;
+        }
+        for (int32_t jj = h_row_ptr[x]; jj < j1; ++jj) {
+            const int32_t y = nbr_s[(size_t)jj];
+            bmask[(size_t)x * nblk + y / kMY] |= (uint8_t)(1u << (y % kMY));
+        }
+    }
+    m->nblk = nblk;
+    HIP_OK(hipMalloc(&m->bstart, bstart.size() * 4));
+    HIP_OK(hipMalloc(&m->bmask, std::max<size_t>(1, bmask.size())));
+    HIP_OK(hipMemcpy(m->bstart, bstart.data(), bstart.size() * 4, hipMemcpyHostToDevice));
+    if (!bmask.empty()) HIP_OK(hipMemcpy(m->bmask, bmask.data(), bmask.size(), hipMemcpyHostToDevice));
     int32_t *d_src = nullptr;
     HIP_OK(hipMalloc(&m->row_ptr, ((size_t)n + 1) * 4));
     HIP_OK(hipMalloc(&m->nbr_s, std::max<size_t>(1, (size_t)arcs) * 4));
@@ -562,6 +689,9 @@ static int ensure_capacity(MfmaData &md, int32_t B) {
     mfree(m->wipe);
     mfree(m->act[0]);
     mfree(m->act[1]);
+    mfree(m->prev_slot[0]);
+    mfree(m->prev_slot[1]);
+    mfree(m->ids);
     mfree(m->cnt);
     mfree(m->st);
     mfree(m->hin);
@@ -578,6 +708,9 @@ static int ensure_capacity(MfmaData &md, int32_t B) {
     HIP_OK(hipMalloc(&m->wipe, (size_t)md.n * words * 4));
     HIP_OK(hipMalloc(&m->act[0], (size_t)capB * 4));
     HIP_OK(hipMalloc(&m->act[1], (size_t)capB * 4));
+    HIP_OK(hipMalloc(&m->prev_slot[0], (size_t)capB * 4));
+    HIP_OK(hipMalloc(&m->prev_slot[1], (size_t)capB * 4));
+    HIP_OK(hipMalloc(&m->ids, (size_t)capB * 4));
     HIP_OK(hipMalloc(&m->cnt, 2 * 4));
     HIP_OK(hipMalloc(&m->st, (size_t)capB * sizeof(MState)));
     HIP_OK(hipMalloc(&m->hin, (size_t)capB * md.n * 8));
@@ -603,6 +736,9 @@ static MArgs make_args(MfmaData &md, int32_t B, const uint64_t *din, uint64_t *d
     A.nbr_s = m->nbr_s;
     A.deg = m->deg;
     A.r8 = m->r8;
+    A.bstart = m->bstart;
+    A.bmask = m->bmask;
+    A.nblk = m->nblk;
     A.dom8[0] = m->dom8[0];
     A.dom8[1] = m->dom8[1];
     A.chg = m->chg;
@@ -610,6 +746,8 @@ static MArgs make_args(MfmaData &md, int32_t B, const uint64_t *din, uint64_t *d
     A.words = m->words;   // row stride of the mask matrices (capacity / 32)
     A.act[0] = m->act[0];
     A.act[1] = m->act[1];
+    A.prev_slot[0] = m->prev_slot[0];
+    A.prev_slot[1] = m->prev_slot[1];
     A.cnt = m->cnt;
     A.st = m->st;
     A.mode = mode;
@@ -621,16 +759,20 @@ static MArgs make_args(MfmaData &md, int32_t B, const uint64_t *din, uint64_t *d
     A.dout = dout;
     A.iters_out = it;
     A.status_out = stt;
-    A.rc_out = m->d_rc;
+    A.rc_out = m->d_rc;   // the pack kernel also ORs the per-state codes into it
     A.checks_out = m->d_checks;
     return A;
 }
 
-// Enqueues the whole enforcement; waits on the device only between groups of
-// kMaxChunk steps (to learn whether another group is needed).
-static int run(MfmaData &md, const MArgs &A, bool profile, hipStream_t stream) {
+// Enqueues init and matrix-core steps. After step 2 and every later step the
+// host reads the active-state count (one small device-to-host copy); it stops
+// when no state is active, or hands the rest over when at most `handoff`
+// states remain (0: never), or at the step cap.
+static int run_steps(MfmaData &md, const MArgs &A, bool profile, int32_t handoff,
+                     hipStream_t stream, int32_t *k_out, int32_t *p_out) {
     MfmaImpl *m = impl(md);
     m->profiled = profile;
+    m->args = A;
     const int ntiles_s = (A.words * 32 + kMS - 1) / kMS;
     const int ntiles_x = (A.n + kMX - 1) / kMX;
     const int sweep_blocks = ((ntiles_x + 7) / 8) * 8 * ntiles_s;
@@ -638,10 +780,12 @@ static int run(MfmaData &md, const MArgs &A, bool profile, hipStream_t stream) {
     const int32_t maxs = A.max_sweeps > 0 ? A.max_sweeps : A.n * A.d + 1;
     HIP_OK(hipEventRecord(m->ev0, stream));
     hipLaunchKernelGGL(mfma_init_kernel, dim3(init_blocks), dim3(256), 0, stream, A);
-    int k = 1;
-    for (;;) {
-        const int kend = std::min<int>(k + kMaxChunk - 1, maxs);
-        for (; k <= kend; ++k) {
+    int k = 0;
+    int32_t left = A.B;
+    while (k < maxs) {
+        const int steps = k == 0 ? 2 : 1;
+        for (int i = 0; i < steps && k < maxs; ++i) {
+            ++k;
             const bool timed = profile && k <= 64;
             if (timed) HIP_OK(hipEventRecord(m->kev[2 * (k - 1)], stream));
             hipLaunchKernelGGL(mfma_sweep_kernel, dim3(sweep_blocks), dim3(kMThreads), 0, stream, A, k);
@@ -650,13 +794,60 @@ static int run(MfmaData &md, const MArgs &A, bool profile, hipStream_t stream) {
             hipLaunchKernelGGL(mfma_finalize_kernel, dim3(1), dim3(1024), 0, stream, A, k);
         }
         HIP_OK(hipGetLastError());
-        if (k > maxs) break;
-        HIP_OK(hipMemcpyAsync(m->h_cnt, A.cnt + ((k - 1) & 1), 4, hipMemcpyDeviceToHost, stream));
+        HIP_OK(hipMemcpyAsync(m->h_cnt, A.cnt + (k & 1), 4, hipMemcpyDeviceToHost, stream));
         HIP_OK(hipEventRecord(m->ev_cnt, stream));
         HIP_OK(hipEventSynchronize(m->ev_cnt));
-        if (*m->h_cnt == 0) break;
+        left = *m->h_cnt;
+        if (left == 0 || left <= handoff) break;
     }
-    hipLaunchKernelGGL(mfma_pack_kernel, dim3(init_blocks), dim3(256), 0, stream, A);
+    m->last_k = k;
+    *k_out = k;
+    *p_out = k < maxs ? left : 0;   // at the cap every state has stopped
+    return RAC_OK;
+}
+
+int mfma_start(MfmaData &md, int32_t B, const uint64_t *d_in, int32_t mode, int32_t max_sweeps,
+               int32_t profile, int32_t handoff, hipStream_t stream, int32_t *k_out,
+               int32_t *p_out) {
+    int rc = ensure_capacity(md, B);
+    if (rc) return rc;
+    MfmaImpl *m = impl(md);
+    MArgs A = make_args(md, B, d_in, nullptr, nullptr, nullptr, mode, max_sweeps);
+    m->last_B = B;
+    return run_steps(md, A, profile != 0, handoff, stream, k_out, p_out);
+}
+
+int mfma_handoff(MfmaData &md, int32_t k, uint64_t *d_bits, uint8_t *d_changed, hipStream_t stream) {
+    MfmaImpl *m = impl(md);
+    const MArgs &A = m->args;
+    const int blocks = (int)std::min<int64_t>(4096, ((int64_t)A.B * A.n + 255) / 256);
+    hipLaunchKernelGGL(mfma_handoff_kernel, dim3(blocks), dim3(256), 0, stream, A, k, d_bits,
+                       d_changed, m->ids);
+    HIP_OK(hipGetLastError());
+    return RAC_OK;
+}
+
+int mfma_merge(MfmaData &md, int32_t k, const uint64_t *d_bits, const int32_t *d_it,
+               const int32_t *d_st, const long long *d_chk, const int32_t *d_rc,
+               hipStream_t stream) {
+    MfmaImpl *m = impl(md);
+    const MArgs &A = m->args;
+    const int blocks = (int)std::min<int64_t>(4096, ((int64_t)A.B * A.n + 255) / 256);
+    hipLaunchKernelGGL(mfma_merge_kernel, dim3(blocks), dim3(256), 0, stream, A, k, d_bits, m->ids,
+                       d_it, d_st, d_chk, d_rc);
+    HIP_OK(hipGetLastError());
+    return RAC_OK;
+}
+
+int mfma_finish(MfmaData &md, uint64_t *d_out, int32_t *d_iters, int32_t *d_status,
+                hipStream_t stream) {
+    MfmaImpl *m = impl(md);
+    MArgs A = m->args;
+    A.dout = d_out;
+    A.iters_out = d_iters;
+    A.status_out = d_status;
+    const int blocks = (int)std::min<int64_t>(4096, ((int64_t)A.B * A.n + 255) / 256);
+    hipLaunchKernelGGL(mfma_pack_kernel, dim3(blocks), dim3(256), 0, stream, A);
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(m->ev1, stream));
     return RAC_OK;
@@ -683,10 +874,13 @@ static void collect_stats(MfmaData &md, int32_t B, const std::vector<long long> 
     stats->device_ms = ms;
     stats->path = RAC_PATH_MFMA;
     stats->relation_bytes = md.arcs * 1024;
-    stats->algo_ops = 2ll * md.d * md.d * md.arcs * stats->sweeps;
+    // matrix-core steps performed: state s took part in steps 1..min(iters, last_k)
+    long long mfma_state_steps = 0;
+    for (int32_t s = 0; s < B; ++s) mfma_state_steps += std::min(iters[(size_t)s], m->last_k);
+    stats->algo_ops = 2ll * md.d * md.d * md.arcs * mfma_state_steps;
     if (m->profiled) {
-        // the step kernels that had work: steps 1..max iters
-        const int32_t kl = std::min(max_it, 64);
+        // the step kernels that had work: steps 1..min(max iters, last step)
+        const int32_t kl = std::min(std::min(max_it, m->last_k), 64);
         for (int32_t k = 1; k <= kl; ++k) {
             float t = 0.f;
             (void)hipEventElapsedTime(&t, m->kev[2 * (k - 1)], m->kev[2 * (k - 1) + 1]);
@@ -696,55 +890,16 @@ static void collect_stats(MfmaData &md, int32_t B, const std::vector<long long> 
     }
 }
 
-int mfma_enforce_host(MfmaData &md, int32_t B, uint64_t *dom, int32_t *iters, int32_t *status,
-                      int32_t mode, int32_t max_sweeps, int32_t profile, hipStream_t stream,
-                      rac_stats *stats) {
-    int rc = ensure_capacity(md, B);
-    if (rc) return rc;
+int mfma_collect(MfmaData &md, rac_stats *stats) {
     MfmaImpl *m = impl(md);
-    HIP_OK(hipMemcpyAsync(m->hin, dom, (size_t)B * md.n * 8, hipMemcpyHostToDevice, stream));
-    MArgs A = make_args(md, B, m->hin, m->hout, m->d_iters, m->d_status, mode, max_sweeps);
-    m->last_B = B;
-    rc = run(md, A, profile != 0, stream);
-    if (rc) return rc;
-    std::vector<int32_t> hi((size_t)B), hs((size_t)B);
-    std::vector<long long> hc((size_t)B);
-    int32_t hrc = 0;
-    HIP_OK(hipMemcpyAsync(dom, m->hout, (size_t)B * md.n * 8, hipMemcpyDeviceToHost, stream));
-    HIP_OK(hipMemcpyAsync(hi.data(), m->d_iters, (size_t)B * 4, hipMemcpyDeviceToHost, stream));
-    HIP_OK(hipMemcpyAsync(hs.data(), m->d_status, (size_t)B * 4, hipMemcpyDeviceToHost, stream));
-    HIP_OK(hipMemcpyAsync(hc.data(), m->d_checks, (size_t)B * 8, hipMemcpyDeviceToHost, stream));
-    HIP_OK(hipMemcpyAsync(&hrc, m->d_rc, 4, hipMemcpyDeviceToHost, stream));
-    HIP_OK(hipStreamSynchronize(stream));
-    if (iters) memcpy(iters, hi.data(), (size_t)B * 4);
-    if (status) memcpy(status, hs.data(), (size_t)B * 4);
-    collect_stats(md, B, hc, hi, stats);
-    return rc_of(hrc);
-}
-
-int mfma_enforce_device(MfmaData &md, int32_t B, const uint64_t *d_in, uint64_t *d_out,
-                        int32_t *d_iters, int32_t *d_status, int32_t mode, int32_t max_sweeps,
-                        int32_t profile, hipStream_t stream) {
-    int rc = ensure_capacity(md, B);
-    if (rc) return rc;
-    MfmaImpl *m = impl(md);
-    MArgs A = make_args(md, B, d_in, d_out, d_iters, d_status, mode, max_sweeps);
-    m->last_B = B;
-    return run(md, A, profile != 0, stream);
-}
-
-int mfma_sync_status(MfmaData &md, rac_stats *stats) {
-    MfmaImpl *m = impl(md);
-    if (!m) return RAC_OK;
     const int32_t B = m->last_B;
     HIP_OK(hipEventSynchronize(m->ev1));
-    std::vector<long long> hc((size_t)B);
-    std::vector<int32_t> hi((size_t)B);
-    int32_t hrc = 0;
-    // iteration counts of the device call live in the per-state table
     std::vector<MState> hs((size_t)B);
+    int32_t hrc = 0;
     HIP_OK(hipMemcpy(hs.data(), m->st, (size_t)B * sizeof(MState), hipMemcpyDeviceToHost));
     HIP_OK(hipMemcpy(&hrc, m->d_rc, 4, hipMemcpyDeviceToHost));
+    std::vector<long long> hc((size_t)B);
+    std::vector<int32_t> hi((size_t)B);
     for (int32_t s = 0; s < B; ++s) {
         hc[(size_t)s] = hs[(size_t)s].checks;
         hi[(size_t)s] = hs[(size_t)s].iters;

@@ -210,6 +210,9 @@ struct rac_net {
     uint64_t *rel = nullptr;   // [m][d] constraint rows, kept for lazily packed layouts
     PathData bits, i8;
     MfmaData mfma;
+    uint64_t *mf_in = nullptr, *mf_out = nullptr;   // staging of host-pointer batch calls
+    int32_t *mf_it = nullptr, *mf_st = nullptr;
+    int32_t mf_cap = 0;
     Runner run;
     rac_stats last{};
     int pending_rc = RAC_OK;   // device-pointer call awaiting rac_sync_status
@@ -315,6 +318,10 @@ extern "C" void rac_destroy(rac_net *net) {
     release_path(net->bits);
     release_path(net->i8);
     mfma_release(net->mfma);
+    dfree(net->mf_in);
+    dfree(net->mf_out);
+    dfree(net->mf_it);
+    dfree(net->mf_st);
     dfree(net->row_ptr);
     dfree(net->nbr);
     dfree(net->deg);
@@ -896,6 +903,49 @@ extern "C" int rac_enforce(rac_net *net, uint64_t *dom, const int32_t *changed, 
     return collect_bits(net, 1, path, dom, iters, status);
 }
 
+// States still active when at most this many remain leave the matrix-core
+// path and finish on the persistent bit-row path, whose incremental steps
+// touch only arcs into changed variables.
+static int32_t mfma_handoff_threshold() {
+    const char *e = getenv("RAC_MFMA_HANDOFF");
+    if (e) return std::max(0, atoi(e));
+    return 32;
+}
+
+// The batched matrix-core path: matrix-core steps while many states are
+// active, then the stragglers on the bit-row path (continuing from D^(k)
+// with @changed = the variables step k changed, Proposition 2).
+static int run_mfma(rac_net *net, int32_t B, const uint64_t *d_in, uint64_t *d_out,
+                    int32_t *d_it, int32_t *d_st, hipStream_t s) {
+    RAC_TRY(mfma_ensure(net->mfma, net->n, net->d, net->arcs, net->row_ptr, net->nbr, net->deg,
+                        net->rel, net->arc_src, net->h_row_ptr, net->stream));
+    int32_t k = 0, P = 0;
+    RAC_TRY(mfma_start(net->mfma, B, d_in, net->opt.mode, net->opt.max_sweeps, net->opt.profile,
+                       mfma_handoff_threshold(), s, &k, &P));
+    if (P > 0) {
+        RAC_TRY(ensure_path(net, RAC_PATH_BITS, call_target(net, P)));
+        PathData &pd = net->bits;
+        RAC_TRY(prepare_net_runner(net, P, pd));
+        Runner &r = net->run;
+        RAC_TRY(mfma_handoff(net->mfma, k, r.din, r.changed, s));
+        Launch L = base_launch(r, P, net->opt);
+        L.nets = pd.d_desc;
+        L.stage_vars = stage_vars_for(net->n);
+        L.din = r.din;
+        L.dout = r.dout;
+        L.iters_out = r.iters;
+        L.status_out = r.status;
+        L.changed0 = r.changed;
+        L.checks1 = 0;   // the matrix-core finaliser already counted step k+1
+        const int32_t maxs = net->opt.max_sweeps > 0 ? net->opt.max_sweeps : net->n * net->d + 1;
+        L.max_sweeps = maxs - k;
+        RAC_TRY(launch_fixpoint(r, net->device, s, L, (int64_t)pd.nitems * P, false, false));
+        RAC_TRY(mfma_merge(net->mfma, k, r.dout, r.iters, r.status, r.checks, r.rc, s));
+    }
+    RAC_TRY(mfma_finish(net->mfma, d_out, d_it, d_st, s));
+    return RAC_OK;
+}
+
 extern "C" int rac_enforce_batch(rac_net *net, int32_t B, uint64_t *dom, int32_t *iters,
                                  int32_t *status) {
     if (!net || (!dom && B > 0)) return set_error(RAC_EINVAL, "net or dom is NULL");
@@ -905,11 +955,29 @@ extern "C" int rac_enforce_batch(rac_net *net, int32_t B, uint64_t *dom, int32_t
     HIP_TRY(hipSetDevice(net->device));
     const int32_t path = pick_path(net, B, net->opt.path);
     if (path == RAC_PATH_MFMA) {
-        RAC_TRY(mfma_ensure(net->mfma, net->n, net->d, net->arcs, net->row_ptr, net->nbr,
-                            net->deg, net->rel, net->arc_src, net->h_row_ptr, net->stream));
-        RAC_TRY(mfma_enforce_host(net->mfma, B, dom, iters, status, net->opt.mode,
-                                  net->opt.max_sweeps, net->opt.profile, net->stream, &net->last));
-        return RAC_OK;
+        if (B > net->mf_cap) {
+            dfree(net->mf_in);
+            dfree(net->mf_out);
+            dfree(net->mf_it);
+            dfree(net->mf_st);
+            RAC_TRY(dalloc(&net->mf_in, (size_t)B * net->n));
+            RAC_TRY(dalloc(&net->mf_out, (size_t)B * net->n));
+            RAC_TRY(dalloc(&net->mf_it, (size_t)B));
+            RAC_TRY(dalloc(&net->mf_st, (size_t)B));
+            net->mf_cap = B;
+        }
+        HIP_TRY(hipMemcpyAsync(net->mf_in, dom, (size_t)B * net->n * 8, hipMemcpyHostToDevice,
+                               net->stream));
+        RAC_TRY(run_mfma(net, B, net->mf_in, net->mf_out, net->mf_it, net->mf_st, net->stream));
+        HIP_TRY(hipMemcpyAsync(dom, net->mf_out, (size_t)B * net->n * 8, hipMemcpyDeviceToHost,
+                               net->stream));
+        if (iters)
+            HIP_TRY(hipMemcpyAsync(iters, net->mf_it, (size_t)B * 4, hipMemcpyDeviceToHost, net->stream));
+        if (status)
+            HIP_TRY(hipMemcpyAsync(status, net->mf_st, (size_t)B * 4, hipMemcpyDeviceToHost,
+                                   net->stream));
+        HIP_TRY(hipStreamSynchronize(net->stream));
+        return mfma_collect(net->mfma, &net->last);
     }
     RAC_TRY(ensure_path(net, path, call_target(net, B)));
     RAC_TRY(prepare_net_runner(net, B, path == RAC_PATH_INT8 ? net->i8 : net->bits));
@@ -933,10 +1001,7 @@ extern "C" int rac_enforce_batch_device(rac_net *net, int32_t B, const uint64_t 
     hipStream_t s = (hipStream_t)stream;
     const int32_t path = pick_path(net, B, net->opt.path);
     if (path == RAC_PATH_MFMA) {
-        RAC_TRY(mfma_ensure(net->mfma, net->n, net->d, net->arcs, net->row_ptr, net->nbr,
-                            net->deg, net->rel, net->arc_src, net->h_row_ptr, net->stream));
-        RAC_TRY(mfma_enforce_device(net->mfma, B, d_dom_in, d_dom_out, d_iters, d_status,
-                                    net->opt.mode, net->opt.max_sweeps, net->opt.profile, s));
+        RAC_TRY(run_mfma(net, B, d_dom_in, d_dom_out, d_iters, d_status, s));
         net->pending = true;
         net->last.path = RAC_PATH_MFMA;
         return RAC_OK;
@@ -966,7 +1031,7 @@ extern "C" int rac_sync_status(rac_net *net) {
     if (!net->pending) return RAC_OK;
     HIP_TRY(hipSetDevice(net->device));
     net->pending = false;
-    if (net->last.path == RAC_PATH_MFMA) return mfma_sync_status(net->mfma, &net->last);
+    if (net->last.path == RAC_PATH_MFMA) return mfma_collect(net->mfma, &net->last);
     int32_t hrc = 0;
     HIP_TRY(hipDeviceSynchronize());
     HIP_TRY(hipMemcpy(&hrc, net->run.rc, 4, hipMemcpyDeviceToHost));

@@ -23,6 +23,16 @@ namespace rac {
 
 #define DEV __device__ __forceinline__
 
+// Pointers into device memory that arrive through descriptors are generic;
+// casting them to the global address space lets the compiler emit global
+// loads, which (unlike flat loads) do not count against the LDS wait counter.
+#define GLOBAL __attribute__((address_space(1)))
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+template <typename T> DEV const GLOBAL T *as_global(const T *p) {
+    return (const GLOBAL T *)p;
+}
+
 template <typename T> DEV T ld_rlx(T *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -111,7 +121,7 @@ struct DomView {
 // Rows of one 16-byte quad without support in dom(y), as bits 0..3 (uint32
 // rows) or 0..1 (uint64 rows).
 template <bool WIDE>
-DEV uint32_t quad_fail(const uint4 v, uint64_t dy) {
+DEV uint32_t quad_fail(const u32x4 v, uint64_t dy) {
     if (WIDE) {
         const uint64_t r0 = (uint64_t)v.x | ((uint64_t)v.y << 32);
         const uint64_t r1 = (uint64_t)v.z | ((uint64_t)v.w << 32);
@@ -124,7 +134,7 @@ DEV uint32_t quad_fail(const uint4 v, uint64_t dy) {
 
 template <int C>
 struct GroupUnit {
-    uint4 v[C];
+    u32x4 v[C];
     int32_t y;
     int32_t q0;
     bool live;
@@ -143,13 +153,13 @@ struct UnitCursor {
 };
 
 template <bool ALL, int C, class DV>
-DEV void load_unit(GroupUnit<C> &u, UnitCursor &cur, const uint4 *__restrict__ rows,
-                   const int32_t *__restrict__ nbrp, const DV &D, int32_t qpa, int lane) {
+DEV void load_unit(GroupUnit<C> &u, UnitCursor &cur, const GLOBAL u32x4 *__restrict__ rows,
+                   const GLOBAL int32_t *__restrict__ nbrp, const DV &D, int32_t qpa, int lane) {
     u.live = cur.g < cur.g1;     // wave-uniform
     if (!u.live) return;
     u.y = nbrp[cur.g * kGroup + lane];
     u.q0 = cur.c * C;
-    const uint4 *base = rows + (cur.g * qpa + u.q0) * kGroup + lane;
+    const GLOBAL u32x4 *base = rows + (cur.g * qpa + u.q0) * kGroup + lane;
     if (ALL) {
 #pragma unroll
         for (int q = 0; q < C; ++q) u.v[q] = base[q * kGroup];
@@ -177,8 +187,9 @@ DEV uint64_t test_unit(const GroupUnit<C> &u, const DV &D) {
 }
 
 template <bool ALL, bool WIDE, int C, int DEPTH, class DV>
-DEV uint64_t revise_groups(const uint4 *__restrict__ rows, const int32_t *__restrict__ nbrp,
-                           const DV &D, int64_t g0, int64_t g1, int32_t qpa) {
+DEV uint64_t revise_groups(const GLOBAL u32x4 *__restrict__ rows,
+                           const GLOBAL int32_t *__restrict__ nbrp, const DV &D, int64_t g0,
+                           int64_t g1, int32_t qpa) {
     const int lane = threadIdx.x & (kWave - 1);
     UnitCursor cur{g0, g1, 0, qpa / C};
     GroupUnit<C> u[DEPTH];
@@ -197,18 +208,19 @@ DEV uint64_t revise_groups(const uint4 *__restrict__ rows, const int32_t *__rest
 
 template <bool ALL, class DV>
 DEV uint64_t revise_bits(const NetDesc &N, const DV &D, int64_t g0, int64_t g1) {
-    const uint4 *rows = (const uint4 *)N.rows;
+    const GLOBAL u32x4 *rows = as_global((const u32x4 *)N.rows);
+    const GLOBAL int32_t *nbrp = as_global(N.nbrp);
     if (N.kind == ROW64)   // qpa is a multiple of 4
-        return revise_groups<ALL, true, 4, 2>(rows, N.nbrp, D, g0, g1, N.qpa);
+        return revise_groups<ALL, true, 4, 2>(rows, nbrp, D, g0, g1, N.qpa);
     switch (N.qpa) {       // ROW32: qpa = 1..8, one chunk per group
-    case 1: return revise_groups<ALL, false, 1, 8>(rows, N.nbrp, D, g0, g1, 1);
-    case 2: return revise_groups<ALL, false, 2, 4>(rows, N.nbrp, D, g0, g1, 2);
-    case 3: return revise_groups<ALL, false, 3, 3>(rows, N.nbrp, D, g0, g1, 3);
-    case 4: return revise_groups<ALL, false, 4, 2>(rows, N.nbrp, D, g0, g1, 4);
-    case 5: return revise_groups<ALL, false, 5, 2>(rows, N.nbrp, D, g0, g1, 5);
-    case 6: return revise_groups<ALL, false, 6, 2>(rows, N.nbrp, D, g0, g1, 6);
-    case 7: return revise_groups<ALL, false, 7, 2>(rows, N.nbrp, D, g0, g1, 7);
-    default: return revise_groups<ALL, false, 8, 2>(rows, N.nbrp, D, g0, g1, 8);
+    case 1: return revise_groups<ALL, false, 1, 8>(rows, nbrp, D, g0, g1, 1);
+    case 2: return revise_groups<ALL, false, 2, 4>(rows, nbrp, D, g0, g1, 2);
+    case 3: return revise_groups<ALL, false, 3, 3>(rows, nbrp, D, g0, g1, 3);
+    case 4: return revise_groups<ALL, false, 4, 2>(rows, nbrp, D, g0, g1, 4);
+    case 5: return revise_groups<ALL, false, 5, 2>(rows, nbrp, D, g0, g1, 5);
+    case 6: return revise_groups<ALL, false, 6, 2>(rows, nbrp, D, g0, g1, 6);
+    case 7: return revise_groups<ALL, false, 7, 2>(rows, nbrp, D, g0, g1, 7);
+    default: return revise_groups<ALL, false, 8, 2>(rows, nbrp, D, g0, g1, 8);
     }
 }
 
@@ -221,7 +233,7 @@ DEV uint64_t revise_bits(const NetDesc &N, const DV &D, int64_t g0, int64_t g1) 
 constexpr int kI8Depth = 6;
 
 template <bool ALL, class DV>
-DEV uint64_t revise_i8(const int8_t *__restrict__ rows, const int32_t *__restrict__ nbr,
+DEV uint64_t revise_i8(const GLOBAL int8_t *__restrict__ rows, const GLOBAL int32_t *__restrict__ nbr,
                        const DV &D, int64_t j0, int64_t j1, int32_t d, int32_t dp) {
     const int lane = threadIdx.x & (kWave - 1);
     const int lpr = dp >> 4;              // lanes per row: 1 or 2
@@ -234,7 +246,7 @@ DEV uint64_t revise_i8(const int8_t *__restrict__ rows, const int32_t *__restric
     const bool active = s < A;
     const int64_t arc_bytes = (int64_t)d * dp;
     bool ok = true;
-    int4 v[kI8Depth];
+    i32x4 v[kI8Depth];
     int32_t y[kI8Depth];
     bool in[kI8Depth];
     int64_t jn = j0;                      // first arc of the next unit to load
@@ -245,7 +257,7 @@ DEV uint64_t revise_i8(const int8_t *__restrict__ rows, const int32_t *__restric
         y[i] = nbr[jc];
         bool want = true;
         if (!ALL) want = in[i] && D.changed(y[i]);
-        if (want) v[i] = *reinterpret_cast<const int4 *>(rows + jc * arc_bytes + u0 * 16);
+        if (want) v[i] = *reinterpret_cast<const GLOBAL i32x4 *>(rows + jc * arc_bytes + u0 * 16);
         if (!ALL) in[i] = want;
         jn += A;
     };
@@ -277,7 +289,8 @@ DEV uint64_t revise_i8(const int8_t *__restrict__ rows, const int32_t *__restric
 template <bool ALL, class DV>
 DEV uint64_t revise(const NetDesc &N, const DV &D, int64_t u0, int64_t u1) {
     if (N.kind != ROWI8) return revise_bits<ALL>(N, D, u0, u1);
-    return revise_i8<ALL>((const int8_t *)N.rows, N.nbr, D, u0, u1, N.d, N.dp);
+    return revise_i8<ALL>(as_global((const int8_t *)N.rows), as_global(N.nbr), D, u0, u1, N.d,
+                          N.dp);
 }
 
 // ---------------------------------------------------------------------------
@@ -435,12 +448,18 @@ DEV int probe_slots(const Launch &L, int64_t first, int32_t width, int64_t nslot
 }
 
 DEV int try_claim(const Launch &L, int64_t &cursor, int &p_out, int &k_out, int &c_out,
-                  int &lane_out) {
+                  int &lane_out, int spins) {
     Global *G = L.ws.global;
     if (ld_rlx(&G->error) != 0) return -1;
     if (ld_rlx(&G->active) <= 0) return -1;
     const int64_t nslots = (int64_t)L.nprob * L.lanes_per_prob;
     if (probe_slots(L, cursor, 1, nslots, cursor, p_out, k_out, c_out, lane_out)) return 1;
+    // While its own problem is still running, an idle wave mostly re-probes
+    // its own lane (the next step's tickets appear on every lane at once) and
+    // scans the other slots only every fourth poll, which keeps the polling
+    // traffic on the ticket lines low.
+    const int32_t cp = (int32_t)(cursor / L.lanes_per_prob);
+    if (spins > 0 && (spins & 3) != 3 && ld_rlx(&L.ws.ctrl[cp].done) == 0) return 0;
     for (int64_t base = 1; base <= nslots; base += kWave) {
         const int32_t width = (int32_t)((nslots - base + 1) < kWave ? (nslots - base + 1) : kWave);
         int64_t first = cursor + base;
@@ -507,7 +526,7 @@ __global__ __launch_bounds__(kWave) void sweep_kernel(Launch L) {
     int staged_p = -1, staged_k = -1;
     for (;;) {
         int p = 0, k = 0, c = 0, ln = 0;
-        const int r = try_claim(L, cursor, p, k, c, ln);
+        const int r = try_claim(L, cursor, p, k, c, ln, spins);
         if (r < 0) return;
         if (r == 0) {
             if (++spins > L.spin_limit) {

@@ -214,13 +214,17 @@ MFMA_CASES = [(40, 32, 37, 0.6, 0.3), (45, 10, 130, 0.8, 0.5), (13, 4, 300, 1.0,
               (70, 17, 129, 0.4, 0.7), (9, 1, 64, 0.9, 0.0), (100, 32, 257, 0.8, 0.25)]
 
 
+@pytest.mark.parametrize("handoff", ["0", "32", "100000"])
 @pytest.mark.parametrize("n,d,B,p1,p2", MFMA_CASES)
-def test_batch_states_mfma(n, d, B, p1, p2):
+def test_batch_states_mfma(n, d, B, p1, p2, handoff, monkeypatch):
+    # handoff: states left when the rest moves to the bit-row path
+    # (0: never; 100000: right after the first matrix-core steps)
+    monkeypatch.setenv("RAC_MFMA_HANDOFF", handoff)
     inst = gen.model_b(40 + n + d, n, d, p1, p2)
     doms, _ = gen.partial_assign_states(41 + B, n, d, B, min(n, 12))
     rel = inst.rel_u8()
     for mode in (0, 1):
-        say(f"[gpu] batch mfma n={n} d={d} B={B} mode={mode}")
+        say(f"[gpu] batch mfma n={n} d={d} B={B} mode={mode} handoff={handoff}")
         net = rac.Net.from_u8(n, d, inst.edges, rel, path=rac.PATH_MFMA, mode=mode)
         for rep in range(2):
             got, iters, status = net.enforce_batch(doms)
@@ -258,4 +262,30 @@ def test_mfma_step_cap():
     with pytest.raises(rac.RacError) as ei:
         net.enforce_batch(doms)
     assert ei.value.code == rac.RAC_ENOTCONVERGED
+    net.close()
+
+
+@pytest.mark.parametrize("path", [rac.PATH_BITS, rac.PATH_MFMA])
+def test_batch_device_entry_point_matches_host(path):
+    torch = pytest.importorskip("torch")
+    n, d, B = 60, 32, 200
+    inst = gen.model_b(7, n, d, 0.7, 0.3)
+    doms, _ = gen.partial_assign_states(8, n, d, B, 10)
+    say(f"[gpu] device entry point path={path}")
+    net = rac.Net.from_instance(inst, path=path)
+    h_dom, h_it, h_st = net.enforce_batch(doms)
+    dev = torch.device("cuda:0")
+    d_in = torch.from_numpy(doms.view(np.int64)).to(dev)
+    d_out = torch.zeros_like(d_in)
+    d_it = torch.zeros(B, dtype=torch.int32, device=dev)
+    d_st = torch.zeros(B, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    for _ in range(2):
+        net.enforce_batch_device(d_in, d_out, d_it, d_st, stream)
+        net.sync()
+        torch.cuda.synchronize()
+        assert np.array_equal(d_out.cpu().numpy().view(np.uint64), h_dom)
+        assert np.array_equal(d_it.cpu().numpy(), h_it)
+        assert np.array_equal(d_st.cpu().numpy(), h_st)
+    assert np.array_equal(d_in.cpu().numpy().view(np.uint64), doms)   # input untouched
     net.close()
