@@ -65,7 +65,19 @@ class rac_stats(ctypes.Structure):
                 ("item_bytes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
+def _share_runtime_with_torch():
+    """PyTorch ships its own HIP runtime. Importing it first makes librac's
+    libamdhip64.so.7 / libhsa-runtime64.so.1 resolve to that same runtime (by
+    soname), so one process never holds two HIP runtimes; with the order
+    reversed, torch would load a second copy and fail to see the GPU."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
 def _load():
+    _share_runtime_with_torch()
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first "
                            "(the library has no CPU fallback)")
