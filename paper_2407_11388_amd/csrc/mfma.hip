@@ -60,8 +60,10 @@ struct MArgs {
     const int32_t *deg;               // [n]
     const int8_t *r8;                 // [arcs][32][32]
     const int32_t *bstart;            // [n][nblk+1] first arc of x with neighbour >= 8*b
-    const uint8_t *bmask;             // [n][nblk] bit l: x is constrained with y = 8*b + l
+    const uint32_t *bmask;            // [n][nblk] bit l: x is constrained with y = 8*b + l
+                                      // (32-bit words, so that scalar loads read them)
     int32_t nblk;                     // ceil(n / 8)
+    int32_t narcs;                    // number of arcs (rows of r8)
     int8_t *dom8[2];                  // [capB][N32]
     uint32_t *chg, *wipe;             // [n][words]
     int32_t words;                    // capB / 32
@@ -118,7 +120,10 @@ __global__ void mfma_init_kernel(MArgs A) {
 }
 
 __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
-    __shared__ v4i s_b[2][kMY][kMS][2];   // [buffer][y][state][half]: 2 x 32 KiB
+    // [buffer][neighbour][half][state]: bytes 16*half .. 16*half+15 of the
+    // domain column of one state, so the 64 lanes of a B-operand read cover
+    // 1 KiB contiguously (no bank conflicts)
+    __shared__ v4i s_b[2][kMY][2][kMS];   // 2 x 32 KiB
     const int nact = A.cnt[(k - 1) & 1];
     // workgroup -> (x-tile, state tile); the state tiles of one x-tile share
     // blockIdx % 8 and so an XCD
@@ -141,46 +146,45 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
     auto state_of = [&](int i) { return st0 + i < nact ? act[st0 + i] : -1; };
 
     const int x = xt * kMX + wave;
-    const bool xv = x < A.n;
+    const bool xv = x < A.n;                // wave-uniform
     const int nblk = A.nblk;
     const int32_t *bst = A.bstart + (int64_t)(xv ? x : 0) * (nblk + 1);
-    const uint8_t *bmk = A.bmask + (int64_t)(xv ? x : 0) * nblk;
+    const uint32_t *bmk = A.bmask + (int64_t)(xv ? x : 0) * nblk;
     const int8_t *dcur = A.dom8[(k - 1) & 1];
     const int half = lane >> 5, col = lane & 31;
 
-    // B staging: thread t moves units u = t + 512 i of the block (y, state, half)
-    constexpr int kUnitsPerThread = kMY * kMS * 2 / kMThreads;   // 4
-    auto fetch_b = [&](int yb, v4i (&r)[kUnitsPerThread]) {
+    // B staging: thread t moves, for every neighbour block, the 16-byte units
+    // (state slot t & 127, half (t >> 7) & 1, neighbour (t >> 8) + 2i),
+    // i = 0..3. Every load is issued: a slot past the active states reads a
+    // valid state (its products are never used) and a neighbour past n reads
+    // variable n-1 (it is never a neighbour of anything).
+    const int b_sl = tid & (kMS - 1), b_h = (tid >> 7) & 1, b_y0 = tid >> 8;
+    const int b_state = act[st0 + b_sl < nact ? st0 + b_sl : nact - 1];
+    const int8_t *b_src = dcur + (int64_t)b_state * A.N32 + b_h * 16;
+    auto fetch_b = [&](int yb, v4i (&r)[4]) {
 #pragma unroll
-        for (int i = 0; i < kUnitsPerThread; ++i) {
-            const int u = tid + kMThreads * i;
-            const int yl = u / (kMS * 2), rem = u - yl * kMS * 2;
-            const int sl = rem >> 1, h = rem & 1;
-            const int s = state_of(sl);
-            const int y = yb + yl;
-            v4i v = {0, 0, 0, 0};
-            if (s >= 0 && y < A.n)
-                v = *reinterpret_cast<const v4i *>(dcur + (int64_t)s * A.N32 + (int64_t)y * 32 + h * 16);
-            r[i] = v;
+        for (int i = 0; i < 4; ++i) {
+            int y = yb + b_y0 + 2 * i;
+            y = y < A.n ? y : A.n - 1;
+            r[i] = *reinterpret_cast<const v4i *>(b_src + (int64_t)y * 32);
         }
     };
-    auto store_b = [&](int buf, const v4i (&r)[kUnitsPerThread]) {
+    auto store_b = [&](int buf, const v4i (&r)[4]) {
 #pragma unroll
-        for (int i = 0; i < kUnitsPerThread; ++i) {
-            const int u = tid + kMThreads * i;
-            const int yl = u / (kMS * 2), rem = u - yl * kMS * 2;
-            s_b[buf][yl][rem >> 1][rem & 1] = r[i];
-        }
+        for (int i = 0; i < 4; ++i) s_b[buf][b_y0 + 2 * i][b_h][b_sl] = r[i];
     };
-    // relation blocks of this wave's arcs in one neighbour block, indexed by
-    // the neighbour's position in the block (arcs are sorted by neighbour)
-    auto fetch_a = [&](int32_t j0, uint32_t msk, v4i (&a)[kMY]) {
+    // relation blocks of this wave's arcs in one neighbour block: the block's
+    // arcs are consecutive (sorted by neighbour), j0 .. j0+cnt-1; slots past
+    // cnt repeat the last arc so that every load is issued unconditionally
+    const int32_t jmax = A.narcs > 0 ? A.narcs - 1 : 0;   // r8 holds at least one block
+    auto fetch_a = [&](int32_t j0, int cnt, v4i (&a)[kMY]) {
+        const int last = cnt > 0 ? cnt - 1 : 0;
 #pragma unroll
-        for (int l = 0; l < kMY; ++l)
-            if ((msk >> l) & 1u) {
-                const int32_t j = j0 + __builtin_popcount(msk & ((1u << l) - 1u));
-                a[l] = *reinterpret_cast<const v4i *>(A.r8 + (int64_t)j * 1024 + col * 32 + half * 16);
-            }
+        for (int l = 0; l < kMY; ++l) {
+            int32_t j = j0 + (l < last ? l : last);
+            j = j < jmax ? j : jmax;
+            a[l] = *reinterpret_cast<const v4i *>(A.r8 + (int64_t)j * 1024 + col * 32 + half * 16);
+        }
     };
 
     v16i rm[kMSub];
@@ -189,68 +193,62 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) rm[t][v] = 0x7FFFFFFF;
 
-    v4i breg[kUnitsPerThread];
+    v4i breg[4];
     v4i acur[kMY], anext[kMY];
-    // neighbour tables are read two blocks ahead, relation blocks one ahead
-    uint32_t mcur = xv ? bmk[0] : 0u;
-    int32_t jnext = xv && nblk > 1 ? bst[1] : 0;
-    uint32_t mnext = xv && nblk > 1 ? bmk[1] : 0u;
+    // neighbour tables are read two blocks ahead, operands one block ahead
+    auto jtab = [&](int b) { return xv ? bst[b < nblk ? b : nblk - 1] : 0; };
+    auto mtab = [&](int b) { return xv ? bmk[b < nblk ? b : nblk - 1] : 0u; };
+    uint32_t mcur = mtab(0);
+    int32_t jnext = jtab(1);
+    uint32_t mnext = mtab(1);
     fetch_b(0, breg);
+    fetch_a(jtab(0), __builtin_popcount(mcur), acur);
     store_b(0, breg);
-    fetch_a(xv ? bst[0] : 0, mcur, acur);
     __syncthreads();
     for (int blk = 0; blk < nblk; ++blk) {
         const int buf = blk & 1;
-        const int yb = blk * kMY;
-        uint32_t mnn = 0u;
-        int32_t jnn = 0;
-        if (blk + 1 < nblk) {
-            fetch_b(yb + kMY, breg);
-            fetch_a(jnext, mnext, anext);
-            if (xv && blk + 2 < nblk) {
-                jnn = bst[blk + 2];
-                mnn = bmk[blk + 2];
+        // next block's operands, in flight during this block's products (the
+        // last block re-reads itself: harmless, never used)
+        const int bn = blk + 1 < nblk ? blk + 1 : blk;
+        const int32_t jnn = jtab(blk + 2);
+        const uint32_t mnn = mtab(blk + 2);
+        fetch_b(bn * kMY, breg);
+        fetch_a(jnext, __builtin_popcount(mnext), anext);
+
+        // products of this block's arcs, two at a time: a fresh accumulator
+        // per arc, folded into the running minimum with one min3 per value.
+        // An odd last arc is paired with itself.
+        const int cnt = __builtin_popcount(mcur);
+        uint32_t msk = mcur;
+#pragma unroll
+        for (int i = 0; i < kMY; i += 2) {
+            if (i >= cnt) break;
+            const int l0 = __builtin_ctz(msk);
+            msk &= msk - 1u;
+            const bool two = i + 1 < cnt;
+            const int l1 = two ? __builtin_ctz(msk) : l0;
+            if (two) msk &= msk - 1u;
+            v4i b0[kMSub], b1[kMSub];
+#pragma unroll
+            for (int t = 0; t < kMSub; ++t) {
+                b0[t] = s_b[buf][l0][half][t * 32 + col];
+                b1[t] = s_b[buf][l1][half][t * 32 + col];
+            }
+#pragma unroll
+            for (int t = 0; t < kMSub; ++t) {
+                const v16i zero = {0};
+                const v16i c0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(acur[i], b0[t], zero, 0, 0, 0);
+                const v16i c1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(acur[i + 1], b1[t], zero, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 16; ++v) rm[t][v] = min(rm[t][v], min(c0[v], c1[v]));
             }
         }
-        // products of this block: a fresh accumulator per neighbour, folded
-        // into the running minimum two neighbours at a time
+        store_b(buf ^ 1, breg);
 #pragma unroll
-        for (int l = 0; l < kMY; l += 2) {
-            const bool p0 = (mcur >> l) & 1u, p1 = (mcur >> (l + 1)) & 1u;
-            if (p0 || p1) {
-#pragma unroll
-                for (int t = 0; t < kMSub; ++t) {
-                    const v16i zero = {0};
-                    v16i c0, c1;
-                    if (p0) {
-                        const v4i b0 = s_b[buf][l][t * 32 + col][half];
-                        c0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(acur[l], b0, zero, 0, 0, 0);
-                    }
-                    if (p1) {
-                        const v4i b1 = s_b[buf][l + 1][t * 32 + col][half];
-                        c1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(acur[l + 1], b1, zero, 0, 0, 0);
-                    }
-                    if (p0 && p1) {
-#pragma unroll
-                        for (int v = 0; v < 16; ++v) rm[t][v] = min(rm[t][v], min(c0[v], c1[v]));
-                    } else if (p0) {
-#pragma unroll
-                        for (int v = 0; v < 16; ++v) rm[t][v] = min(rm[t][v], c0[v]);
-                    } else {
-#pragma unroll
-                        for (int v = 0; v < 16; ++v) rm[t][v] = min(rm[t][v], c1[v]);
-                    }
-                }
-            }
-        }
-        if (blk + 1 < nblk) {
-            store_b(buf ^ 1, breg);
-#pragma unroll
-            for (int l = 0; l < kMY; ++l) acur[l] = anext[l];
-            mcur = mnext;
-            mnext = mnn;
-            jnext = jnn;
-        }
+        for (int l = 0; l < kMY; ++l) acur[l] = anext[l];
+        mcur = mnext;
+        mnext = mnn;
+        jnext = jnn;
         __syncthreads();
     }
 
@@ -531,7 +529,7 @@ struct MfmaImpl {
     const int32_t *deg = nullptr;
     int8_t *r8 = nullptr;
     int32_t *bstart = nullptr;
-    uint8_t *bmask = nullptr;
+    uint32_t *bmask = nullptr;
     int32_t nblk = 0;
     int32_t capB = 0, words = 0;
     int8_t *dom8[2] = {nullptr, nullptr};
@@ -636,7 +634,7 @@ int mfma_ensure(MfmaData &md, int32_t n, int32_t d, int64_t arcs, const int32_t 
     // per (variable, block of 8 neighbours): first arc and neighbour mask
     const int32_t nblk = (n + kMY - 1) / kMY;
     std::vector<int32_t> bstart((size_t)n * (nblk + 1));
-    std::vector<uint8_t> bmask((size_t)n * nblk, 0);
+    std::vector<uint32_t> bmask((size_t)n * nblk, 0);
     for (int32_t x = 0; x < n; ++x) {
         int32_t j = h_row_ptr[x];
         const int32_t j1 = h_row_ptr[x + 1];
@@ -646,14 +644,15 @@ int mfma_ensure(MfmaData &md, int32_t n, int32_t d, int64_t arcs, const int32_t 
         }
         for (int32_t jj = h_row_ptr[x]; jj < j1; ++jj) {
             const int32_t y = nbr_s[(size_t)jj];
-            bmask[(size_t)x * nblk + y / kMY] |= (uint8_t)(1u << (y % kMY));
+            bmask[(size_t)x * nblk + y / kMY] |= 1u << (y % kMY);
         }
     }
     m->nblk = nblk;
     HIP_OK(hipMalloc(&m->bstart, bstart.size() * 4));
-    HIP_OK(hipMalloc(&m->bmask, std::max<size_t>(1, bmask.size())));
+    HIP_OK(hipMalloc(&m->bmask, std::max<size_t>(1, bmask.size()) * 4));
     HIP_OK(hipMemcpy(m->bstart, bstart.data(), bstart.size() * 4, hipMemcpyHostToDevice));
-    if (!bmask.empty()) HIP_OK(hipMemcpy(m->bmask, bmask.data(), bmask.size(), hipMemcpyHostToDevice));
+    if (!bmask.empty())
+        HIP_OK(hipMemcpy(m->bmask, bmask.data(), bmask.size() * 4, hipMemcpyHostToDevice));
     int32_t *d_src = nullptr;
     HIP_OK(hipMalloc(&m->row_ptr, ((size_t)n + 1) * 4));
     HIP_OK(hipMalloc(&m->nbr_s, std::max<size_t>(1, (size_t)arcs) * 4));
@@ -739,6 +738,7 @@ static MArgs make_args(MfmaData &md, int32_t B, const uint64_t *din, uint64_t *d
     A.bstart = m->bstart;
     A.bmask = m->bmask;
     A.nblk = m->nblk;
+    A.narcs = (int32_t)md.arcs;
     A.dom8[0] = m->dom8[0];
     A.dom8[1] = m->dom8[1];
     A.chg = m->chg;
