@@ -119,12 +119,12 @@ static int device_info(int device, DeviceInfo **out) {
     return RAC_OK;
 }
 
-// LDS bytes the sweep kernel needs to stage `vars` variables.
+// LDS bytes of one sweep wave: its scratch plus `vars` staged variables.
 static size_t stage_bytes(int32_t vars) {
-    return vars > 0 ? (size_t)vars * 8 + ((size_t)vars / 32 + 2) * 4 : 0;
+    return (size_t)kScratchWords * 8 + (vars > 0 ? (size_t)vars * 8 + ((size_t)vars / 32 + 2) * 4 : 0);
 }
 
-// Resident sweep workgroups (= waves) on the whole device for a given LDS size.
+// Resident revise workgroups (= waves) on the whole device for a given LDS size.
 static int sweep_slots(int device, size_t smem, int64_t *slots) {
     DeviceInfo *di;
     RAC_TRY(device_info(device, &di));
@@ -135,7 +135,7 @@ static int sweep_slots(int device, size_t smem, int64_t *slots) {
             return RAC_OK;
         }
     int nb = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep_kernel, kWave, smem));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, revise_kernel, kWave, smem));
     if (nb < 1) nb = 1;
     di->blocks_per_cu.push_back({smem, nb});
     *slots = (int64_t)nb * di->num_cu;
@@ -172,29 +172,38 @@ struct PathData {
     NetDesc *d_desc = nullptr;
 };
 
+constexpr int kProfSteps = 64;   // steps whose revise kernel is timed in profile mode
+constexpr int kHist = kProfSteps + 2;
+
+// One round of steps, captured as a HIP graph.
+struct RoundGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 // Workspace + per-call buffers for up to `cap_probs` problems of one layout.
 struct Runner {
     int32_t cap_probs = 0;
     int64_t cap_vars = 0;
     Workspace ws{};
+    int32_t *hist = nullptr;        // [kHist] problems running at step k (profile mode)
     int32_t *prob_net = nullptr;
     int64_t *prob_off = nullptr;
-    int64_t *item_off = nullptr;
     int64_t tables_key = -1;   // (B, nitems) the problem tables were last written for
     uint64_t *din = nullptr, *dout = nullptr;
     int32_t *iters = nullptr, *status = nullptr, *rc = nullptr;
     long long *checks = nullptr;
     uint8_t *changed = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr, evk0 = nullptr, evk1 = nullptr;
+    int32_t *h_nact = nullptr;      // pinned: problems still running after a round
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_round = nullptr;
+    hipEvent_t kev[2 * kProfSteps] = {};
     bool profiled = false;
-    // graph of (init, sweep, finish)
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipGraphNode_t nodes[3] = {nullptr, nullptr, nullptr};
+    int32_t steps_launched = 0;
+    // captured rounds, valid for graph_args / graph_grid
+    std::vector<RoundGraph> rounds;
     Launch graph_args{};
-    dim3 graph_grid[3];
+    unsigned graph_grid[4] = {0, 0, 0, 0};
     size_t graph_smem = 0;
-    bool graph_valid = false;
 };
 
 struct rac_net {
@@ -206,6 +215,7 @@ struct rac_net {
     std::vector<int32_t> h_row_ptr, h_deg, h_gptr;
     int32_t *row_ptr = nullptr, *nbr = nullptr, *deg = nullptr, *arc_src = nullptr;
     int32_t *gptr = nullptr, *nbrp = nullptr, *src_p = nullptr;   // 64-arc group layout
+    int32_t *gown = nullptr;                                      // owner variable of each group
     int64_t groups = 0;
     uint64_t *rel = nullptr;   // [m][d] constraint rows, kept for lazily packed layouts
     PathData bits, i8;
@@ -229,30 +239,34 @@ struct rac_group {
     std::vector<int64_t> h_off;
     Runner run;
     rac_stats last{};
-    int64_t total_vars = 0, total_items = 0, rel_bytes = 0, max_n = 0;
+    int64_t total_vars = 0, total_items = 0, rel_bytes = 0, max_n = 0, max_nd = 0;
     bool pending = false;
 };
 
 static int32_t round_up(int32_t v, int32_t m) { return (v + m - 1) / m * m; }
 
+static void drop_graphs(Runner &r) {
+    for (RoundGraph &g : r.rounds) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    r.rounds.clear();
+}
+
 static void release_runner(Runner &r) {
-    if (r.exec) (void)hipGraphExecDestroy(r.exec);
-    if (r.graph) (void)hipGraphDestroy(r.graph);
-    r.exec = nullptr;
-    r.graph = nullptr;
-    r.graph_valid = false;
+    drop_graphs(r);
     dfree(r.ws.dom[0]);
     dfree(r.ws.dom[1]);
     dfree(r.ws.chg[0]);
     dfree(r.ws.chg[1]);
     dfree(r.ws.failacc);
-    dfree(r.ws.xcnt);
     dfree(r.ws.ctrl);
-    dfree(r.ws.lanes);
-    dfree(r.ws.global);
+    dfree(r.ws.plan);
+    dfree(r.ws.act);
+    dfree(r.ws.act_off);
+    dfree(r.hist);
     dfree(r.prob_net);
     dfree(r.prob_off);
-    dfree(r.item_off);
     r.tables_key = -1;
     dfree(r.din);
     dfree(r.dout);
@@ -261,11 +275,16 @@ static void release_runner(Runner &r) {
     dfree(r.rc);
     dfree(r.checks);
     dfree(r.changed);
+    if (r.h_nact) (void)hipHostFree(r.h_nact);
+    r.h_nact = nullptr;
     if (r.ev0) (void)hipEventDestroy(r.ev0);
     if (r.ev1) (void)hipEventDestroy(r.ev1);
-    if (r.evk0) (void)hipEventDestroy(r.evk0);
-    if (r.evk1) (void)hipEventDestroy(r.evk1);
-    r.ev0 = r.ev1 = r.evk0 = r.evk1 = nullptr;
+    if (r.ev_round) (void)hipEventDestroy(r.ev_round);
+    r.ev0 = r.ev1 = r.ev_round = nullptr;
+    for (hipEvent_t &e : r.kev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
     r.cap_probs = 0;
     r.cap_vars = 0;
 }
@@ -278,13 +297,13 @@ static int ensure_runner(Runner &r, int32_t nprob, int64_t nvars) {
     RAC_TRY(dalloc(&r.ws.chg[0], nvars));
     RAC_TRY(dalloc(&r.ws.chg[1], nvars));
     RAC_TRY(dalloc(&r.ws.failacc, nvars));
-    RAC_TRY(dalloc(&r.ws.xcnt, nvars));
     RAC_TRY(dalloc(&r.ws.ctrl, nprob));
-    RAC_TRY(dalloc(&r.ws.lanes, (size_t)std::max<int32_t>(nprob, 256)));
-    RAC_TRY(dalloc(&r.ws.global, 1));
+    RAC_TRY(dalloc(&r.ws.plan, 1));
+    RAC_TRY(dalloc(&r.ws.act, nprob));
+    RAC_TRY(dalloc(&r.ws.act_off, (size_t)nprob + 1));
+    RAC_TRY(dalloc(&r.hist, kHist));
     RAC_TRY(dalloc(&r.prob_net, nprob));
     RAC_TRY(dalloc(&r.prob_off, (size_t)nprob + 1));
-    RAC_TRY(dalloc(&r.item_off, (size_t)nprob + 1));
     RAC_TRY(dalloc(&r.din, nvars));
     RAC_TRY(dalloc(&r.dout, nvars));
     RAC_TRY(dalloc(&r.iters, nprob));
@@ -292,10 +311,11 @@ static int ensure_runner(Runner &r, int32_t nprob, int64_t nvars) {
     RAC_TRY(dalloc(&r.rc, 1));
     RAC_TRY(dalloc(&r.checks, nprob));
     RAC_TRY(dalloc(&r.changed, nvars));
+    HIP_TRY(hipHostMalloc((void **)&r.h_nact, 4, hipHostMallocDefault));
     HIP_TRY(hipEventCreate(&r.ev0));
     HIP_TRY(hipEventCreate(&r.ev1));
-    HIP_TRY(hipEventCreate(&r.evk0));
-    HIP_TRY(hipEventCreate(&r.evk1));
+    HIP_TRY(hipEventCreateWithFlags(&r.ev_round, hipEventDisableTiming));
+    for (hipEvent_t &e : r.kev) HIP_TRY(hipEventCreate(&e));
     r.cap_probs = nprob;
     r.cap_vars = nvars;
     return RAC_OK;
@@ -328,6 +348,7 @@ extern "C" void rac_destroy(rac_net *net) {
     dfree(net->arc_src);
     dfree(net->gptr);
     dfree(net->nbrp);
+    dfree(net->gown);
     dfree(net->src_p);
     dfree(net->rel);
     if (net->stream) (void)hipStreamDestroy(net->stream);
@@ -354,7 +375,7 @@ static int make_items(rac_net *net, PathData &pd, int32_t target) {
     const int32_t n = net->n;
     const std::vector<int32_t> &rp = groups ? net->h_gptr : net->h_row_ptr;
     const int64_t per_var = 64;   // accounts for the domain read/write of a variable
-    const int32_t max_vars = 256;
+    const int32_t max_vars = groups ? kItemVars : 256;   // bit rows: one variable per lane
     int32_t xb = 0;
     int64_t acc = 0;
     auto flush = [&](int32_t xe) {
@@ -456,6 +477,7 @@ static int ensure_path(rac_net *net, int32_t path, int32_t item_bytes) {
         pd.desc.nbr = net->nbr;
         pd.desc.gptr = net->gptr;
         pd.desc.nbrp = net->nbrp;
+        pd.desc.gown = net->gown;
         pd.desc.deg = net->deg;
         pd.desc.rows = pd.rows;
         pd.desc.n = net->n;
@@ -555,8 +577,17 @@ static int create_common(int32_t n, int32_t d, int64_t m, const int32_t *edges,
                 srcp[(size_t)(pb + j - net->h_row_ptr[x])] = src[(size_t)j];
             }
         }
+        std::vector<int32_t> gown((size_t)net->groups);
+        for (int32_t x = 0; x < n; ++x)
+            for (int32_t g = net->h_gptr[x]; g < net->h_gptr[x + 1]; ++g) gown[(size_t)g] = x;
         if ((rc = dalloc(&net->gptr, (size_t)n + 1))) break;
         if ((rc = dalloc(&net->nbrp, nbrp.size()))) break;
+        if ((rc = dalloc(&net->gown, gown.size()))) break;
+        if (!gown.empty() &&
+            hipMemcpy(net->gown, gown.data(), gown.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+            rc = set_error(RAC_EHIP, "hipMemcpy of the group owners failed");
+            break;
+        }
         if ((rc = dalloc(&net->src_p, srcp.size()))) break;
         if (hipMemcpy(net->gptr, net->h_gptr.data(), ((size_t)n + 1) * 4, hipMemcpyHostToDevice) != hipSuccess ||
             (!nbrp.empty() && hipMemcpy(net->nbrp, nbrp.data(), nbrp.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
@@ -652,12 +683,6 @@ extern "C" int rac_net_info(const rac_net *net, int32_t *n, int32_t *d, int64_t 
 // launching
 // ---------------------------------------------------------------------------
 
-static int spin_limit() {
-    const char *s = getenv("RAC_SPIN_LIMIT");
-    if (s && atoi(s) > 0) return atoi(s);
-    return 4000000;
-}
-
 static dim3 grid_init(int64_t nvars) {
     int64_t b = (nvars + 255) / 256;
     if (b > 4096) b = 4096;
@@ -665,77 +690,159 @@ static dim3 grid_init(int64_t nvars) {
     return dim3((unsigned)b);
 }
 
-// Enqueues init + persistent sweep + finish on `stream`.
-static int launch_fixpoint(Runner &r, int device, hipStream_t stream, const Launch &L,
-                           int64_t total_items, bool use_graph, bool profile = false) {
-    const size_t smem = stage_bytes(L.stage_vars);
-    int64_t g = 0;
-    RAC_TRY(sweep_slots(device, smem, &g));
-    if (total_items < g) g = total_items;
-    if (g < 1) g = 1;
-    if (getenv("RAC_DEBUG"))
-        fprintf(stderr, "[rac] sweep grid=%lld items=%lld lds=%zu stage_vars=%d lanes/prob=%d nprob=%d\n",
-                (long long)g, (long long)total_items, smem, L.stage_vars, L.lanes_per_prob, L.nprob);
-    dim3 grids[3] = {grid_init(r.cap_vars), dim3((unsigned)g), grid_init(r.cap_vars)};
-    const void *funcs[3] = {(const void *)init_kernel, (const void *)sweep_kernel,
-                            (const void *)finish_kernel};
-    r.profiled = profile;
-    if (!use_graph || profile) {
-        HIP_TRY(hipEventRecord(r.ev0, stream));
-        hipLaunchKernelGGL(init_kernel, grids[0], dim3(256), 0, stream, L);
-        if (profile) HIP_TRY(hipEventRecord(r.evk0, stream));
-        hipLaunchKernelGGL(sweep_kernel, grids[1], dim3(kWave), smem, stream, L);
-        if (profile) HIP_TRY(hipEventRecord(r.evk1, stream));
-        hipLaunchKernelGGL(finish_kernel, grids[2], dim3(256), 0, stream, L);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipEventRecord(r.ev1, stream));
-        return RAC_OK;
-    }
-    Launch args = L;
-    void *params[1] = {&args};
-    hipKernelNodeParams kp[3];
-    for (int i = 0; i < 3; ++i) {
-        memset(&kp[i], 0, sizeof(kp[i]));
-        kp[i].func = const_cast<void *>(funcs[i]);
-        kp[i].gridDim = grids[i];
-        kp[i].blockDim = dim3(i == 1 ? kWave : 256);
-        kp[i].sharedMemBytes = i == 1 ? (unsigned)smem : 0u;
-        kp[i].kernelParams = params;
-        kp[i].extra = nullptr;
-    }
-    const bool same_grid = r.graph_valid && r.graph_grid[0].x == grids[0].x &&
-                           r.graph_grid[1].x == grids[1].x && r.graph_grid[2].x == grids[2].x &&
-                           r.graph_smem == smem;
-    if (!same_grid) {
-        if (r.exec) (void)hipGraphExecDestroy(r.exec);
-        if (r.graph) (void)hipGraphDestroy(r.graph);
-        r.exec = nullptr;
-        r.graph = nullptr;
-        r.graph_valid = false;
-        HIP_TRY(hipGraphCreate(&r.graph, 0));
-        HIP_TRY(hipGraphAddKernelNode(&r.nodes[0], r.graph, nullptr, 0, &kp[0]));
-        HIP_TRY(hipGraphAddKernelNode(&r.nodes[1], r.graph, &r.nodes[0], 1, &kp[1]));
-        HIP_TRY(hipGraphAddKernelNode(&r.nodes[2], r.graph, &r.nodes[1], 1, &kp[2]));
-        HIP_TRY(hipGraphInstantiate(&r.exec, r.graph, nullptr, nullptr, 0));
-        for (int i = 0; i < 3; ++i) r.graph_grid[i] = grids[i];
-        r.graph_smem = smem;
-        r.graph_args = args;
-        r.graph_valid = true;
-    } else if (memcmp(&r.graph_args, &args, sizeof(Launch)) != 0) {
-        for (int i = 0; i < 3; ++i) HIP_TRY(hipGraphExecKernelNodeSetParams(r.exec, r.nodes[i], &kp[i]));
-        r.graph_args = args;
-    }
-    HIP_TRY(hipEventRecord(r.ev0, stream));
-    HIP_TRY(hipGraphLaunch(r.exec, stream));
-    HIP_TRY(hipEventRecord(r.ev1, stream));
+// Steps per round: 4, 8, 16, 32, then 64.
+static int32_t round_steps(int round) { return round >= 4 ? 64 : (4 << round); }
+static int32_t round_first_step(int round) {
+    int32_t k = 1;
+    for (int i = 0; i < round; ++i) k += round_steps(i);
+    return k;
+}
+
+struct StepGrids {
+    dim3 init, revise, update;
+    size_t smem;
+};
+
+// Kernel node of a round graph, chained after `prev` (if any).
+static int add_node(hipGraph_t g, hipGraphNode_t *prev, const void *func, dim3 grid, dim3 block,
+                    size_t smem, void **params) {
+    hipKernelNodeParams kp;
+    memset(&kp, 0, sizeof(kp));
+    kp.func = const_cast<void *>(func);
+    kp.gridDim = grid;
+    kp.blockDim = block;
+    kp.sharedMemBytes = (unsigned)smem;
+    kp.kernelParams = params;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    HIP_TRY(hipGraphAddKernelNode(&node, g, *prev ? prev : nullptr, *prev ? 1 : 0, &kp));
+    *prev = node;
     return RAC_OK;
 }
 
-// Lane slots per problem: up to 64, with at most 256 lanes over all problems.
-static int32_t lanes_per_problem(int32_t nprob) {
-    int32_t lpp = 64;
-    while (lpp > 1 && (int64_t)lpp * nprob > 256) lpp >>= 1;
-    return lpp;
+// Round `round` as a graph: (round 0: init and the plan of step 1, then) for
+// each of its steps k: revise(k), update(k), plan(k+1).
+static int build_round(Runner &r, int round, const Launch &L, const StepGrids &sg) {
+    RoundGraph rg;
+    HIP_TRY(hipGraphCreate(&rg.graph, 0));
+    Launch args = L;
+    hipGraphNode_t prev = nullptr;
+    int32_t one = 1;
+    if (round == 0) {
+        void *pi[1] = {&args};
+        RAC_TRY(add_node(rg.graph, &prev, (const void *)init_kernel, sg.init, dim3(256), 0, pi));
+        void *pp[2] = {&args, &one};
+        RAC_TRY(add_node(rg.graph, &prev, (const void *)plan_kernel, dim3(1), dim3(1024), 0, pp));
+    }
+    const int32_t k0 = round_first_step(round), K = round_steps(round);
+    std::vector<int32_t> ks((size_t)K + 1);
+    for (int32_t i = 0; i <= K; ++i) ks[(size_t)i] = k0 + i;
+    for (int32_t i = 0; i < K; ++i) {
+        void *pk[2] = {&args, &ks[(size_t)i]};
+        void *pn[2] = {&args, &ks[(size_t)i + 1]};
+        RAC_TRY(add_node(rg.graph, &prev, (const void *)revise_kernel, sg.revise, dim3(kWave),
+                         sg.smem, pk));
+        RAC_TRY(add_node(rg.graph, &prev, (const void *)update_kernel, sg.update, dim3(256), 0, pk));
+        RAC_TRY(add_node(rg.graph, &prev, (const void *)plan_kernel, dim3(1), dim3(1024), 0, pn));
+    }
+    HIP_TRY(hipGraphInstantiate(&rg.exec, rg.graph, nullptr, nullptr, 0));
+    if ((int)r.rounds.size() <= round) r.rounds.resize((size_t)round + 1);
+    r.rounds[(size_t)round] = rg;
+    return RAC_OK;
+}
+
+// Enqueues a whole enforcement on `stream`: init, then rounds of steps until
+// the plan reports that no problem runs the next step (the host reads one
+// counter per round), then finish. `nv` variables in all; `kcap` bounds the
+// steps of every problem.
+static int launch_fixpoint(Runner &r, int device, hipStream_t stream, const Launch &L, int64_t nv,
+                           int64_t total_items, int32_t kcap, bool use_graph, bool profile = false) {
+    StepGrids sg;
+    sg.smem = stage_bytes(L.stage_vars);
+    int64_t g = 0;
+    RAC_TRY(sweep_slots(device, sg.smem, &g));
+    if (total_items < g) g = total_items;
+    if (g < 1) g = 1;
+    sg.init = grid_init(nv);
+    sg.revise = dim3((unsigned)g);
+    const int64_t ub = std::min<int64_t>(4096, std::max<int64_t>(1, (nv + 255) / 256));
+    sg.update = dim3((unsigned)ub);
+    if (getenv("RAC_DEBUG"))
+        fprintf(stderr, "[rac] revise grid=%lld items=%lld lds=%zu stage_vars=%d nprob=%d\n",
+                (long long)g, (long long)total_items, sg.smem, L.stage_vars, L.nprob);
+    r.profiled = profile;
+    const bool graphs = use_graph && !profile;
+    if (graphs) {
+        const bool same = r.graph_grid[0] == sg.init.x && r.graph_grid[1] == sg.revise.x &&
+                          r.graph_grid[2] == sg.update.x && r.graph_smem == sg.smem &&
+                          memcmp(&r.graph_args, &L, sizeof(Launch)) == 0;
+        if (!same) {
+            drop_graphs(r);
+            r.graph_args = L;
+            r.graph_grid[0] = sg.init.x;
+            r.graph_grid[1] = sg.revise.x;
+            r.graph_grid[2] = sg.update.x;
+            r.graph_smem = sg.smem;
+        }
+    }
+    HIP_TRY(hipEventRecord(r.ev0, stream));
+    int32_t k = 0;   // steps enqueued
+    for (int round = 0;; ++round) {
+        const int32_t K = round_steps(round);
+        if (graphs) {
+            if ((int)r.rounds.size() <= round || !r.rounds[(size_t)round].exec)
+                RAC_TRY(build_round(r, round, L, sg));
+            HIP_TRY(hipGraphLaunch(r.rounds[(size_t)round].exec, stream));
+        } else {
+            if (round == 0) {
+                hipLaunchKernelGGL(init_kernel, sg.init, dim3(256), 0, stream, L);
+                hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, stream, L, 1);
+            }
+            for (int32_t i = 1; i <= K; ++i) {
+                const int32_t kk = k + i;
+                const bool timed = profile && kk <= kProfSteps;
+                if (timed) HIP_TRY(hipEventRecord(r.kev[2 * (kk - 1)], stream));
+                hipLaunchKernelGGL(revise_kernel, sg.revise, dim3(kWave), sg.smem, stream, L, kk);
+                if (timed) HIP_TRY(hipEventRecord(r.kev[2 * (kk - 1) + 1], stream));
+                hipLaunchKernelGGL(update_kernel, sg.update, dim3(256), 0, stream, L, kk);
+                hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, stream, L, kk + 1);
+                if (profile && kk + 1 < kHist)
+                    HIP_TRY(hipMemcpyAsync(r.hist + kk + 1, &L.ws.plan->nact, 4,
+                                           hipMemcpyDeviceToDevice, stream));
+            }
+            HIP_TRY(hipGetLastError());
+        }
+        k += K;
+        HIP_TRY(hipMemcpyAsync(r.h_nact, &L.ws.plan->nact, 4, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipEventRecord(r.ev_round, stream));
+        HIP_TRY(hipEventSynchronize(r.ev_round));
+        if (*r.h_nact == 0 || k >= kcap) break;
+    }
+    hipLaunchKernelGGL(finish_kernel, sg.init, dim3(256), 0, stream, L);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(r.ev1, stream));
+    r.steps_launched = k;
+    return RAC_OK;
+}
+
+// Profile mode: summed duration of the revise launches of steps that some
+// problem executed, and their number.
+static void revise_timing(Runner &r, double *ms, int64_t *launches) {
+    *ms = 0.0;
+    *launches = 0;
+    if (!r.profiled) return;
+    int32_t h[kHist] = {0};
+    const int32_t n = std::min<int32_t>(r.steps_launched, kProfSteps);
+    if (hipMemcpy(h, r.hist, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return;
+    h[1] = 1;   // step 1 always runs
+    for (int32_t k = 1; k <= n; ++k) {
+        if (h[k] <= 0) continue;
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.kev[2 * (k - 1)], r.kev[2 * (k - 1) + 1]) == hipSuccess) {
+            *ms += t;
+            ++*launches;
+        }
+    }
 }
 
 static Launch base_launch(Runner &r, int32_t nprob, const rac_options &o) {
@@ -743,21 +850,23 @@ static Launch base_launch(Runner &r, int32_t nprob, const rac_options &o) {
     memset(&L, 0, sizeof(L));
     L.prob_net = r.prob_net;
     L.prob_off = r.prob_off;
-    L.item_off = r.item_off;
     L.nprob = nprob;
     L.mode = o.mode;
     L.max_sweeps = o.max_sweeps;
-    L.spin_limit = spin_limit();
-    L.lanes_per_prob = lanes_per_problem(nprob);
     L.ws = r.ws;
     L.rc_out = r.rc;
     L.checks_out = r.checks;
-    L.checks1 = -1;
+    L.arcs1 = 0;
     return L;
 }
 
+// Step bound over the nets of a launch.
+static int32_t step_cap(const rac_options &o, int64_t max_nd) {
+    if (o.max_sweeps > 0) return o.max_sweeps;
+    return (int32_t)std::min<int64_t>(max_nd + 1, INT32_MAX - 128);
+}
+
 static int rc_from_device(int32_t dev_rc) {
-    if (dev_rc & 2) return set_error(RAC_ETIMEOUT, "device scheduler wait expired");
     if (dev_rc & 1) return set_error(RAC_ENOTCONVERGED, "max_sweeps reached before the fixpoint");
     return RAC_OK;
 }
@@ -778,15 +887,10 @@ static int prepare_net_runner(rac_net *net, int32_t B, PathData &pd) {
     const int64_t key = (int64_t)B * 2147483648LL + pd.nitems;
     if (r.tables_key == key) return RAC_OK;
     std::vector<int32_t> pn((size_t)B, 0);
-    std::vector<int64_t> off((size_t)B + 1), ioff((size_t)B + 1);
-    for (int32_t s = 0; s <= B; ++s) {
-        off[(size_t)s] = (int64_t)s * net->n;
-        ioff[(size_t)s] = (int64_t)s * pd.nitems;
-    }
+    std::vector<int64_t> off((size_t)B + 1);
+    for (int32_t s = 0; s <= B; ++s) off[(size_t)s] = (int64_t)s * net->n;
     HIP_TRY(hipMemcpyAsync(r.prob_net, pn.data(), (size_t)B * 4, hipMemcpyHostToDevice, net->stream));
     HIP_TRY(hipMemcpyAsync(r.prob_off, off.data(), ((size_t)B + 1) * 8, hipMemcpyHostToDevice,
-                           net->stream));
-    HIP_TRY(hipMemcpyAsync(r.item_off, ioff.data(), ((size_t)B + 1) * 8, hipMemcpyHostToDevice,
                            net->stream));
     HIP_TRY(hipStreamSynchronize(net->stream));
     r.tables_key = key;
@@ -821,9 +925,9 @@ static int pick_path(const rac_net *net, int32_t B, int32_t requested) {
     return mfma_auto_choice(net->d, net->n, net->arcs, B) ? RAC_PATH_MFMA : RAC_PATH_BITS;
 }
 
-// Bit / int8 path for B states already in r.din. Synchronous when `sync`.
+// Bit / int8 path for B states already in r.din (host waits between rounds).
 static int run_states(rac_net *net, int32_t B, int32_t path, const uint8_t *d_changed,
-                      long long checks1, bool sync) {
+                      long long arcs1) {
     PathData &pd = path == RAC_PATH_INT8 ? net->i8 : net->bits;
     RAC_TRY(ensure_path(net, path, call_target(net, B)));
     Runner &r = net->run;
@@ -835,10 +939,10 @@ static int run_states(rac_net *net, int32_t B, int32_t path, const uint8_t *d_ch
     L.iters_out = r.iters;
     L.status_out = r.status;
     L.changed0 = d_changed;
-    L.checks1 = checks1;
-    RAC_TRY(launch_fixpoint(r, net->device, net->stream, L, (int64_t)pd.nitems * B,
+    L.arcs1 = arcs1;
+    RAC_TRY(launch_fixpoint(r, net->device, net->stream, L, (int64_t)B * net->n,
+                            (int64_t)pd.nitems * B, step_cap(net->opt, (int64_t)net->n * net->d),
                             net->opt.use_graph != 0, net->opt.profile != 0));
-    (void)sync;
     return RAC_OK;
 }
 
@@ -859,12 +963,7 @@ static int collect_bits(rac_net *net, int32_t B, int32_t path, uint64_t *dom, in
     (void)hipEventElapsedTime(&ms, r.ev0, r.ev1);
     fill_stats_bits(net->last, hc, hi, path, pd, ms);
     net->last.relation_bytes = (int64_t)pd.rows_bytes;
-    if (r.profiled) {
-        float kms = 0.f;
-        (void)hipEventElapsedTime(&kms, r.evk0, r.evk1);
-        net->last.kernel_ms = kms;
-        net->last.kernel_launches = 1;
-    }
+    revise_timing(r, &net->last.kernel_ms, &net->last.kernel_launches);
     if (iters) memcpy(iters, hi.data(), (size_t)B * 4);
     if (status) memcpy(status, hs.data(), (size_t)B * 4);
     return rc_from_device(hrc);
@@ -883,7 +982,7 @@ extern "C" int rac_enforce(rac_net *net, uint64_t *dom, const int32_t *changed, 
     Runner &r = net->run;
     HIP_TRY(hipMemcpyAsync(r.din, dom, (size_t)net->n * 8, hipMemcpyHostToDevice, net->stream));
     const uint8_t *d_changed = nullptr;
-    long long checks1 = -1;
+    long long arcs1 = 0;
     if (changed) {
         std::vector<uint8_t> mask((size_t)net->n, 0);
         long long degs = 0;
@@ -897,9 +996,9 @@ extern "C" int rac_enforce(rac_net *net, uint64_t *dom, const int32_t *changed, 
                                net->stream));
         HIP_TRY(hipStreamSynchronize(net->stream));
         d_changed = r.changed;
-        checks1 = degs * net->d * net->d;
+        arcs1 = degs;
     }
-    RAC_TRY(run_states(net, 1, path, d_changed, checks1, true));
+    RAC_TRY(run_states(net, 1, path, d_changed, arcs1));
     return collect_bits(net, 1, path, dom, iters, status);
 }
 
@@ -936,10 +1035,11 @@ static int run_mfma(rac_net *net, int32_t B, const uint64_t *d_in, uint64_t *d_o
         L.iters_out = r.iters;
         L.status_out = r.status;
         L.changed0 = r.changed;
-        L.checks1 = 0;   // the matrix-core finaliser already counted step k+1
+        L.arcs1 = 0;   // the matrix-core finaliser already counted step k+1
         const int32_t maxs = net->opt.max_sweeps > 0 ? net->opt.max_sweeps : net->n * net->d + 1;
         L.max_sweeps = maxs - k;
-        RAC_TRY(launch_fixpoint(r, net->device, s, L, (int64_t)pd.nitems * P, false, false));
+        RAC_TRY(launch_fixpoint(r, net->device, s, L, (int64_t)P * net->n, (int64_t)pd.nitems * P,
+                                maxs - k, true, false));
         RAC_TRY(mfma_merge(net->mfma, k, r.dout, r.iters, r.status, r.checks, r.rc, s));
     }
     RAC_TRY(mfma_finish(net->mfma, d_out, d_it, d_st, s));
@@ -983,7 +1083,7 @@ extern "C" int rac_enforce_batch(rac_net *net, int32_t B, uint64_t *dom, int32_t
     RAC_TRY(prepare_net_runner(net, B, path == RAC_PATH_INT8 ? net->i8 : net->bits));
     HIP_TRY(hipMemcpyAsync(net->run.din, dom, (size_t)B * net->n * 8, hipMemcpyHostToDevice,
                            net->stream));
-    RAC_TRY(run_states(net, B, path, nullptr, -1, true));
+    RAC_TRY(run_states(net, B, path, nullptr, 0));
     return collect_bits(net, B, path, dom, iters, status);
 }
 
@@ -1017,7 +1117,8 @@ extern "C" int rac_enforce_batch_device(rac_net *net, int32_t B, const uint64_t 
     L.dout = d_dom_out;
     L.iters_out = d_iters;
     L.status_out = d_status;
-    RAC_TRY(launch_fixpoint(r, net->device, s, L, (int64_t)pd.nitems * B, net->opt.use_graph != 0,
+    RAC_TRY(launch_fixpoint(r, net->device, s, L, (int64_t)B * net->n, (int64_t)pd.nitems * B,
+                            step_cap(net->opt, (int64_t)net->n * net->d), net->opt.use_graph != 0,
                             net->opt.profile != 0));
     net->pending = true;
     net->last.path = path;
@@ -1038,12 +1139,7 @@ extern "C" int rac_sync_status(rac_net *net) {
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, net->run.ev0, net->run.ev1);
     net->last.device_ms = ms;
-    if (net->run.profiled) {
-        float kms = 0.f;
-        (void)hipEventElapsedTime(&kms, net->run.evk0, net->run.evk1);
-        net->last.kernel_ms = kms;
-        net->last.kernel_launches = 1;
-    }
+    revise_timing(net->run, &net->last.kernel_ms, &net->last.kernel_launches);
     return rc_from_device(hrc);
 }
 
@@ -1129,13 +1225,11 @@ extern "C" int rac_group_create(int32_t k, rac_net *const *nets, const rac_optio
         }
         if ((rc = ensure_runner(g->run, k, g->total_vars))) break;
         std::vector<int32_t> pn((size_t)k);
-        std::vector<int64_t> ioff((size_t)k + 1, 0);
         for (int32_t i = 0; i < k; ++i) {
             pn[(size_t)i] = i;
-            ioff[(size_t)i + 1] = ioff[(size_t)i] + descs[(size_t)i].nitems;
+            g->max_nd = std::max<int64_t>(g->max_nd, (int64_t)nets[i]->n * nets[i]->d);
         }
         if (hipMemcpy(g->run.prob_net, pn.data(), (size_t)k * 4, hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(g->run.item_off, ioff.data(), ((size_t)k + 1) * 8, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(g->run.prob_off, g->h_off.data(), ((size_t)k + 1) * 8, hipMemcpyHostToDevice) != hipSuccess) {
             rc = set_error(RAC_EHIP, "hipMemcpy of problem tables");
             break;
@@ -1174,7 +1268,8 @@ extern "C" int rac_group_enforce(rac_group *g, uint64_t *const *dom, int32_t *it
     }
     HIP_TRY(hipMemcpyAsync(r.din, h.data(), h.size() * 8, hipMemcpyHostToDevice, g->stream));
     Launch L = group_launch(g, r.din, r.dout, r.iters, r.status);
-    RAC_TRY(launch_fixpoint(r, g->device, g->stream, L, g->total_items, g->opt.use_graph != 0,
+    RAC_TRY(launch_fixpoint(r, g->device, g->stream, L, g->total_vars, g->total_items,
+                            step_cap(g->opt, g->max_nd), g->opt.use_graph != 0,
                             g->opt.profile != 0));
     std::vector<int32_t> hi((size_t)g->k), hs((size_t)g->k);
     std::vector<long long> hc((size_t)g->k);
@@ -1199,12 +1294,7 @@ extern "C" int rac_group_enforce(rac_group *g, uint64_t *const *dom, int32_t *it
     g->last.device_ms = ms;
     g->last.path = RAC_PATH_BITS;
     g->last.relation_bytes = g->rel_bytes;
-    if (r.profiled) {
-        float kms = 0.f;
-        (void)hipEventElapsedTime(&kms, r.evk0, r.evk1);
-        g->last.kernel_ms = kms;
-        g->last.kernel_launches = 1;
-    }
+    revise_timing(r, &g->last.kernel_ms, &g->last.kernel_launches);
     return rc_from_device(hrc);
 }
 
@@ -1217,8 +1307,8 @@ extern "C" int rac_group_enforce_device(rac_group *g, uint64_t *d_dom, int32_t *
         if (prc != RAC_OK) return prc;
     }
     Launch L = group_launch(g, d_dom, d_dom, d_iters, d_status);
-    RAC_TRY(launch_fixpoint(g->run, g->device, (hipStream_t)stream, L, g->total_items,
-                            g->opt.use_graph != 0));
+    RAC_TRY(launch_fixpoint(g->run, g->device, (hipStream_t)stream, L, g->total_vars,
+                            g->total_items, step_cap(g->opt, g->max_nd), g->opt.use_graph != 0));
     g->pending = true;
     return RAC_OK;
 }

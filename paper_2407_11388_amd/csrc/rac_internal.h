@@ -27,6 +27,16 @@ enum RowKind : int32_t {
 
 constexpr int kGroup = 64;        // arcs per group of the bit-row layout
 
+// Bit-row work items hold at most kItemVars whole variables (one per lane when
+// the item's variables are updated). Steps that re-examine only the arcs into
+// changed variables look at kSparseGroups groups at a time.
+constexpr int kItemVars = 64;
+constexpr int kSparseGroups = 16;
+// Per-wave LDS scratch in front of the staged domains, in 8-byte words: the
+// failing values of the item's variables (kItemVars words) and the compacted
+// active arcs of a sparse batch (kSparseGroups * 64 16-bit codes).
+constexpr int kScratchWords = kItemVars + kSparseGroups * kGroup / 4;
+
 // One network as seen by the sweep kernel (device memory, read-only).
 // Arcs leaving x: row_ptr[x] .. row_ptr[x+1]-1 (to nbr[j]); in the padded
 // group layout, groups gptr[x] .. gptr[x+1]-1 with nbrp[g*64 + l] the
@@ -36,6 +46,7 @@ struct NetDesc {
     const int32_t *nbr;       // [arcs]
     const int32_t *gptr;      // [n+1] group offsets (bit rows)
     const int32_t *nbrp;      // [groups*64] (bit rows)
+    const int32_t *gown;      // [groups] the variable group g belongs to (bit rows)
     const int32_t *deg;       // [n]
     const void *rows;
     const int4 *items;        // [nitems] {x_begin, x_end, unit_begin, unit_end}; units are
@@ -46,57 +57,43 @@ struct NetDesc {
     int64_t arcs;
 };
 
-// Fixpoint control block of one problem (one domain state of one network).
-// A step's work items are split into `nlanes` contiguous lanes, each with its
-// own claim ticket and completion counter on its own cache line, so that no
-// single address takes every item's atomics.
+// Control words of one problem (one domain state of one network).
 struct Ctrl {
-    unsigned long long degsum[2];  // sum of deg(x) over variables changed in steps of that parity
-    long long checks;              // support checks so far (d*d per re-examined arc)
-    int32_t lanes_done;            // lanes whose items all completed in the current step
-    int32_t nlanes;
-    int32_t last_change;           // last step that removed a value (0 = none yet)
-    int32_t wiped;                 // a domain is empty (domains only shrink: sticky)
-    int32_t done;                  // 1 once the problem has stopped
-    int32_t iters, status, rc;
-    int32_t pad[20];               // 128 bytes
+    long long arcs[3];      // arcs[k % 3]: arcs into variables step k changed = arcs that
+                            // step k+1 re-examines (arcs[0]: those of step 1)
+    long long checks;       // support checks so far (d*d per re-examined arc)
+    int32_t last_change;    // last step that removed a value (0 = none)
+    int32_t wipe_step;      // first step after which some domain was empty (0 = none)
+    int32_t pad[8];         // 64 bytes
 };
 
-struct Lane {
-    unsigned long long ticket;     // (step << 32) | next unclaimed item of the lane
-    int32_t finish;                // items of the lane completed in the current step
-    int32_t start, count;          // the lane's items: start .. start+count-1
-    int32_t pad[27];               // 128 bytes
-};
-
-struct Global {
-    int32_t active;   // problems not yet done
-    int32_t error;    // nonzero: a bounded wait expired; every workgroup leaves
-    int32_t pad[2];
+// The problems that execute the next step and the prefix sums of their item
+// counts (written by the plan kernel).
+struct Plan {
+    int32_t nact;
+    int32_t pad;
+    int64_t items;
 };
 
 // Device workspace of a set of problems; variable v of problem p lives at off[p] + v.
 struct Workspace {
-    uint64_t *dom[2];     // double buffer: sweep k reads dom[(k-1)&1], writes dom[k&1]
+    uint64_t *dom[2];     // double buffer: step k reads dom[(k-1)&1], writes dom[k&1]
     uint32_t *chg[2];     // chg[k&1][v] = 1 iff step k shrank dom(v); chg[0] starts as @changed
-    uint64_t *failacc;    // OR of the values failing on pieces of a split variable
-    int32_t *xcnt;        // pieces of a split variable finished in the current sweep
+    uint64_t *failacc;    // values found failing in the current step (OR), cleared by the update
     Ctrl *ctrl;           // [nprob]
-    Lane *lanes;          // [nprob * lanes_per_prob]
-    Global *global;
+    Plan *plan;           // [1]
+    int32_t *act;         // [nprob] problems of the next step
+    int64_t *act_off;     // [nprob + 1] their item prefix sums
 };
 
-// Everything one enforcement launch needs (passed by value).
+// Everything one enforcement needs (passed by value to every kernel).
 struct Launch {
     const NetDesc *nets;      // [nnet]
     const int32_t *prob_net;  // [nprob]
     const int64_t *prob_off;  // [nprob + 1]
-    const int64_t *item_off;  // [nprob + 1] prefix sums of the problems' item counts
     int32_t nprob;
     int32_t mode;             // RAC_RUN_TO_FIXPOINT / RAC_STOP_ON_WIPEOUT
     int32_t max_sweeps;       // 0: per network n*d + 1
-    int32_t spin_limit;       // bounded wait (polls) of an idle workgroup
-    int32_t lanes_per_prob;   // lane slots reserved per problem (a power of two <= 64)
     int32_t stage_vars;       // LDS staging capacity in variables (0: none)
     Workspace ws;
     const uint64_t *din;      // [prob_off[nprob]] initial domains
@@ -105,8 +102,8 @@ struct Launch {
     int32_t *status_out;      // [nprob] or null
     const uint8_t *changed0;  // [prob_off[nprob]] initial @changed flags, or null (= all)
     long long *checks_out;    // [nprob] or null
-    long long checks1;        // support checks of step 1 when changed0 is given (else 2m*d*d)
-    int32_t *rc_out;          // [1]: worst per-problem return code of the call
+    long long arcs1;          // with changed0: arcs step 1 re-examines, per problem
+    int32_t *rc_out;          // [1]: 1 if some problem reached max_sweeps unconverged
 };
 
 // Records a message for rac_last_error() and returns `code` (rac_host.hip).
@@ -114,7 +111,9 @@ int set_error(int code, const char *fmt, ...);
 
 // Kernel entry points (defined in sweep.hip), launched by rac_host.hip.
 __global__ void init_kernel(Launch L);
-__global__ void sweep_kernel(Launch L);
+__global__ void plan_kernel(Launch L, int k);
+__global__ void revise_kernel(Launch L, int k);
+__global__ void update_kernel(Launch L, int k);
 __global__ void finish_kernel(Launch L);
 __global__ void pack_bits_kernel(const uint64_t *rel, const int32_t *src_p, int64_t groups,
                                  int32_t d, int32_t qpa, int32_t kind, uint4 *out);

@@ -6,16 +6,17 @@
 // current dom(y) is allowed with a. Step k reads D^(k-1) from dom[(k-1)&1]
 // and writes D^(k) to dom[k&1], so steps are synchronous as Eq. (1) requires.
 //
-// Scheduling: one persistent launch runs every step of every problem (one
-// problem = one domain state of one network). A problem's step is cut into
-// work items (whole variables, or a piece of one high-degree variable). A
-// workgroup claims an item with one atomic on the problem's ticket word
-// (step << 32 | item). The workgroup that completes the last item of a step
-// finalises it: it reads the step's change / wipe-out flags and either
-// publishes the next step's ticket (release) or retires the problem. Item
-// claims are ordered after the previous step's completion by that ticket, so
-// no workgroup ever waits on another: idle workgroups only poll for new
-// tickets, with a bounded number of polls.
+// Scheduling: every step is three kernels. The plan kernel lists the problems
+// (one problem = one domain state of one network) still running at step k
+// and the prefix sums of their work items (whole variables, or a piece of one
+// high-degree variable). The revise kernel hands each workgroup one
+// contiguous range of those items; it ORs the values that lose their support
+// into a per-variable accumulator. The update kernel applies the accumulator
+// to D^(k-1), writes D^(k) and the @changed flags of step k, and records per
+// problem whether the step removed anything or emptied a domain. The host
+// enqueues the steps in rounds (captured HIP graphs of 4, 8, 16, ... steps)
+// and reads one counter per round: the number of problems still running. No
+// workgroup ever waits on another, and no counter is shared by work items.
 #include "rac_internal.h"
 #include "rac.h"
 
@@ -33,31 +34,6 @@ template <typename T> DEV const GLOBAL T *as_global(const T *p) {
     return (const GLOBAL T *)p;
 }
 
-template <typename T> DEV T ld_rlx(T *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T> DEV T ld_acq(T *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T> DEV void st_rlx(T *p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T> DEV void st_rel(T *p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T> DEV T add_ar(T *p, T v) {
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T> DEV T or_ar(T *p, T v) {
-    return __hip_atomic_fetch_or(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T> DEV T max_ar(T *p, T v) {
-    return __hip_atomic_fetch_max(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T> DEV T xchg_ar(T *p, T v) {
-    return __hip_atomic_exchange(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 DEV uint64_t wave_or64(uint64_t v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v |= __shfl_xor(v, o, kWave);
@@ -70,36 +46,26 @@ DEV uint64_t dmask_of(int d) { return d >= 64 ? ~0ull : ((1ull << d) - 1ull); }
 // copies of v 7 bits apart, so no two copies overlap and no carry occurs.
 DEV uint32_t spread4(uint32_t v) { return (v * 0x00204081u) & 0x01010101u; }
 
-constexpr int kUnroll = 4;
-
 // ---------------------------------------------------------------------------
-// Memory protocol. Data another workgroup wrote in this launch (domains of
-// steps >= 1, change flags, control words) is only ever read with agent-scope
-// relaxed atomics, which the hardware keeps coherent across the XCDs' L2
-// caches without cache-wide write-back or invalidation, and written the same
-// way. Before a wave signals that an item is complete it waits until its own
-// stores and atomics have been performed (vmcnt(0)). A claimer reads nothing
-// of a step before its claim atomic has returned that step's ticket. Step 1
-// reads D^(0), written by the previous kernel, with ordinary loads. Relation
-// rows, arc lists and work items are read-only during the launch.
+// Memory protocol. Within a kernel, D^(k-1), the @changed flags of step k-1
+// and the control words are read-only (they were written by earlier kernels
+// of the stream). The only data written by several workgroups of one kernel
+// are the failure accumulators (agent-scope atomic OR, read by the next
+// kernel) and a few per-problem words that every writer sets to the same
+// value (last step with a change, first step with a wipe-out) or adds to with
+// one atomic per workgroup.
 // ---------------------------------------------------------------------------
-
-DEV void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // Where a step reads D^(k-1) and the previous step's @changed set from.
-enum ViewKind { VIEW_PLAIN = 0, VIEW_LDS = 1, VIEW_COHERENT = 2 };
+enum ViewKind { VIEW_PLAIN = 0, VIEW_LDS = 1 };
 
 template <int VK>
 struct DomView {
     const uint64_t *dom;   // [n] (LDS or global)
     const uint32_t *chg;   // LDS: bit mask; global: flags [n]
-    DEV uint64_t get(int32_t y) const {
-        if (VK == VIEW_COHERENT) return ld_rlx(const_cast<uint64_t *>(dom + y));
-        return dom[y];
-    }
+    DEV uint64_t get(int32_t y) const { return dom[y]; }
     DEV bool changed(int32_t y) const {
         if (VK == VIEW_LDS) return (chg[y >> 5] >> (y & 31)) & 1u;
-        if (VK == VIEW_COHERENT) return ld_rlx(const_cast<uint32_t *>(chg + y)) != 0;
         return chg[y] != 0;
     }
 };
@@ -111,15 +77,37 @@ struct DomView {
 // with @changed = all variables).
 // ---------------------------------------------------------------------------
 
+// Per-wave LDS scratch of the bit-row revision.
+struct Scratch {
+    unsigned long long *failx;   // [kItemVars] values of variable xbase + i found failing
+    uint16_t *cmp;               // [kSparseGroups * 64] active arcs of a sparse batch:
+                                 // (group within the batch << 6) | arc within the group
+};
+
+DEV void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Position of this lane among the set lanes of m below it.
+DEV int lane_rank(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Records that the values f of the item's variable slot `own` lost their
+// support on some arc. Failures are rare, so the LDS atomic is seldom taken.
+DEV void note_fail(const Scratch &S, int32_t own, uint64_t f) {
+    if (f)
+        (void)__hip_atomic_fetch_or(S.failx + own, (unsigned long long)f, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Bit rows in 64-arc groups (lane = arc). A lane tests each row a of its arc
-// against dom(y) and records the rows without support; OR-ing those masks
-// over the lanes and groups gives the values that lose all support on some
-// arc. Work is cut into units of one group and C row quads (C divides qpa);
-// DEPTH units are kept in flight: unit t+DEPTH is issued right after unit t
-// is tested. In the first step every row is loaded (padding rows are zero),
-// so no load waits for a neighbour index and no load is predicated.
-// Rows of one 16-byte quad without support in dom(y), as bits 0..3 (uint32
-// rows) or 0..1 (uint64 rows).
+// against dom(y) and records the rows without support under the variable
+// owning the group. Rows of one 16-byte quad without support in dom(y), as
+// bits 0..3 (uint32 rows) or 0..1 (uint64 rows).
 template <bool WIDE>
 DEV uint32_t quad_fail(const u32x4 v, uint64_t dy) {
     if (WIDE) {
@@ -132,11 +120,17 @@ DEV uint32_t quad_fail(const u32x4 v, uint64_t dy) {
            ((v.z & d32) == 0 ? 4u : 0u) | ((v.w & d32) == 0 ? 8u : 0u);
 }
 
+// Every arc re-examined (the first step with @changed = all variables): the
+// groups g0 .. g1-1 are cut into units of one group and C row quads (C
+// divides qpa); DEPTH units are kept in flight: unit t+DEPTH is issued right
+// after unit t is tested. Every row is loaded (padding rows are zero), so no
+// load waits for a neighbour index and no load is predicated.
 template <int C>
 struct GroupUnit {
     u32x4 v[C];
     int32_t y;
     int32_t q0;
+    int32_t own;
     bool live;
 };
 
@@ -152,76 +146,155 @@ struct UnitCursor {
     }
 };
 
-template <bool ALL, int C, class DV>
+template <int C>
 DEV void load_unit(GroupUnit<C> &u, UnitCursor &cur, const GLOBAL u32x4 *__restrict__ rows,
-                   const GLOBAL int32_t *__restrict__ nbrp, const DV &D, int32_t qpa, int lane) {
+                   const GLOBAL int32_t *__restrict__ nbrp, const GLOBAL int32_t *__restrict__ gown,
+                   int32_t xbase, int32_t qpa, int lane) {
     u.live = cur.g < cur.g1;     // wave-uniform
     if (!u.live) return;
     u.y = nbrp[cur.g * kGroup + lane];
+    u.own = gown[cur.g] - xbase;
     u.q0 = cur.c * C;
     const GLOBAL u32x4 *base = rows + (cur.g * qpa + u.q0) * kGroup + lane;
-    if (ALL) {
 #pragma unroll
-        for (int q = 0; q < C; ++q) u.v[q] = base[q * kGroup];
-    } else {
-        if (u.y >= 0 && D.changed(u.y)) {
-#pragma unroll
-            for (int q = 0; q < C; ++q) u.v[q] = base[q * kGroup];
-        }
-    }
+    for (int q = 0; q < C; ++q) u.v[q] = base[q * kGroup];
     cur.next();
 }
 
-template <bool ALL, bool WIDE, int C, class DV>
-DEV uint64_t test_unit(const GroupUnit<C> &u, const DV &D) {
+template <bool WIDE, int C, class DV>
+DEV void test_unit(const GroupUnit<C> &u, const DV &D, const Scratch &S) {
     constexpr int RPQ = WIDE ? 2 : 4;
     static_assert(C * RPQ <= 32, "a unit covers at most 32 rows");
-    if (!u.live) return 0;
-    const bool valid = u.y >= 0 && (ALL || D.changed(u.y < 0 ? 0 : u.y));
+    if (!u.live) return;
+    const bool valid = u.y >= 0;
     const uint64_t dy = D.get(valid ? u.y : 0);
     uint32_t f = 0;
 #pragma unroll
     for (int q = 0; q < C; ++q) f |= quad_fail<WIDE>(u.v[q], dy) << (q * RPQ);
-    if (!valid) f = 0;
-    return (uint64_t)f << (u.q0 * RPQ);
+    if (valid) note_fail(S, u.own, (uint64_t)f << (u.q0 * RPQ));
 }
 
-template <bool ALL, bool WIDE, int C, int DEPTH, class DV>
-DEV uint64_t revise_groups(const GLOBAL u32x4 *__restrict__ rows,
-                           const GLOBAL int32_t *__restrict__ nbrp, const DV &D, int64_t g0,
-                           int64_t g1, int32_t qpa) {
+template <bool WIDE, int C, int DEPTH, class DV>
+DEV void revise_all(const GLOBAL u32x4 *__restrict__ rows, const GLOBAL int32_t *__restrict__ nbrp,
+                    const GLOBAL int32_t *__restrict__ gown, const DV &D, int64_t g0, int64_t g1,
+                    int32_t qpa, int32_t xbase, const Scratch &S) {
     const int lane = threadIdx.x & (kWave - 1);
     UnitCursor cur{g0, g1, 0, qpa / C};
     GroupUnit<C> u[DEPTH];
 #pragma unroll
-    for (int i = 0; i < DEPTH; ++i) load_unit<ALL, C>(u[i], cur, rows, nbrp, D, qpa, lane);
-    uint64_t fail = 0;
+    for (int i = 0; i < DEPTH; ++i) load_unit<C>(u[i], cur, rows, nbrp, gown, xbase, qpa, lane);
     while (u[0].live) {
 #pragma unroll
         for (int i = 0; i < DEPTH; ++i) {
-            fail |= test_unit<ALL, WIDE, C>(u[i], D);
-            load_unit<ALL, C>(u[i], cur, rows, nbrp, D, qpa, lane);
+            test_unit<WIDE, C>(u[i], D, S);
+            load_unit<C>(u[i], cur, rows, nbrp, gown, xbase, qpa, lane);
         }
     }
-    return wave_or64(fail);
 }
 
+// Only the arcs x->y with y in @changed re-examined (steps after the first,
+// Proposition 2). The groups are taken kSparseGroups at a time: one load per
+// lane per group fetches the neighbours, a ballot per group marks the arcs
+// into changed variables, and their positions are compacted in LDS. The
+// active arcs are then processed 64 at a time (lane = active arc), in units of
+// C row quads, two units in flight. Loads past the last unit repeat the last
+// active arc and are never tested, so every load is issued unconditionally.
+template <bool WIDE, int C, class DV>
+DEV void revise_sparse(const GLOBAL u32x4 *__restrict__ rows, const GLOBAL int32_t *__restrict__ nbrp,
+                       const GLOBAL int32_t *__restrict__ gown, const DV &D, int64_t g0,
+                       int64_t g1, int32_t qpa, int32_t xbase, const Scratch &S) {
+    constexpr int RPQ = WIDE ? 2 : 4;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int nch = qpa / C;
+    struct Unit {
+        u32x4 v[C];
+        int32_t y, own, q0;
+        bool ok;
+    };
+    for (int64_t gb = g0; gb < g1; gb += kSparseGroups) {
+        const int nb = (int)(g1 - gb < kSparseGroups ? g1 - gb : kSparseGroups);
+        int32_t y[kSparseGroups];
+#pragma unroll
+        for (int i = 0; i < kSparseGroups; ++i)
+            y[i] = nbrp[(gb + (i < nb ? i : nb - 1)) * kGroup + lane];
+        int total = 0;
+#pragma unroll
+        for (int i = 0; i < kSparseGroups; ++i) {
+            const bool act = i < nb && y[i] >= 0 && D.changed(y[i] < 0 ? 0 : y[i]);
+            const uint64_t m = __ballot(act);
+            if (act) S.cmp[total + lane_rank(m)] = (uint16_t)(i * kGroup + lane);
+            total += __popcll(m);
+        }
+        if (total == 0) continue;
+        wave_sync();
+        const int nunits = ((total + kWave - 1) / kWave) * nch;
+        auto load = [&](int u, Unit &s) {
+            const int uc = u < nunits ? u : nunits - 1;
+            const int a = uc / nch;
+            const int c = uc - a * nch;
+            const int p = a * kWave + lane;
+            s.ok = u < nunits && p < total;
+            const int code = S.cmp[p < total ? p : total - 1];
+            const int64_t g = gb + (code >> 6);
+            const int l = code & (kGroup - 1);
+            s.y = nbrp[g * kGroup + l];
+            s.own = gown[g] - xbase;
+            s.q0 = c * C;
+            const GLOBAL u32x4 *base = rows + (g * qpa + s.q0) * kGroup + l;
+#pragma unroll
+            for (int q = 0; q < C; ++q) s.v[q] = base[q * kGroup];
+        };
+        auto test = [&](const Unit &s) {
+            const uint64_t dy = D.get(s.y);
+            uint32_t f = 0;
+#pragma unroll
+            for (int q = 0; q < C; ++q) f |= quad_fail<WIDE>(s.v[q], dy) << (q * RPQ);
+            if (s.ok) note_fail(S, s.own, (uint64_t)f << (s.q0 * RPQ));
+        };
+        Unit s0, s1;
+        load(0, s0);
+        load(1, s1);
+        for (int u = 0; u < nunits; u += 2) {
+            test(s0);
+            load(u + 2, s0);
+            test(s1);
+            load(u + 3, s1);
+        }
+        wave_sync();   // every lane has read S.cmp before the next batch rewrites it
+    }
+}
+
+// The groups g0 .. g1-1 of a bit-row network; failures go to S.failx[own].
 template <bool ALL, class DV>
-DEV uint64_t revise_bits(const NetDesc &N, const DV &D, int64_t g0, int64_t g1) {
+DEV void revise_bits(const NetDesc &N, const DV &D, int64_t g0, int64_t g1, int32_t xbase,
+                     const Scratch &S) {
     const GLOBAL u32x4 *rows = as_global((const u32x4 *)N.rows);
     const GLOBAL int32_t *nbrp = as_global(N.nbrp);
-    if (N.kind == ROW64)   // qpa is a multiple of 4
-        return revise_groups<ALL, true, 4, 2>(rows, nbrp, D, g0, g1, N.qpa);
-    switch (N.qpa) {       // ROW32: qpa = 1..8, one chunk per group
-    case 1: return revise_groups<ALL, false, 1, 8>(rows, nbrp, D, g0, g1, 1);
-    case 2: return revise_groups<ALL, false, 2, 4>(rows, nbrp, D, g0, g1, 2);
-    case 3: return revise_groups<ALL, false, 3, 3>(rows, nbrp, D, g0, g1, 3);
-    case 4: return revise_groups<ALL, false, 4, 2>(rows, nbrp, D, g0, g1, 4);
-    case 5: return revise_groups<ALL, false, 5, 2>(rows, nbrp, D, g0, g1, 5);
-    case 6: return revise_groups<ALL, false, 6, 2>(rows, nbrp, D, g0, g1, 6);
-    case 7: return revise_groups<ALL, false, 7, 2>(rows, nbrp, D, g0, g1, 7);
-    default: return revise_groups<ALL, false, 8, 2>(rows, nbrp, D, g0, g1, 8);
+    const GLOBAL int32_t *gown = as_global(N.gown);
+    if (N.kind == ROW64) {   // qpa is a multiple of 4
+        if (ALL) revise_all<true, 4, 2>(rows, nbrp, gown, D, g0, g1, N.qpa, xbase, S);
+        else revise_sparse<true, 4>(rows, nbrp, gown, D, g0, g1, N.qpa, xbase, S);
+        return;
     }
+#define RAC_ROW32(Q, DEP)                                                                   \
+    case Q:                                                                                 \
+        if (ALL) revise_all<false, Q, DEP>(rows, nbrp, gown, D, g0, g1, Q, xbase, S);       \
+        else revise_sparse<false, Q>(rows, nbrp, gown, D, g0, g1, Q, xbase, S);             \
+        return;
+    switch (N.qpa) {         // ROW32: qpa = 1..8, one chunk per group
+        RAC_ROW32(1, 8)
+        RAC_ROW32(2, 4)
+        RAC_ROW32(3, 3)
+        RAC_ROW32(4, 2)
+        RAC_ROW32(5, 2)
+        RAC_ROW32(6, 2)
+        RAC_ROW32(7, 2)
+    default:
+        if (ALL) revise_all<false, 8, 2>(rows, nbrp, gown, D, g0, g1, 8, xbase, S);
+        else revise_sparse<false, 8>(rows, nbrp, gown, D, g0, g1, 8, xbase, S);
+        return;
+    }
+#undef RAC_ROW32
 }
 
 // int8 rows (d <= 32, dp = 16 or 32 bytes per row): a lane reads 16 bytes of
@@ -286,193 +359,145 @@ DEV uint64_t revise_i8(const GLOBAL int8_t *__restrict__ rows, const GLOBAL int3
     return wave_or64(fail);
 }
 
+// ---------------------------------------------------------------------------
+// Work items
+// ---------------------------------------------------------------------------
+
+DEV unsigned long long wave_sum64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+DEV void or_fail(const Launch &L, int64_t v, uint64_t f) {
+    (void)__hip_atomic_fetch_or(L.ws.failacc + v, (unsigned long long)f, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One work item of a bit-row network: every group of the item's variables
+// (or of one piece of a split variable) is revised in one pipeline; the
+// failing values of each variable go to its accumulator.
 template <bool ALL, class DV>
-DEV uint64_t revise(const NetDesc &N, const DV &D, int64_t u0, int64_t u1) {
-    if (N.kind != ROWI8) return revise_bits<ALL>(N, D, u0, u1);
-    return revise_i8<ALL>(as_global((const int8_t *)N.rows), as_global(N.nbr), D, u0, u1, N.d,
-                          N.dp);
+DEV void process_bits_item(const Launch &L, const NetDesc &N, const DV &D, const int4 it,
+                           int64_t off, const Scratch &S) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t nx = it.y - it.x;   // <= kItemVars = kWave (work items are built so)
+    S.failx[lane] = 0;
+    wave_sync();
+    revise_bits<ALL>(N, D, it.z, it.w, it.x, S);
+    wave_sync();
+    const uint64_t f = lane < nx ? S.failx[lane] : 0ull;
+    if (f) or_fail(L, off + it.x + lane, f);
+}
+
+// One work item of an int8-row network: variable by variable.
+template <bool ALL, class DV>
+DEV void process_i8_item(const Launch &L, const NetDesc &N, const DV &D, const int4 it,
+                         int32_t pieces, int64_t off) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const GLOBAL int8_t *rows = as_global((const int8_t *)N.rows);
+    const GLOBAL int32_t *nbr = as_global(N.nbr);
+    for (int32_t x = it.x; x < it.y; ++x) {
+        const int64_t j0 = pieces ? it.z : N.row_ptr[x];
+        const int64_t j1 = pieces ? it.w : N.row_ptr[x + 1];
+        const uint64_t fail = revise_i8<ALL>(rows, nbr, D, j0, j1, N.d, N.dp);
+        if (lane == 0 && fail) or_fail(L, off + x, fail);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Per-problem bookkeeping
+// Step control
 // ---------------------------------------------------------------------------
 
-struct ItemFlags {
-    int changed;
-    int wiped;
-    unsigned long long degsum;
-};
-
-// New domain of x after step k: D^(k)(x) = D^(k-1)(x) minus the failing values.
-DEV void update_var(const NetDesc &N, uint64_t *dnext, uint32_t *chg_next, int32_t x,
-                    uint64_t dx, uint64_t fail, ItemFlags &f) {
-    const uint64_t nx = dx & ~fail & dmask_of(N.d);
-    const bool changed = nx != dx;
-    st_rlx(dnext + x, nx);
-    st_rlx(chg_next + x, changed ? 1u : 0u);
-    if (changed) {
-        f.changed = 1;
-        f.degsum += (unsigned long long)N.deg[x];
-    }
-    if (nx == 0) f.wiped = 1;
+DEV int32_t max_steps(const Launch &L, const NetDesc &N) {
+    return L.max_sweeps > 0 ? L.max_sweeps : N.n * N.d + 1;
 }
 
-template <bool ALL, class DV>
-DEV void process_item(const Launch &L, const NetDesc &N, const DV &D, int k, const int4 it,
-                      int32_t pieces, int64_t off, ItemFlags &f) {
-    uint64_t *dnext = L.ws.dom[k & 1] + off;
-    uint32_t *chg_next = L.ws.chg[k & 1] + off;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int32_t *up = N.kind == ROWI8 ? N.row_ptr : N.gptr;
-    if (pieces == 0) {
-        // whole variables, one after the other
-        for (int32_t x = it.x; x < it.y; ++x) {
-            const uint64_t dx = D.get(x);
-            uint64_t fail = 0;
-            if (dx != 0) fail = revise<ALL>(N, D, up[x], up[x + 1]);
-            if (lane == 0) update_var(N, dnext, chg_next, x, dx, fail, f);
+// Does problem p execute step k? Step 1 always; step k > 1 if step k-1
+// removed a value (Algorithm 1's loop test), unless the step cap is reached
+// or, when stopping on a wipe-out, an earlier step emptied a domain. Only
+// words written by earlier kernels decide it (last_change >= k-1 also holds
+// while the update kernel of step k raises it to k).
+DEV bool active(const Launch &L, const NetDesc &N, const Ctrl &C, int k) {
+    if (k > max_steps(L, N)) return false;
+    if (k > 1 && C.last_change < k - 1) return false;
+    if (L.mode == RAC_STOP_ON_WIPEOUT && C.wipe_step != 0 && C.wipe_step < k) return false;
+    return true;
+}
+
+DEV int prob_of_var(const Launch &L, int64_t v) {
+    int lo = 0, hi = L.nprob - 1;   // largest p with prob_off[p] <= v
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.prob_off[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// The problems that execute step k, in order, with the prefix sums of their
+// item counts. One workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void plan_kernel(Launch L, int k) {
+    __shared__ int64_t s_wave[16];
+    __shared__ int64_t s_base_items;
+    __shared__ int32_t s_wave_n[16];
+    __shared__ int32_t s_base_n;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) {
+        s_base_items = 0;
+        s_base_n = 0;
+    }
+    __syncthreads();
+    for (int32_t p0 = 0; p0 < L.nprob; p0 += 1024) {
+        const int32_t p = p0 + (int32_t)threadIdx.x;
+        bool on = false;
+        int64_t items = 0;
+        if (p < L.nprob) {
+            const NetDesc &N = L.nets[L.prob_net[p]];
+            on = active(L, N, L.ws.ctrl[p], k);
+            if (on) items = N.nitems;
         }
-        return;
-    }
-    // one piece of a split variable: the last piece to finish (over all
-    // workgroups) writes the variable
-    const int32_t x = it.x;
-    const uint64_t dx = D.get(x);
-    const uint64_t fail = dx != 0 ? revise<ALL>(N, D, it.z, it.w) : 0ull;
-    if (lane == 0) {
-        uint64_t *acc = L.ws.failacc + off + x;
-        int32_t *cnt = L.ws.xcnt + off + x;
-        if (fail) (void)__hip_atomic_fetch_or(acc, fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        wait_stores();
-        const int32_t arrived = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == pieces - 1) {
-            const uint64_t ftot = __hip_atomic_exchange(acc, (uint64_t)0, __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT);
-            st_rlx(cnt, 0);
-            update_var(N, dnext, chg_next, x, dx, ftot, f);
+        // inclusive scan of the item counts within the wave, then across waves
+        int64_t inc = items;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += t;
         }
-    }
-}
-
-// Lane 0, after the wave finished an item of lane `lane` of step k and its
-// stores were performed.
-DEV void complete_item(const Launch &L, const NetDesc &N, int p, int k, int lane,
-                       const ItemFlags &f) {
-    Ctrl *C = L.ws.ctrl + p;
-    Lane *lanes = L.ws.lanes + (int64_t)p * L.lanes_per_prob;
-    if (f.changed) {
-        (void)__hip_atomic_fetch_max(&C->last_change, (int32_t)k, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
-        (void)__hip_atomic_fetch_add(&C->degsum[k & 1], f.degsum, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (f.wiped)
-        (void)__hip_atomic_fetch_or(&C->wiped, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    wait_stores();
-    const int32_t lane_done = __hip_atomic_fetch_add(&lanes[lane].finish, 1, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-    if (lane_done != lanes[lane].count - 1) return;
-    const int32_t nl = C->nlanes;
-    const int32_t all_done = __hip_atomic_fetch_add(&C->lanes_done, 1, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-    if (all_done != nl - 1) return;
-
-    // last item of step k: finalise the step (Algorithm 1's loop test)
-    const bool changed = ld_rlx(&C->last_change) == k;
-    const bool wiped = ld_rlx(&C->wiped) != 0;
-    const int32_t maxs = L.max_sweeps > 0 ? L.max_sweeps : N.n * N.d + 1;
-    const bool stop_on_wipe = (L.mode == RAC_STOP_ON_WIPEOUT) && wiped;
-    if (changed && !stop_on_wipe && k < maxs) {
-        const unsigned long long ds = __hip_atomic_exchange(
-            &C->degsum[k & 1], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        st_rlx(&C->checks, ld_rlx(&C->checks) + (long long)ds * N.d * N.d);
-        for (int32_t l = 0; l < nl; ++l) st_rlx(&lanes[l].finish, 0);
-        st_rlx(&C->lanes_done, 0);
-        wait_stores();
-        for (int32_t l = 0; l < nl; ++l) st_rlx(&lanes[l].ticket, (unsigned long long)(k + 1) << 32);
-    } else {
-        st_rlx(&C->iters, (int32_t)k);
-        st_rlx(&C->status, wiped ? (int32_t)RAC_WIPEOUT : (int32_t)RAC_CONSISTENT);
-        st_rlx(&C->rc, (changed && !stop_on_wipe) ? (int32_t)RAC_ENOTCONVERGED : 0);
-        wait_stores();
-        st_rlx(&C->done, 1);
-        (void)__hip_atomic_fetch_add(&L.ws.global->active, -1, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-// Claim an item (whole wave). 1 = claimed, 0 = nothing claimable now,
-// -1 = leave. Every (problem, lane) pair is a slot. The wave first tries its
-// cursor slot alone, then probes 64 slots at once and claims from the first
-// slot with items left. The result is the same in every lane.
-DEV int probe_slots(const Launch &L, int64_t first, int32_t width, int64_t nslots,
-                    int64_t &cursor, int &p_out, int &k_out, int &c_out, int &lane_out) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int32_t lpp = L.lanes_per_prob;
-    int64_t slot = first + lane;
-    while (slot >= nslots) slot -= nslots;
-    bool cand = false;
-    int32_t cnt = 0, start = 0;
-    if (lane < width) {
-        const int32_t p = (int32_t)(slot / lpp);
-        const int32_t l = (int32_t)(slot - (int64_t)p * lpp);
-        if (l < L.ws.ctrl[p].nlanes) {
-            Lane *ln = L.ws.lanes + slot;
-            cnt = ln->count;
-            start = ln->start;
-            cand = (int32_t)(ld_rlx(&ln->ticket) & 0xFFFFFFFFull) < cnt;
+        const uint64_t bal = __ballot(on);
+        const int rank = lane_rank(bal);
+        if (lane == 63) s_wave[wave] = inc;
+        if (lane == 0) s_wave_n[wave] = __popcll(bal);
+        __syncthreads();
+        int64_t before = s_base_items;
+        int32_t nbefore = s_base_n;
+        for (int w = 0; w < wave; ++w) {
+            before += s_wave[w];
+            nbefore += s_wave_n[w];
         }
-    }
-    uint64_t m = __ballot(cand);
-    while (m) {
-        const int src = __ffsll((unsigned long long)m) - 1;
-        m &= m - 1;
-        unsigned long long tk = 0;
-        if (lane == src)
-            tk = __hip_atomic_fetch_add(&L.ws.lanes[slot].ticket, 1ull, __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT);
-        tk = __shfl(tk, src, kWave);
-        const int32_t c = (int32_t)(tk & 0xFFFFFFFFull);
-        if (c < __shfl(cnt, src, kWave)) {
-            const int64_t sslot = __shfl(slot, src, kWave);
-            cursor = sslot;
-            p_out = (int32_t)(sslot / lpp);
-            lane_out = (int32_t)(sslot - (int64_t)p_out * lpp);
-            k_out = (int32_t)(tk >> 32);
-            c_out = __shfl(start, src, kWave) + c;
-            return 1;
+        if (on) {
+            L.ws.act[nbefore + rank] = p;
+            L.ws.act_off[nbefore + rank] = before + inc - items;
         }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 0; w < 16; ++w) {
+                s_base_items += s_wave[w];
+                s_base_n += s_wave_n[w];
+            }
+        }
+        __syncthreads();
     }
-    return 0;
+    if (threadIdx.x == 0) {
+        L.ws.act_off[s_base_n] = s_base_items;
+        L.ws.plan->nact = s_base_n;
+        L.ws.plan->items = s_base_items;
+    }
 }
 
-DEV int try_claim(const Launch &L, int64_t &cursor, int &p_out, int &k_out, int &c_out,
-                  int &lane_out, int spins) {
-    Global *G = L.ws.global;
-    if (ld_rlx(&G->error) != 0) return -1;
-    if (ld_rlx(&G->active) <= 0) return -1;
-    const int64_t nslots = (int64_t)L.nprob * L.lanes_per_prob;
-    if (probe_slots(L, cursor, 1, nslots, cursor, p_out, k_out, c_out, lane_out)) return 1;
-    // While its own problem is still running, an idle wave mostly re-probes
-    // its own lane (the next step's tickets appear on every lane at once) and
-    // scans the other slots only every fourth poll, which keeps the polling
-    // traffic on the ticket lines low.
-    const int32_t cp = (int32_t)(cursor / L.lanes_per_prob);
-    if (spins > 0 && (spins & 3) != 3 && ld_rlx(&L.ws.ctrl[cp].done) == 0) return 0;
-    for (int64_t base = 1; base <= nslots; base += kWave) {
-        const int32_t width = (int32_t)((nslots - base + 1) < kWave ? (nslots - base + 1) : kWave);
-        int64_t first = cursor + base;
-        while (first >= nslots) first -= nslots;
-        if (probe_slots(L, first, width, nslots, cursor, p_out, k_out, c_out, lane_out)) return 1;
-    }
-    return 0;
-}
-
-// Stage D^(k-1) (and, after step 1, the previous step's change flags) of a
-// problem in LDS. Step 1 reads what the init kernel wrote: ordinary loads.
+// Stage D^(k-1) (and, when only changed arcs are re-examined, the @changed
+// flags of step k-1 as a bit mask) of a problem in LDS.
 DEV void stage(uint64_t *s_dom, uint32_t *s_chg, const uint64_t *gdom, const uint32_t *gchg,
-               int32_t n, bool coherent, bool flags) {
+               int32_t n, bool flags) {
     const int lane = threadIdx.x & (kWave - 1);
     constexpr int kBatch = 8;
     for (int32_t base = 0; base < n; base += kBatch * kWave) {
@@ -480,7 +505,7 @@ DEV void stage(uint64_t *s_dom, uint32_t *s_chg, const uint64_t *gdom, const uin
 #pragma unroll
         for (int i = 0; i < kBatch; ++i) {
             const int32_t v = base + i * kWave + lane;
-            t[i] = v < n ? (coherent ? ld_rlx(const_cast<uint64_t *>(gdom + v)) : gdom[v]) : 0ull;
+            t[i] = v < n ? gdom[v] : 0ull;
         }
 #pragma unroll
         for (int i = 0; i < kBatch; ++i) {
@@ -494,7 +519,7 @@ DEV void stage(uint64_t *s_dom, uint32_t *s_chg, const uint64_t *gdom, const uin
 #pragma unroll
             for (int i = 0; i < kBatch; ++i) {
                 const int32_t v = base + i * kWave + lane;
-                t[i] = v < n ? (coherent ? ld_rlx(const_cast<uint32_t *>(gchg + v)) : gchg[v]) : 0u;
+                t[i] = v < n ? gchg[v] : 0u;
             }
 #pragma unroll
             for (int i = 0; i < kBatch; ++i) {
@@ -507,79 +532,150 @@ DEV void stage(uint64_t *s_dom, uint32_t *s_chg, const uint64_t *gdom, const uin
             }
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_sync();
 }
 
-// The persistent fixpoint kernel: one wave per workgroup, each an independent
-// worker that claims items through the tickets. No workgroup ever waits for
-// another, so the kernel is correct whether or not all of its workgroups are
-// resident at once.
-__global__ __launch_bounds__(kWave) void sweep_kernel(Launch L) {
-    extern __shared__ uint64_t s_stage[];
-    uint64_t *s_dom = s_stage;
-    uint32_t *s_chg = reinterpret_cast<uint32_t *>(s_stage + L.stage_vars);
-    const int lane = threadIdx.x & (kWave - 1);
-    int64_t cursor = (int64_t)(blockIdx.x % (unsigned)((int64_t)L.nprob * L.lanes_per_prob));
-    int spins = 0;
-    int staged_p = -1, staged_k = -1;
-    for (;;) {
-        int p = 0, k = 0, c = 0, ln = 0;
-        const int r = try_claim(L, cursor, p, k, c, ln, spins);
-        if (r < 0) return;
-        if (r == 0) {
-            if (++spins > L.spin_limit) {
-                if (lane == 0)
-                    (void)__hip_atomic_fetch_or(&L.ws.global->error, 1, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-                return;
-            }
-            __builtin_amdgcn_s_sleep(32);
-            continue;
+// Step k, revision: workgroup w (one wave) takes items [w*T/G, (w+1)*T/G) of
+// the T items the plan listed, stages each problem's D^(k-1) once, and ORs
+// the failing values into the accumulators.
+__global__ __launch_bounds__(kWave) void revise_kernel(Launch L, int k) {
+    extern __shared__ uint64_t s_lds[];
+    const Scratch S{reinterpret_cast<unsigned long long *>(s_lds),
+                    reinterpret_cast<uint16_t *>(s_lds + kItemVars)};
+    uint64_t *s_dom = s_lds + kScratchWords;
+    uint32_t *s_chg = reinterpret_cast<uint32_t *>(s_dom + L.stage_vars);
+    const int32_t nact = L.ws.plan->nact;
+    const int64_t T = L.ws.plan->items;
+    const int64_t G = gridDim.x;
+    const int64_t c0 = T * blockIdx.x / G, c1 = T * (blockIdx.x + 1) / G;
+    if (c0 >= c1) return;
+    const bool all = (k == 1) && (L.changed0 == nullptr);
+    // the listed problem holding item c0
+    int a = 0;
+    {
+        int hi = nact - 1;
+        while (a < hi) {
+            const int mid = (a + hi + 1) >> 1;
+            if (L.ws.act_off[mid] <= c0) a = mid; else hi = mid - 1;
         }
-        spins = 0;
+    }
+    int staged = -1;
+    for (int64_t c = c0; c < c1; ++c) {
+        while (L.ws.act_off[a + 1] <= c) ++a;
+        const int32_t p = L.ws.act[a];
         const NetDesc &N = L.nets[L.prob_net[p]];
         const int64_t off = L.prob_off[p];
-        const int4 it = N.items[c];
-        const int32_t pieces = N.pieces[c];
-        const bool all = (k == 1) && (L.changed0 == nullptr);
+        const int32_t ci = (int32_t)(c - L.ws.act_off[a]);
+        const int4 it = N.items[ci];
+        const int32_t pieces = N.pieces[ci];
         const uint64_t *gdom = L.ws.dom[(k - 1) & 1] + off;
         const uint32_t *gchg = L.ws.chg[(k - 1) & 1] + off;
-        ItemFlags fl{0, 0, 0ull};
         if (N.n <= L.stage_vars) {
-            if (p != staged_p || k != staged_k) {
-                stage(s_dom, s_chg, gdom, gchg, N.n, k > 1, !all);
-                staged_p = p;
-                staged_k = k;
+            if (p != staged) {
+                stage(s_dom, s_chg, gdom, gchg, N.n, !all);
+                staged = p;
             }
             const DomView<VIEW_LDS> D{s_dom, s_chg};
-            if (all) process_item<true>(L, N, D, k, it, pieces, off, fl);
-            else process_item<false>(L, N, D, k, it, pieces, off, fl);
-        } else if (k == 1) {
-            const DomView<VIEW_PLAIN> D{gdom, gchg};
-            if (all) process_item<true>(L, N, D, k, it, pieces, off, fl);
-            else process_item<false>(L, N, D, k, it, pieces, off, fl);
+            if (N.kind == ROWI8) {
+                if (all) process_i8_item<true>(L, N, D, it, pieces, off);
+                else process_i8_item<false>(L, N, D, it, pieces, off);
+            } else {
+                if (all) process_bits_item<true>(L, N, D, it, off, S);
+                else process_bits_item<false>(L, N, D, it, off, S);
+            }
         } else {
-            const DomView<VIEW_COHERENT> D{gdom, gchg};
-            process_item<false>(L, N, D, k, it, pieces, off, fl);
+            const DomView<VIEW_PLAIN> D{gdom, gchg};
+            if (N.kind == ROWI8) {
+                if (all) process_i8_item<true>(L, N, D, it, pieces, off);
+                else process_i8_item<false>(L, N, D, it, pieces, off);
+            } else {
+                if (all) process_bits_item<true>(L, N, D, it, off, S);
+                else process_bits_item<false>(L, N, D, it, off, S);
+            }
         }
-        wait_stores();
-        if (lane == 0) complete_item(L, N, p, k, ln, fl);
     }
 }
 
-// ---------------------------------------------------------------------------
-// Set-up and result kernels
-// ---------------------------------------------------------------------------
+// Block-wide reductions of the update kernel (256 threads = 4 waves).
+struct UpdRed {
+    unsigned long long deg[4];
+    int32_t changed[4], wiped[4];
+};
 
-DEV int prob_of_var(const Launch &L, int64_t v) {
-    int lo = 0, hi = L.nprob - 1;   // largest p with prob_off[p] <= v
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (L.prob_off[mid] <= v) lo = mid; else hi = mid - 1;
+// Step k, update: D^(k)(v) = D^(k-1)(v) minus its accumulated failures, the
+// @changed flag of step k, and per problem the last step with a change, the
+// first step with a wipe-out, the arcs the next step re-examines (arcs into
+// changed variables) and the support checks of step k (d*d per arc it
+// re-examined).
+__global__ __launch_bounds__(256) void update_kernel(Launch L, int k) {
+    __shared__ UpdRed s_red;
+    const int s_now = k % 3, s_prev = (k + 2) % 3, s_next = (k + 1) % 3;
+    const int64_t nv = L.prob_off[L.nprob];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (blockIdx.x == 0)
+        for (int32_t p = threadIdx.x; p < L.nprob; p += blockDim.x) L.ws.ctrl[p].arcs[s_next] = 0;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nv;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = base + threadIdx.x;
+        const int64_t vlast = base + blockDim.x - 1 < nv ? base + blockDim.x - 1 : nv - 1;
+        const int pb0 = prob_of_var(L, base), pb1 = prob_of_var(L, vlast);
+        bool ch = false, wp = false;
+        unsigned long long dg = 0;
+        int p = -1;
+        if (v < nv) {
+            p = pb0 == pb1 ? pb0 : prob_of_var(L, v);
+            const NetDesc &N = L.nets[L.prob_net[p]];
+            Ctrl &C = L.ws.ctrl[p];
+            if (active(L, N, C, k)) {
+                const uint64_t dx = L.ws.dom[(k - 1) & 1][v];
+                const uint64_t f = L.ws.failacc[v];
+                if (f) L.ws.failacc[v] = 0;
+                const uint64_t nd = dx & ~f & dmask_of(N.d);
+                ch = nd != dx;
+                wp = nd == 0;
+                L.ws.dom[k & 1][v] = nd;
+                L.ws.chg[k & 1][v] = ch ? 1u : 0u;
+                const int32_t x = (int32_t)(v - L.prob_off[p]);
+                if (ch) dg = (unsigned long long)N.deg[x];
+                if (x == 0) C.checks += C.arcs[s_prev] * (long long)N.d * N.d;
+            }
+        }
+        if (pb0 == pb1) {   // the whole block is one problem: one atomic per block
+            const uint64_t mc = __ballot(ch), mw = __ballot(wp);
+            const unsigned long long ws = wave_sum64(dg);
+            if (lane == 0) {
+                s_red.deg[wave] = ws;
+                s_red.changed[wave] = mc != 0;
+                s_red.wiped[wave] = mw != 0;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                unsigned long long tdeg = 0;
+                int tch = 0, twp = 0;
+                for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+                    tdeg += s_red.deg[w];
+                    tch |= s_red.changed[w];
+                    twp |= s_red.wiped[w];
+                }
+                Ctrl &C = L.ws.ctrl[pb0];
+                if (tch) {
+                    (void)__hip_atomic_fetch_add(&C.arcs[s_now], (long long)tdeg, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+                    C.last_change = k;
+                }
+                if (twp && C.wipe_step == 0) C.wipe_step = k;
+            }
+            __syncthreads();
+        } else if (p >= 0) {
+            Ctrl &C = L.ws.ctrl[p];
+            if (ch) {
+                (void)__hip_atomic_fetch_add(&C.arcs[s_now], (long long)dg, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+                C.last_change = k;
+            }
+            if (wp && C.wipe_step == 0) C.wipe_step = k;
+        }
     }
-    return lo;
 }
 
 __global__ void init_kernel(Launch L) {
@@ -588,61 +684,57 @@ __global__ void init_kernel(Launch L) {
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = tid; v < nv; v += nthreads) {
         L.ws.dom[0][v] = L.din[v];
-        L.ws.chg[0][v] = L.changed0 ? (uint32_t)(L.changed0[v] != 0) : 1u;
-        L.ws.chg[1][v] = 0;
+        const bool c = L.changed0 ? L.changed0[v] != 0 : true;
+        L.ws.chg[0][v] = c ? 1u : 0u;
         L.ws.failacc[v] = 0;
-        L.ws.xcnt[v] = 0;
     }
     for (int64_t p = tid; p < L.nprob; p += nthreads) {
         const NetDesc &N = L.nets[L.prob_net[p]];
-        Ctrl *C = L.ws.ctrl + p;
-        const int32_t nl = N.nitems < L.lanes_per_prob ? N.nitems : L.lanes_per_prob;
-        C->degsum[0] = 0;
-        C->degsum[1] = 0;
-        C->checks = (L.changed0 && L.checks1 >= 0) ? L.checks1 : (long long)N.arcs * N.d * N.d;
-        C->lanes_done = 0;
-        C->nlanes = nl;
-        C->last_change = 0;
-        C->wiped = 0;
-        C->done = 0;
-        C->iters = 0;
-        C->status = 0;
-        C->rc = 0;
-        Lane *lanes = L.ws.lanes + p * L.lanes_per_prob;
-        for (int32_t l = 0; l < L.lanes_per_prob; ++l) {
-            const int32_t st = l < nl ? (int32_t)((int64_t)N.nitems * l / nl) : 0;
-            const int32_t en = l < nl ? (int32_t)((int64_t)N.nitems * (l + 1) / nl) : 0;
-            lanes[l].ticket = 1ull << 32;
-            lanes[l].finish = 0;
-            lanes[l].start = st;
-            lanes[l].count = en - st;
-        }
+        Ctrl &C = L.ws.ctrl[p];
+        C.arcs[0] = L.changed0 ? L.arcs1 : N.arcs;   // arcs step 1 re-examines
+        C.arcs[1] = 0;
+        C.arcs[2] = 0;
+        C.checks = 0;
+        C.last_change = 0;
+        C.wipe_step = 0;
     }
-    if (tid == 0) {
-        L.ws.global->active = L.nprob;
-        L.ws.global->error = 0;
-        if (L.rc_out) *L.rc_out = 0;
-    }
+    if (tid == 0 && L.rc_out) *L.rc_out = 0;
 }
 
 __global__ void finish_kernel(Launch L) {
     const int64_t nv = L.prob_off[L.nprob];
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    auto iters_of = [&](int p, int32_t *rc) {
+        const NetDesc &N = L.nets[L.prob_net[p]];
+        const Ctrl &C = L.ws.ctrl[p];
+        const int32_t maxs = max_steps(L, N);
+        if (L.mode == RAC_STOP_ON_WIPEOUT && C.wipe_step != 0) {
+            *rc = 0;
+            return C.wipe_step;
+        }
+        if (C.last_change < maxs) {
+            *rc = 0;
+            return C.last_change + 1;
+        }
+        *rc = 1;
+        return maxs;
+    };
     for (int64_t v = tid; v < nv; v += nthreads) {
         const int p = prob_of_var(L, v);
-        const int32_t k = L.ws.ctrl[p].iters;
-        L.dout[v] = L.ws.dom[k & 1][v];
+        int32_t rc;
+        const int32_t it = iters_of(p, &rc);
+        L.dout[v] = L.ws.dom[it & 1][v];
     }
     for (int64_t p = tid; p < L.nprob; p += nthreads) {
         const Ctrl &C = L.ws.ctrl[p];
-        if (L.iters_out) L.iters_out[p] = C.iters;
-        if (L.status_out) L.status_out[p] = C.status;
+        int32_t rc;
+        const int32_t it = iters_of((int)p, &rc);
+        if (L.iters_out) L.iters_out[p] = it;
+        if (L.status_out) L.status_out[p] = C.wipe_step != 0 ? RAC_WIPEOUT : RAC_CONSISTENT;
         if (L.checks_out) L.checks_out[p] = C.checks;
-        if (C.rc != 0 && L.rc_out) atomicOr(L.rc_out, 1);
-        if (!C.done && L.rc_out) atomicOr(L.rc_out, 2);
+        if (rc && L.rc_out) atomicOr(L.rc_out, 1);
     }
-    if (tid == 0 && L.ws.global->error != 0 && L.rc_out) atomicOr(L.rc_out, 2);
 }
 
 // Relation row a of an arc from the per-constraint rows rel[e][a] (bit b =
