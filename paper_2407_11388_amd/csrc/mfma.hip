@@ -217,31 +217,56 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
 
         // products of this block's arcs, two at a time: a fresh accumulator
         // per arc, folded into the running minimum with one min3 per value.
-        // An odd last arc is paired with itself.
+        // An odd last arc is paired with itself. Units u = 4*pair + sub-tile
+        // are software-pipelined: the LDS operands of unit u+1 are read and
+        // the products of unit u issued before the minimum of unit u-1 is
+        // folded, so the fold overlaps the matrix-core work.
         const int cnt = __builtin_popcount(mcur);
-        uint32_t msk = mcur;
+        const int npairs = (cnt + 1) >> 1;
+        int l0[kMY / 2], l1[kMY / 2];
+        {
+            uint32_t msk = mcur;
 #pragma unroll
-        for (int i = 0; i < kMY; i += 2) {
-            if (i >= cnt) break;
-            const int l0 = __builtin_ctz(msk);
-            msk &= msk - 1u;
-            const bool two = i + 1 < cnt;
-            const int l1 = two ? __builtin_ctz(msk) : l0;
-            if (two) msk &= msk - 1u;
-            v4i b0[kMSub], b1[kMSub];
-#pragma unroll
-            for (int t = 0; t < kMSub; ++t) {
-                b0[t] = s_b[buf][l0][half][t * 32 + col];
-                b1[t] = s_b[buf][l1][half][t * 32 + col];
+            for (int q = 0; q < kMY / 2; ++q) {
+                l0[q] = msk ? __builtin_ctz(msk) : 0;
+                msk &= msk - 1u;
+                l1[q] = msk ? __builtin_ctz(msk) : l0[q];
+                msk &= msk - 1u;
             }
+        }
+        if (npairs > 0) {
+            auto lds_b = [&](int q, int t, v4i &b0, v4i &b1) {
+                b0 = s_b[buf][l0[q]][half][t * 32 + col];
+                b1 = s_b[buf][l1[q]][half][t * 32 + col];
+            };
+            auto fold = [&](v16i &r, const v16i &c0, const v16i &c1) {
 #pragma unroll
-            for (int t = 0; t < kMSub; ++t) {
-                const v16i zero = {0};
-                const v16i c0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(acur[i], b0[t], zero, 0, 0, 0);
-                const v16i c1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(acur[i + 1], b1[t], zero, 0, 0, 0);
+                for (int v = 0; v < 16; ++v) r[v] = min(r[v], min(c0[v], c1[v]));
+            };
+            const v16i zero = {0};
+            v4i bn0, bn1;
+            lds_b(0, 0, bn0, bn1);
+            v16i cp0 = zero, cp1 = zero;
 #pragma unroll
-                for (int v = 0; v < 16; ++v) rm[t][v] = min(rm[t][v], min(c0[v], c1[v]));
+            for (int u = 0; u < 2 * kMY; ++u) {
+                const int q = u >> 2, t = u & 3;
+                if (q >= npairs) break;
+                const v4i b0 = bn0, b1 = bn1;
+                if (u + 1 < 2 * kMY) {
+                    const int qn = ((u + 1) >> 2) < npairs ? ((u + 1) >> 2) : npairs - 1;
+                    lds_b(qn, (u + 1) & 3, bn0, bn1);
+                }
+                const v16i c0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(acur[2 * q], b0, zero, 0, 0, 0);
+                const v16i c1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(acur[2 * q + 1], b1, zero, 0, 0, 0);
+                // keep the compiler from moving the fold next to the products
+                // it would then wait for
+                __builtin_amdgcn_sched_barrier(0);
+                if (u > 0) fold(rm[(u - 1) & 3], cp0, cp1);
+                __builtin_amdgcn_sched_barrier(0);
+                cp0 = c0;
+                cp1 = c1;
             }
+            fold(rm[kMSub - 1], cp0, cp1);   // a pair's last unit is sub-tile 3
         }
         store_b(buf ^ 1, breg);
 #pragma unroll
