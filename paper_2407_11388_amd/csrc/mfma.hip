@@ -153,25 +153,38 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
     const int8_t *dcur = A.dom8[(k - 1) & 1];
     const int half = lane >> 5, col = lane & 31;
 
-    // B staging: thread t moves, for every neighbour block, the 16-byte units
-    // (state slot t & 127, half (t >> 7) & 1, neighbour (t >> 8) + 2i),
+    // B staging. The domain bytes of one state for the 8 neighbours of a
+    // block are 256 consecutive bytes; 16 lanes read them as 16-byte chunks
+    // (chunk j: neighbour j >> 1, half j & 1), so a wave's load covers 4
+    // states' rows. Thread t moves chunk t & 15 of state slots (t >> 4) + 32i,
     // i = 0..3. Every load is issued: a slot past the active states reads a
     // valid state (its products are never used) and a neighbour past n reads
-    // variable n-1 (it is never a neighbour of anything).
-    const int b_sl = tid & (kMS - 1), b_h = (tid >> 7) & 1, b_y0 = tid >> 8;
-    const int b_state = act[st0 + b_sl < nact ? st0 + b_sl : nact - 1];
-    const int8_t *b_src = dcur + (int64_t)b_state * A.N32 + b_h * 16;
-    auto fetch_b = [&](int yb, v4i (&r)[4]) {
+    // variable n-1's bytes (never a neighbour of anything).
+    const int b_j = tid & 15, b_yl = b_j >> 1, b_h = b_j & 1;
+    const int8_t *b_src[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            int y = yb + b_y0 + 2 * i;
-            y = y < A.n ? y : A.n - 1;
-            r[i] = *reinterpret_cast<const v4i *>(b_src + (int64_t)y * 32);
-        }
+    for (int i = 0; i < 4; ++i) {
+        const int sl = (tid >> 4) + 32 * i;
+        const int st = act[st0 + sl < nact ? st0 + sl : nact - 1];
+        b_src[i] = dcur + (int64_t)st * A.N32 + b_h * 16;
+    }
+    // LDS slot of (neighbour yl, half h, state slot sl): the slot index is
+    // XOR-ed with 2*yl + h so that the 16 lanes writing one state's chunks hit
+    // 16 different bank groups; readers of one (yl, h) apply the same XOR to
+    // 32 consecutive slots, which permutes them within 16-slot groups.
+    auto bslot = [](int yl, int h, int sl) { return sl ^ ((2 * yl + h) & 15); };
+    auto fetch_b = [&](int yb, v4i (&r)[4]) {
+        int y = yb + b_yl;
+        y = y < A.n ? y : A.n - 1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) r[i] = *reinterpret_cast<const v4i *>(b_src[i] + (int64_t)y * 32);
     };
     auto store_b = [&](int buf, const v4i (&r)[4]) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) s_b[buf][b_y0 + 2 * i][b_h][b_sl] = r[i];
+        for (int i = 0; i < 4; ++i) {
+            const int sl = (tid >> 4) + 32 * i;
+            s_b[buf][b_yl][b_h][bslot(b_yl, b_h, sl)] = r[i];
+        }
     };
     // relation blocks of this wave's arcs in one neighbour block: the block's
     // arcs are consecutive (sorted by neighbour), j0 .. j0+cnt-1; slots past
@@ -236,8 +249,8 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
         }
         if (npairs > 0) {
             auto lds_b = [&](int q, int t, v4i &b0, v4i &b1) {
-                b0 = s_b[buf][l0[q]][half][t * 32 + col];
-                b1 = s_b[buf][l1[q]][half][t * 32 + col];
+                b0 = s_b[buf][l0[q]][half][bslot(l0[q], half, t * 32 + col)];
+                b1 = s_b[buf][l1[q]][half][bslot(l1[q], half, t * 32 + col)];
             };
             auto fold = [&](v16i &r, const v16i &c0, const v16i &c1) {
 #pragma unroll
