@@ -45,6 +45,10 @@ constexpr int kMY = 8;            // neighbours per LDS block
 constexpr int kMThreads = 64 * kMX;
 constexpr int kMaxChunk = 16;     // steps enqueued per group of steps
 
+// 4 bits -> 4 bytes holding 0/1 (bit i of v becomes byte i). The factor places
+// copies of v 7 bits apart, so no two copies overlap and no carry occurs.
+__device__ __forceinline__ uint32_t spread4(uint32_t v) { return (v * 0x00204081u) & 0x01010101u; }
+
 struct MState {
     long long checks;     // support checks so far
     unsigned long long degsum;
@@ -58,12 +62,12 @@ struct MArgs {
     const int32_t *row_ptr;           // [n+1] arcs of x, sorted by neighbour
     const int32_t *nbr_s;             // [arcs]
     const int32_t *deg;               // [n]
-    const int8_t *r8;                 // [arcs][32][32]
+    const uint32_t *r1;               // [arcs][32] row a of each arc as bits (bit b: (a,b) allowed)
     const int32_t *bstart;            // [n][nblk+1] first arc of x with neighbour >= 8*b
     const uint32_t *bmask;            // [n][nblk] bit l: x is constrained with y = 8*b + l
                                       // (32-bit words, so that scalar loads read them)
     int32_t nblk;                     // ceil(n / 8)
-    int32_t narcs;                    // number of arcs (rows of r8)
+    int32_t narcs;                    // number of arcs (blocks of r1)
     int8_t *dom8[2];                  // [capB][N32]
     uint32_t *chg, *wipe;             // [n][words]
     int32_t words;                    // capB / 32
@@ -188,16 +192,27 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
     };
     // relation blocks of this wave's arcs in one neighbour block: the block's
     // arcs are consecutive (sorted by neighbour), j0 .. j0+cnt-1; slots past
-    // cnt repeat the last arc so that every load is issued unconditionally
-    const int32_t jmax = A.narcs > 0 ? A.narcs - 1 : 0;   // r8 holds at least one block
-    auto fetch_a = [&](int32_t j0, int cnt, v4i (&a)[kMY]) {
+    // cnt repeat the last arc so that every load is issued unconditionally.
+    // Lane (col, half) loads row a = col of the arc as 32 bits; its matrix-core
+    // operand is the 16 bytes 0/1 of bits 16*half .. 16*half+15 (expand_a).
+    const int32_t jmax = A.narcs > 0 ? A.narcs - 1 : 0;   // r1 holds at least one block
+    auto fetch_a = [&](int32_t j0, int cnt, uint32_t (&a)[kMY]) {
         const int last = cnt > 0 ? cnt - 1 : 0;
 #pragma unroll
         for (int l = 0; l < kMY; ++l) {
             int32_t j = j0 + (l < last ? l : last);
             j = j < jmax ? j : jmax;
-            a[l] = *reinterpret_cast<const v4i *>(A.r8 + (int64_t)j * 1024 + col * 32 + half * 16);
+            a[l] = A.r1[(int64_t)j * 32 + col];
         }
+    };
+    auto expand_a = [&](uint32_t row) {
+        const uint32_t h = row >> (16 * half);
+        v4i v;
+        v.x = (int)spread4(h & 0xFu);
+        v.y = (int)spread4((h >> 4) & 0xFu);
+        v.z = (int)spread4((h >> 8) & 0xFu);
+        v.w = (int)spread4((h >> 12) & 0xFu);
+        return v;
     };
 
     v16i rm[kMSub];
@@ -207,7 +222,7 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
         for (int v = 0; v < 16; ++v) rm[t][v] = 0x7FFFFFFF;
 
     v4i breg[4];
-    v4i acur[kMY], anext[kMY];
+    uint32_t acur[kMY], anext[kMY];
     // neighbour tables are read two blocks ahead, operands one block ahead
     auto jtab = [&](int b) { return xv ? bst[b < nblk ? b : nblk - 1] : 0; };
     auto mtab = [&](int b) { return xv ? bmk[b < nblk ? b : nblk - 1] : 0u; };
@@ -261,23 +276,27 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
             lds_b(0, 0, bn0, bn1);
             v16i cp0 = zero, cp1 = zero;
 #pragma unroll
-            for (int u = 0; u < 2 * kMY; ++u) {
-                const int q = u >> 2, t = u & 3;
+            for (int q = 0; q < kMY / 2; ++q) {
                 if (q >= npairs) break;
-                const v4i b0 = bn0, b1 = bn1;
-                if (u + 1 < 2 * kMY) {
-                    const int qn = ((u + 1) >> 2) < npairs ? ((u + 1) >> 2) : npairs - 1;
-                    lds_b(qn, (u + 1) & 3, bn0, bn1);
+                const v4i a0 = expand_a(acur[2 * q]), a1 = expand_a(acur[2 * q + 1]);
+#pragma unroll
+                for (int t = 0; t < kMSub; ++t) {
+                    const int u = q * kMSub + t;
+                    const v4i b0 = bn0, b1 = bn1;
+                    if (u + 1 < 2 * kMY) {
+                        const int qn = ((u + 1) >> 2) < npairs ? ((u + 1) >> 2) : npairs - 1;
+                        lds_b(qn, (u + 1) & 3, bn0, bn1);
+                    }
+                    const v16i c0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, zero, 0, 0, 0);
+                    const v16i c1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, zero, 0, 0, 0);
+                    // keep the compiler from moving the fold next to the
+                    // products it would then wait for
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (u > 0) fold(rm[(u - 1) & 3], cp0, cp1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    cp0 = c0;
+                    cp1 = c1;
                 }
-                const v16i c0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(acur[2 * q], b0, zero, 0, 0, 0);
-                const v16i c1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(acur[2 * q + 1], b1, zero, 0, 0, 0);
-                // keep the compiler from moving the fold next to the products
-                // it would then wait for
-                __builtin_amdgcn_sched_barrier(0);
-                if (u > 0) fold(rm[(u - 1) & 3], cp0, cp1);
-                __builtin_amdgcn_sched_barrier(0);
-                cp0 = c0;
-                cp1 = c1;
             }
             fold(rm[kMSub - 1], cp0, cp1);   // a pair's last unit is sub-tile 3
         }
@@ -519,11 +538,11 @@ __global__ void mfma_pack_kernel(MArgs A) {
     }
 }
 
-// Relation blocks in the matrix-core layout: out[j][a][b] for the arcs in
-// neighbour-sorted order (src_sorted[j] = 2e + flip), 32 x 32 bytes, zero
-// beyond d.
-__global__ void mfma_pack_r8_kernel(const uint64_t *rel, const int32_t *src_sorted, int64_t arcs,
-                                    int32_t d, int8_t *out) {
+// Relation rows in the matrix-core layout: out[j][a] = row a of arc j as
+// bits (bit b: (a,b) allowed), arcs in neighbour-sorted order (src_sorted[j]
+// = 2e + flip), 32 rows per arc, zero beyond d.
+__global__ void mfma_pack_r1_kernel(const uint64_t *rel, const int32_t *src_sorted, int64_t arcs,
+                                    int32_t d, uint32_t *out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // one row per thread
     if (i >= arcs * 32) return;
     const int64_t j = i >> 5;
@@ -538,16 +557,7 @@ __global__ void mfma_pack_r8_kernel(const uint64_t *rel, const int32_t *src_sort
             for (int b = 0; b < d; ++b) row |= ((R[b] >> a) & 1ull) << b;
         }
     }
-    uint32_t w[8];
-    for (int q = 0; q < 8; ++q) {
-        uint32_t v = 0;
-        for (int t = 0; t < 4; ++t)
-            if ((row >> (4 * q + t)) & 1ull) v |= 1u << (8 * t);
-        w[q] = v;
-    }
-    uint4 *dst = reinterpret_cast<uint4 *>(out + j * 1024 + (int64_t)a * 32);
-    dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
-    dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    out[i] = (uint32_t)row;
 }
 
 // ---------------------------------------------------------------------------
@@ -565,7 +575,7 @@ __global__ void mfma_pack_r8_kernel(const uint64_t *rel, const int32_t *src_sort
 struct MfmaImpl {
     int32_t *row_ptr = nullptr, *nbr_s = nullptr;
     const int32_t *deg = nullptr;
-    int8_t *r8 = nullptr;
+    uint32_t *r1 = nullptr;
     int32_t *bstart = nullptr;
     uint32_t *bmask = nullptr;
     int32_t nblk = 0;
@@ -602,7 +612,7 @@ void mfma_release(MfmaData &md) {
     if (!m) return;
     mfree(m->row_ptr);
     mfree(m->nbr_s);
-    mfree(m->r8);
+    mfree(m->r1);
     mfree(m->bstart);
     mfree(m->bmask);
     mfree(m->dom8[0]);
@@ -694,15 +704,15 @@ int mfma_ensure(MfmaData &md, int32_t n, int32_t d, int64_t arcs, const int32_t 
     int32_t *d_src = nullptr;
     HIP_OK(hipMalloc(&m->row_ptr, ((size_t)n + 1) * 4));
     HIP_OK(hipMalloc(&m->nbr_s, std::max<size_t>(1, (size_t)arcs) * 4));
-    HIP_OK(hipMalloc(&m->r8, std::max<size_t>(1, (size_t)arcs) * 1024));
+    HIP_OK(hipMalloc(&m->r1, std::max<size_t>(1, (size_t)arcs) * 128));
     HIP_OK(hipMalloc(&d_src, std::max<size_t>(1, (size_t)arcs) * 4));
     HIP_OK(hipMemcpy(m->row_ptr, row_ptr, ((size_t)n + 1) * 4, hipMemcpyDeviceToDevice));
     if (arcs > 0) {
         HIP_OK(hipMemcpy(m->nbr_s, nbr_s.data(), (size_t)arcs * 4, hipMemcpyHostToDevice));
         HIP_OK(hipMemcpy(d_src, src_s.data(), (size_t)arcs * 4, hipMemcpyHostToDevice));
         const int64_t threads = arcs * 32;
-        hipLaunchKernelGGL(mfma_pack_r8_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
-                           stream, rel, d_src, arcs, d, m->r8);
+        hipLaunchKernelGGL(mfma_pack_r1_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
+                           stream, rel, d_src, arcs, d, m->r1);
         HIP_OK(hipGetLastError());
         HIP_OK(hipStreamSynchronize(stream));
     }
@@ -772,7 +782,7 @@ static MArgs make_args(MfmaData &md, int32_t B, const uint64_t *din, uint64_t *d
     A.row_ptr = m->row_ptr;
     A.nbr_s = m->nbr_s;
     A.deg = m->deg;
-    A.r8 = m->r8;
+    A.r1 = m->r1;
     A.bstart = m->bstart;
     A.bmask = m->bmask;
     A.nblk = m->nblk;
