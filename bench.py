@@ -30,6 +30,120 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 matrix-core peak, TOP/s
 
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "traffic.json")
+CSRC = os.path.join(ROOT, "paper_2407_11388_amd", "csrc")
+
+
+# Sources whose change invalidates the recorded traffic of a kernel.
+KERNEL_SOURCES = {"mfma_sweep_kernel": ["mfma.hip", "rac_mfma.h"],
+                  "revise_kernel": ["sweep.hip", "rac_internal.h", "rac_host.hip"]}
+
+
+def kernel_digest(kernel: str) -> str:
+    """sha256 over a kernel's sources; measured traffic is only reported while
+    it matches the digest recorded with the counters."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(name: str):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) of profile
+    entry `name`, or None if absent or taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            e = json.load(f)[name]
+    except (OSError, KeyError, ValueError):
+        return None
+    if e.get("sha256") != kernel_digest(e["kernel"]):
+        return None
+    return e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
+
+
+def profile_report(args):
+    """Summarises rocprofv3 output (kernel-trace stats plus FETCH_SIZE and
+    WRITE_SIZE runs, and the same two counters for a 1 GiB copy) into
+    profiles/<name>.txt and the traffic table. CPU only."""
+    import csv
+    from collections import defaultdict
+    name, kernel, trace_dir, fdir, wdir, cfdir, cwdir = args.profile_report
+
+    def counters(d):
+        out = defaultdict(list)
+        for fn in os.listdir(d):
+            if fn.endswith("counter_collection.csv"):
+                with open(os.path.join(d, fn)) as f:
+                    for r in csv.DictReader(f):
+                        out[r["Kernel_Name"].split("(")[0].split("::")[-1]].append(
+                            float(r["Counter_Value"]))
+        return out
+
+    def stats(d):
+        for fn in os.listdir(d):
+            if fn.endswith("kernel_stats.csv"):
+                with open(os.path.join(d, fn)) as f:
+                    return list(csv.DictReader(f))
+        return []
+
+    cf, cw = counters(cfdir), counters(cwdir)
+    copy_kib = args.copy_bytes / 1024.0
+    fscale = copy_kib / cf["__amd_rocclr_copyBuffer"][0]
+    wscale = copy_kib / cw["__amd_rocclr_copyBuffer"][0]
+    fv, wv = counters(fdir)[kernel], counters(wdir)[kernel]
+    top = max(fv)
+    work = [i for i, v in enumerate(fv) if v > 0.01 * top]   # launches that had work
+    fb = sum(fv[i] for i in work) / len(work) * 1024 * fscale
+    wb = sum(wv[i] for i in work) / len(work) * 1024 * wscale
+    rows = stats(trace_dir)
+    lines = [f"# {name}: rocprofv3 summary of {kernel}", ""]
+    lines += ["Commands (from the repository root; rocprofv3 run with TMPDIR=/tmp):", ""]
+    lines += [f"    {c}" for c in args.profile_command] + [""]
+    lines += ["Kernel statistics (--kernel-trace --stats):", "",
+              "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in rows[:10]:
+        lines.append(f"| {r['Name'].split('(')[0]} | {r['Calls']} | {float(r['AverageNs'])/1e3:.1f} | "
+                     f"{float(r['MinNs'])/1e3:.1f} | {float(r['MaxNs'])/1e3:.1f} | "
+                     f"{float(r['Percentage']):.1f} |")
+    krow = next((r for r in rows if r["Name"].split("(")[0].endswith(kernel)), None)
+    lines += ["", f"HBM traffic of {kernel} (--pmc FETCH_SIZE, then --pmc WRITE_SIZE):", "",
+              f"* launches with work: {len(work)} of {len(fv)}",
+              f"* FETCH_SIZE per launch: {sum(fv[i] for i in work)/len(work):.0f} KiB raw, x {fscale:.4f} = {fb/1e6:.1f} MB",
+              f"* WRITE_SIZE per launch: {sum(wv[i] for i in work)/len(work):.0f} KiB raw, x {wscale:.4f} = {wb/1e6:.1f} MB",
+              f"* calibration: a {args.copy_bytes} B device copy reads {cf['__amd_rocclr_copyBuffer'][0]:.0f} KiB "
+              f"FETCH_SIZE and {cw['__amd_rocclr_copyBuffer'][0]:.0f} KiB WRITE_SIZE",
+              ]
+    if krow:
+        lines.append(f"* average launch duration (all launches): {float(krow['AverageNs'])/1e3:.1f} us")
+    durs = []
+    for fn in os.listdir(trace_dir):
+        if fn.endswith("kernel_trace.csv"):
+            with open(os.path.join(trace_dir, fn)) as f:
+                for r in csv.DictReader(f):
+                    if r["Kernel_Name"].split("(")[0].endswith(kernel):
+                        durs.append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    if durs:
+        busy = [t for t in durs if t > 0.1 * max(durs)]
+        lines.append(f"* average duration of the launches with work ({len(busy)} of {len(durs)}, "
+                     f"longer than 10% of the longest): {sum(busy) / len(busy) / 1e3:.1f} us")
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(os.path.join(PROFILES, name + ".txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    table = {}
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            table = json.load(f)
+    table[name] = dict(kernel=kernel, fetch_bytes_per_launch=fb, write_bytes_per_launch=wb,
+                       fetch_scale=fscale, write_scale=wscale, launches=len(work),
+                       sha256=kernel_digest(kernel))
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+        f.write("\n")
+    print("\n".join(lines))
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -50,6 +164,14 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES (to calibrate the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--profile-report", nargs=7, default=None,
+                    metavar=("NAME", "KERNEL", "TRACE_DIR", "FETCH_DIR", "WRITE_DIR",
+                             "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="CPU only: summarise rocprofv3 output into profiles/NAME.txt and "
+                         "profiles/traffic.json")
+    ap.add_argument("--profile-command", action="append", default=[],
+                    help="command line recorded in the profile summary (repeatable)")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     return ap.parse_args()
 
 
@@ -108,6 +230,9 @@ def cpu_baseline_single(inst, dom, budget_s):
 
 def main():
     args = parse()
+    if args.profile_report:
+        profile_report(args)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the batched "
               "states and instances shard across GPUs without communication, but this "
@@ -199,7 +324,8 @@ def main():
             roofline=dict(kernel="mfma_sweep_kernel", bound="mfma", achieved=achieved,
                           peak=INT8_PEAK_TOPS, unit="TOP/s",
                           frac=(achieved / INT8_PEAK_TOPS) if achieved else None,
-                          traffic=None, launches=klaunch,
+                          traffic=recorded_traffic("mfma_sweep_kernel_batch_states"),
+                          launches=klaunch,
                           avg_launch_ms=kms / klaunch if klaunch else None,
                           per_unit="2*d*d int8 ops per (arc, active state, step)"),
         )
@@ -225,9 +351,10 @@ def main():
         out.update(value=st.support_checks / t, ms_per_step=t * 1e3, dtype="u32 bit rows",
                    config=dict(workload=w.name, path="bits"),
                    fixpoints_per_s=1.0 / t, host_ms_per_call=t_host / args.steps * 1e3,
-                   roofline=dict(kernel="sweep_kernel", bound="hbm", achieved=gbs,
+                   roofline=dict(kernel="revise_kernel", bound="hbm", achieved=gbs,
                                  peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS,
-                                 traffic=None, per_unit="relation bytes of every re-examined arc"))
+                                 traffic=recorded_traffic(f"revise_kernel_{args.workload.replace('-', '_')}"),
+                                 per_unit="relation bytes of every re-examined arc"))
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline_single(inst, dom, args.cpu_seconds)
         net.close()
@@ -262,7 +389,7 @@ def main():
                 best = min(best, stg.kernel_ms)
                 best_dev = min(best_dev, stg.device_ms)
             gbs = stg.relation_bytes / (best * 1e-3) / 1e9
-            sec["uneven-multi 256 instances (one persistent launch)"] = dict(
+            sec["uneven-multi 256 instances (shared step kernels)"] = dict(
                 kernel_ms=best, device_ms=best_dev, fixpoints_per_s=len(nets) / (best_dev * 1e-3),
                 relation_bytes=int(stg.relation_bytes), relation_GBs_per_first_step=gbs,
                 support_checks_per_s=stg.support_checks / (best_dev * 1e-3),

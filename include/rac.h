@@ -12,8 +12,9 @@
  * removes nothing (Proposition 1). After the first step only constraints into
  * variables whose domain changed in the previous step are re-examined
  * (Proposition 2; Algorithm 1's @changed). On a GPU each step is one pass over
- * the relation rows with a device-side change flag, so no host round trip
- * happens between steps.
+ * the relation rows; per-problem change and wipe-out words stay on the
+ * device, and the host enqueues steps in rounds of 4, 8, 16, ... (captured
+ * HIP graphs), reading one counter per round instead of one per step.
  *
  * Conventions shared by every entry point
  *   Domains    uint64 per variable: bit a is set iff a is in dom(x). Bits >= d
@@ -62,7 +63,7 @@ enum {
     RAC_EUNSUPPORTED = -4,    /* valid input outside what a path supports */
     RAC_ENOTCONVERGED = -5,   /* max_sweeps reached while values were still being removed */
     RAC_ENODEV = -6,          /* no usable gfx950 device */
-    RAC_ETIMEOUT = -7         /* the device scheduler's bounded wait expired (internal error) */
+    RAC_ETIMEOUT = -7         /* reserved (no current code path returns it) */
 };
 
 enum { RAC_CONSISTENT = 0, RAC_WIPEOUT = 1 };
@@ -95,8 +96,8 @@ typedef struct rac_stats {
     int64_t relation_bytes;  /* relation bytes the kernels were asked to stream */
     double device_ms;        /* device time of the enforcement kernels (HIP events) */
     double kernel_ms;        /* with options.profile: summed duration of the dominant
-                                kernel's launches that had work (persistent sweep kernel,
-                                or the matrix-core step kernel) */
+                                kernel's launches that had work (the revise kernel of each
+                                executed step, or the matrix-core step kernel) */
     int64_t kernel_launches; /* with options.profile: number of those launches */
     int64_t algo_ops;        /* algorithmic int8 operations of the matrix-core step kernel:
                                 2*d*d per (arc, active state, step); 0 on other paths */
@@ -159,9 +160,10 @@ int rac_enforce_batch(rac_net *net, int32_t B, uint64_t *dom, int32_t *iters, in
  * Device-pointer form of rac_enforce_batch: d_dom_in [B][n] and d_dom_out
  * [B][n] uint64 (may be the same buffer), d_iters and d_status [B] int32, all
  * in device memory of the net's device; enqueued on `stream` (a hipStream_t,
- * NULL = the null stream). Returns after enqueueing; per-call errors detected
- * on the device (max_sweeps reached, scheduler timeout) are reported by the
- * next call or by rac_sync_status().
+ * NULL = the null stream). The call waits on the stream between rounds of
+ * steps (to read how many states are still running) and returns once the
+ * last kernels are enqueued; per-call errors detected on the device
+ * (max_sweeps reached) are reported by the next call or by rac_sync_status().
  */
 int rac_enforce_batch_device(rac_net *net, int32_t B, const uint64_t *d_dom_in,
                              uint64_t *d_dom_out, int32_t *d_iters, int32_t *d_status,
@@ -172,7 +174,8 @@ int rac_sync_status(rac_net *net);
 
 /*
  * Many independent networks of uneven n, d and density, one domain state
- * each, enforced together in one persistent launch. dom[i] is [n_i] host
+ * each, enforced together: every step of every network runs in the same
+ * kernels (one captured graph per round of steps). dom[i] is [n_i] host
  * uint64 for nets[i], in/out; iters, status: [k] host int32 (may be NULL).
  * Equivalent to k calls of rac_enforce, each with @changed = all.
  */

@@ -1,6 +1,6 @@
 // Host side of librac: the C ABI of rac.h, input validation, the CSR arc
 // layout, device-side packing of relation rows, work items, and the launch of
-// the persistent fixpoint kernel (directly or as a replayed HIP graph).
+// the per-step fixpoint kernels (directly, or as replayed HIP graphs of rounds of steps).
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
@@ -1003,7 +1003,7 @@ extern "C" int rac_enforce(rac_net *net, uint64_t *dom, const int32_t *changed, 
 }
 
 // States still active when at most this many remain leave the matrix-core
-// path and finish on the persistent bit-row path, whose incremental steps
+// path and finish on the bit-row path, whose incremental steps
 // touch only arcs into changed variables.
 static int32_t mfma_handoff_threshold() {
     const char *e = getenv("RAC_MFMA_HANDOFF");

@@ -234,7 +234,8 @@ class Net:
 
 
 class Group:
-    """Several networks enforced together in one persistent launch."""
+    """Several networks enforced together: every step of every network runs in the
+    same kernels (captured graphs, one per round of steps)."""
 
     def __init__(self, nets: Sequence[Net], **kw):
         self.nets = list(nets)
