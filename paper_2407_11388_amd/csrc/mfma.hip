@@ -43,7 +43,6 @@ constexpr int kMSub = 4;          // 32-state sub-tiles per wave
 constexpr int kMS = 32 * kMSub;   // states per workgroup
 constexpr int kMY = 8;            // neighbours per LDS block
 constexpr int kMThreads = 64 * kMX;
-constexpr int kMaxChunk = 16;     // steps enqueued per group of steps
 
 // 4 bits -> 4 bytes holding 0/1 (bit i of v becomes byte i). The factor places
 // copies of v 7 bits apart, so no two copies overlap and no carry occurs.
@@ -58,30 +57,58 @@ struct MState {
 };
 
 struct MArgs {
-    int32_t n, d, N32;                // N32 = n * 32 bytes per state
+    int32_t n, d, capB;               // capB: state slots of the domain buffers
     const int32_t *row_ptr;           // [n+1] arcs of x, sorted by neighbour
     const int32_t *nbr_s;             // [arcs]
     const int32_t *deg;               // [n]
-    const uint32_t *r1;               // [arcs][32] row a of each arc as bits (bit b: (a,b) allowed)
+    const uint32_t *r1;               // [arcs + kMY][32] row a of each arc as bits (bit b: (a,b)
+                                      // allowed); kMY zero arcs of padding at the end
     const int32_t *bstart;            // [n][nblk+1] first arc of x with neighbour >= 8*b
     const uint32_t *bmask;            // [n][nblk] bit l: x is constrained with y = 8*b + l
                                       // (32-bit words, so that scalar loads read them)
     int32_t nblk;                     // ceil(n / 8)
-    int32_t narcs;                    // number of arcs (blocks of r1)
-    int8_t *dom8[2];                  // [capB][N32]
+    int32_t narcs;                    // number of arcs
+    int8_t *dom8[2];                  // [n][2][capB][16]: bytes 16h .. 16h+15 of the 0/1 domain
+                                      // of (x, state slot); [0]: the current step's input,
+                                      // [1]: its output (same slot order)
     uint32_t *chg, *wipe;             // [n][words]
     int32_t words;                    // capB / 32
     int32_t *act[2];                  // active state lists (by step parity)
     int32_t *prev_slot[2];            // slot each listed state had in the previous step
+    int32_t *slot_map;                // [capB] old slot -> new slot, or -1 when the state stopped
     int32_t *cnt;                     // [2] active counts
     MState *st;                       // [capB]
     int32_t mode, max_sweeps, B, xcd_map;
     long long checks1;                // support checks of step 1: 2m * d * d
     const uint64_t *din;              // [B][n]
-    uint64_t *dout;                   // [B][n]
+    uint64_t *dout;                   // [B][n] (written as states stop)
     int32_t *iters_out, *status_out, *rc_out;
     long long *checks_out;
 };
+
+// Byte offset of the 16 domain bytes (x, half h, slot) in a domain buffer.
+__device__ __forceinline__ int64_t dom_off(const MArgs &A, int32_t x, int h, int32_t slot) {
+    return (((int64_t)x * 2 + h) * A.capB + slot) * 16;
+}
+
+// 32 domain bytes (two 16-byte halves) -> bit mask, and back.
+__device__ __forceinline__ uint64_t bytes_to_mask(const uint4 lo, const uint4 hi) {
+    const uint32_t w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    uint64_t m = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if ((w[q] >> (8 * t)) & 0xFFu) m |= 1ull << (4 * q + t);
+    return m;
+}
+__device__ __forceinline__ void mask_to_bytes(uint64_t m, uint4 &lo, uint4 &hi) {
+    uint32_t w[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) w[q] = spread4((uint32_t)(m >> (4 * q)) & 0xFu);
+    lo = make_uint4(w[0], w[1], w[2], w[3]);
+    hi = make_uint4(w[4], w[5], w[6], w[7]);
+}
 
 // ---------------------------------------------------------------------------
 
@@ -90,19 +117,12 @@ __global__ void mfma_init_kernel(MArgs A) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = tid; i < total; i += nth) {
-        const int64_t s = i / A.n;
-        const int32_t x = (int32_t)(i - s * A.n);
-        const uint64_t dm = A.din[i];
-        uint32_t w[8];
-        for (int q = 0; q < 8; ++q) {
-            uint32_t v = 0;
-            for (int t = 0; t < 4; ++t)
-                if ((dm >> (4 * q + t)) & 1ull) v |= 1u << (8 * t);
-            w[q] = v;
-        }
-        uint4 *dst = reinterpret_cast<uint4 *>(A.dom8[0] + s * A.N32 + (int64_t)x * 32);
-        dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
-        dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+        const int32_t x = (int32_t)(i / A.B);
+        const int32_t s = (int32_t)(i - (int64_t)x * A.B);   // slot = state in step 1
+        uint4 lo, hi;
+        mask_to_bytes(A.din[(int64_t)s * A.n + x], lo, hi);
+        *reinterpret_cast<uint4 *>(A.dom8[0] + dom_off(A, x, 0, s)) = lo;
+        *reinterpret_cast<uint4 *>(A.dom8[0] + dom_off(A, x, 1, s)) = hi;
     }
     for (int64_t s = tid; s < A.B; s += nth) {
         MState &m = A.st[s];
@@ -123,11 +143,37 @@ __global__ void mfma_init_kernel(MArgs A) {
     }
 }
 
+// One wave-uniform 32-bit word through the scalar cache (read-only data).
+// The kernel's LDS copies keep the compiler from proving the neighbour tables
+// unmodified, and a vector load would wait for every copy in flight; this
+// load only waits for the scalar and LDS counter.
+__device__ __forceinline__ uint32_t sload_u32(const void *p) {
+    // readfirstlane returns a signed int: go through uint32_t so that the low
+    // word is zero-extended (sign extension would corrupt the high word)
+    const uint64_t a = (uint64_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+    const uint64_t u = (uint64_t)lo | ((uint64_t)hi << 32);
+    uint32_t v;
+    asm volatile("s_load_dword %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(u) : "memory");
+    return v;
+}
+
+// Direct global -> LDS copy of 16 bytes per lane: lane i writes lds + 16*i.
+__device__ __forceinline__ void dma16(const void *g, void *lds) {
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)g,
+                                     (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
+}
+
+constexpr int kStages = 3;                          // LDS ring depth (loads run 2 blocks ahead)
+constexpr int kBTile = kMY * 2 * kMS;               // v4i per domain tile (32 KiB)
+constexpr int kATile = kMX * kMY * 32 / 4;          // v4i per relation tile (8 KiB)
+constexpr size_t kMSmem = (size_t)kStages * (kBTile + kATile) * 16;   // 120 KiB
+constexpr int kDmaPerBlock = kMY * 2 * kMS / 64 / kMX + 1;           // per wave: 4 + 1
+
 __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
-    // [buffer][neighbour][half][state]: bytes 16*half .. 16*half+15 of the
-    // domain column of one state, so the 64 lanes of a B-operand read cover
-    // 1 KiB contiguously (no bank conflicts)
-    __shared__ v4i s_b[2][kMY][2][kMS];   // 2 x 32 KiB
+    extern __shared__ v4i s_lds[];   // kStages x {domain tile [kMY][2][kMS], relation tile
+                                     // [kMX waves][kMY arcs][32 rows] uint32}
     const int nact = A.cnt[(k - 1) & 1];
     // workgroup -> (x-tile, state tile); the state tiles of one x-tile share
     // blockIdx % 8 and so an XCD
@@ -146,65 +192,15 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
     if (st0 >= nact || xt * kMX >= A.n) return;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int32_t *act = A.act[(k - 1) & 1];
-    auto state_of = [&](int i) { return st0 + i < nact ? act[st0 + i] : -1; };
-
     const int x = xt * kMX + wave;
     const bool xv = x < A.n;                // wave-uniform
     const int nblk = A.nblk;
     const int32_t *bst = A.bstart + (int64_t)(xv ? x : 0) * (nblk + 1);
     const uint32_t *bmk = A.bmask + (int64_t)(xv ? x : 0) * nblk;
-    const int8_t *dcur = A.dom8[(k - 1) & 1];
+    const int8_t *din = A.dom8[0];
     const int half = lane >> 5, col = lane & 31;
-
-    // B staging. The domain bytes of one state for the 8 neighbours of a
-    // block are 256 consecutive bytes; 16 lanes read them as 16-byte chunks
-    // (chunk j: neighbour j >> 1, half j & 1), so a wave's load covers 4
-    // states' rows. Thread t moves chunk t & 15 of state slots (t >> 4) + 32i,
-    // i = 0..3. Every load is issued: a slot past the active states reads a
-    // valid state (its products are never used) and a neighbour past n reads
-    // variable n-1's bytes (never a neighbour of anything).
-    const int b_j = tid & 15, b_yl = b_j >> 1, b_h = b_j & 1;
-    const int8_t *b_src[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int sl = (tid >> 4) + 32 * i;
-        const int st = act[st0 + sl < nact ? st0 + sl : nact - 1];
-        b_src[i] = dcur + (int64_t)st * A.N32 + b_h * 16;
-    }
-    // LDS slot of (neighbour yl, half h, state slot sl): the slot index is
-    // XOR-ed with 2*yl + h so that the 16 lanes writing one state's chunks hit
-    // 16 different bank groups; readers of one (yl, h) apply the same XOR to
-    // 32 consecutive slots, which permutes them within 16-slot groups.
-    auto bslot = [](int yl, int h, int sl) { return sl ^ ((2 * yl + h) & 15); };
-    auto fetch_b = [&](int yb, v4i (&r)[4]) {
-        int y = yb + b_yl;
-        y = y < A.n ? y : A.n - 1;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) r[i] = *reinterpret_cast<const v4i *>(b_src[i] + (int64_t)y * 32);
-    };
-    auto store_b = [&](int buf, const v4i (&r)[4]) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int sl = (tid >> 4) + 32 * i;
-            s_b[buf][b_yl][b_h][bslot(b_yl, b_h, sl)] = r[i];
-        }
-    };
-    // relation blocks of this wave's arcs in one neighbour block: the block's
-    // arcs are consecutive (sorted by neighbour), j0 .. j0+cnt-1; slots past
-    // cnt repeat the last arc so that every load is issued unconditionally.
-    // Lane (col, half) loads row a = col of the arc as 32 bits; its matrix-core
-    // operand is the 16 bytes 0/1 of bits 16*half .. 16*half+15 (expand_a).
-    const int32_t jmax = A.narcs > 0 ? A.narcs - 1 : 0;   // r1 holds at least one block
-    auto fetch_a = [&](int32_t j0, int cnt, uint32_t (&a)[kMY]) {
-        const int last = cnt > 0 ? cnt - 1 : 0;
-#pragma unroll
-        for (int l = 0; l < kMY; ++l) {
-            int32_t j = j0 + (l < last ? l : last);
-            j = j < jmax ? j : jmax;
-            a[l] = A.r1[(int64_t)j * 32 + col];
-        }
-    };
+    // the matrix-core operand of lane (col, half) for an arc: row a = col,
+    // bits 16*half .. 16*half+15 as 16 bytes of 0/1
     auto expand_a = [&](uint32_t row) {
         const uint32_t h = row >> (16 * half);
         v4i v;
@@ -215,40 +211,57 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
         return v;
     };
 
+    // Loads of block `blk` into ring stage `stg`, all direct to LDS (no
+    // registers): the domain tile is 16 rows (neighbour yl, half h) of 128
+    // consecutive slots, 2 KiB each in both memories; wave w copies rows 2w
+    // and 2w+1 as 1 KiB halves. A neighbour past n copies variable n-1's row
+    // (never a neighbour of anything); slots past the active ones are in the
+    // buffer and never used. The relation tile of a wave is the 8 arcs from
+    // the block's first arc (1 KiB; arcs past the block or past the last arc,
+    // where kMY zero arcs pad the array, are never used).
+    auto issue = [&](int stg, int blk) {
+        v4i *bt = s_lds + stg * (kBTile + kATile);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = wave * 2 + (i >> 1), part = i & 1;
+            const int yl = row >> 1, h = row & 1;
+            int y = blk * kMY + yl;
+            y = y < A.n ? y : A.n - 1;
+            dma16(din + dom_off(A, y, h, st0 + part * 64 + lane), bt + (yl * 2 + h) * kMS + part * 64);
+        }
+        const int32_t j0 = (int32_t)sload_u32(bst + blk);
+        dma16(A.r1 + ((int64_t)j0 * 32 + lane * 4), bt + kBTile + wave * (kMY * 32 / 4));
+    };
+    // waits until this wave's loads of the next block are in LDS (the loads of
+    // the block after it may stay in flight), and its LDS reads are done;
+    // then the workgroup barrier makes every wave's copies visible
+    auto ring_sync = [&]() {
+        asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(kDmaPerBlock) : "memory");
+    };
+
     v16i rm[kMSub];
 #pragma unroll
     for (int t = 0; t < kMSub; ++t)
 #pragma unroll
         for (int v = 0; v < 16; ++v) rm[t][v] = 0x7FFFFFFF;
 
-    v4i breg[4];
-    uint32_t acur[kMY], anext[kMY];
-    // neighbour tables are read two blocks ahead, operands one block ahead
-    auto jtab = [&](int b) { return xv ? bst[b < nblk ? b : nblk - 1] : 0; };
-    auto mtab = [&](int b) { return xv ? bmk[b < nblk ? b : nblk - 1] : 0u; };
-    uint32_t mcur = mtab(0);
-    int32_t jnext = jtab(1);
-    uint32_t mnext = mtab(1);
-    fetch_b(0, breg);
-    fetch_a(jtab(0), __builtin_popcount(mcur), acur);
-    store_b(0, breg);
-    __syncthreads();
+    issue(0, 0);
+    issue(1, nblk > 1 ? 1 : 0);
+    ring_sync();
     for (int blk = 0; blk < nblk; ++blk) {
-        const int buf = blk & 1;
-        // next block's operands, in flight during this block's products (the
-        // last block re-reads itself: harmless, never used)
-        const int bn = blk + 1 < nblk ? blk + 1 : blk;
-        const int32_t jnn = jtab(blk + 2);
-        const uint32_t mnn = mtab(blk + 2);
-        fetch_b(bn * kMY, breg);
-        fetch_a(jnext, __builtin_popcount(mnext), anext);
+        // the block two ahead (past the end: a repeat of the last block into
+        // the stage no one reads any more)
+        issue((blk + 2) % kStages, blk + 2 < nblk ? blk + 2 : nblk - 1);
+        const v4i *bt = s_lds + (blk % kStages) * (kBTile + kATile);
+        const uint32_t *at = reinterpret_cast<const uint32_t *>(bt + kBTile) + wave * (kMY * 32);
+        const uint32_t mcur = xv ? sload_u32(bmk + blk) : 0u;
 
         // products of this block's arcs, two at a time: a fresh accumulator
         // per arc, folded into the running minimum with one min3 per value.
-        // An odd last arc is paired with itself. Units u = 4*pair + sub-tile
-        // are software-pipelined: the LDS operands of unit u+1 are read and
-        // the products of unit u issued before the minimum of unit u-1 is
-        // folded, so the fold overlaps the matrix-core work.
+        // An odd last arc is paired with itself. Units u = pair * kMSub +
+        // sub-tile are software-pipelined: the LDS operands of unit u+1 are
+        // read and the products of unit u issued before the minimum of unit
+        // u-1 is folded.
         const int cnt = __builtin_popcount(mcur);
         const int npairs = (cnt + 1) >> 1;
         int l0[kMY / 2], l1[kMY / 2];
@@ -264,8 +277,8 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
         }
         if (npairs > 0) {
             auto lds_b = [&](int q, int t, v4i &b0, v4i &b1) {
-                b0 = s_b[buf][l0[q]][half][bslot(l0[q], half, t * 32 + col)];
-                b1 = s_b[buf][l1[q]][half][bslot(l1[q], half, t * 32 + col)];
+                b0 = bt[(l0[q] * 2 + half) * kMS + t * 32 + col];
+                b1 = bt[(l1[q] * 2 + half) * kMS + t * 32 + col];
             };
             auto fold = [&](v16i &r, const v16i &c0, const v16i &c1) {
 #pragma unroll
@@ -278,59 +291,53 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
 #pragma unroll
             for (int q = 0; q < kMY / 2; ++q) {
                 if (q >= npairs) break;
-                const v4i a0 = expand_a(acur[2 * q]), a1 = expand_a(acur[2 * q + 1]);
+                const int ja = 2 * q, jb = 2 * q + 1 < cnt ? 2 * q + 1 : cnt - 1;
+                const v4i a0 = expand_a(at[ja * 32 + col]), a1 = expand_a(at[jb * 32 + col]);
 #pragma unroll
                 for (int t = 0; t < kMSub; ++t) {
                     const int u = q * kMSub + t;
                     const v4i b0 = bn0, b1 = bn1;
-                    if (u + 1 < 2 * kMY) {
-                        const int qn = ((u + 1) >> 2) < npairs ? ((u + 1) >> 2) : npairs - 1;
-                        lds_b(qn, (u + 1) & 3, bn0, bn1);
+                    if (u + 1 < kMY / 2 * kMSub) {
+                        const int qn = (u + 1) / kMSub < npairs ? (u + 1) / kMSub : npairs - 1;
+                        lds_b(qn, (u + 1) % kMSub, bn0, bn1);
                     }
                     const v16i c0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, zero, 0, 0, 0);
                     const v16i c1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, zero, 0, 0, 0);
                     // keep the compiler from moving the fold next to the
                     // products it would then wait for
                     __builtin_amdgcn_sched_barrier(0);
-                    if (u > 0) fold(rm[(u - 1) & 3], cp0, cp1);
+                    if (u > 0) fold(rm[(u - 1) % kMSub], cp0, cp1);
                     __builtin_amdgcn_sched_barrier(0);
                     cp0 = c0;
                     cp1 = c1;
                 }
             }
-            fold(rm[kMSub - 1], cp0, cp1);   // a pair's last unit is sub-tile 3
+            fold(rm[kMSub - 1], cp0, cp1);   // a pair's last unit is its last sub-tile
         }
-        store_b(buf ^ 1, breg);
-#pragma unroll
-        for (int l = 0; l < kMY; ++l) acur[l] = anext[l];
-        mcur = mnext;
-        mnext = mnn;
-        jnext = jnn;
-        __syncthreads();
+        ring_sync();
     }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // no copy may outlive the workgroup
 
     // epilogue: new domain bytes and per-state change / wipe-out masks
     if (!xv) return;
-    int8_t *dnext = A.dom8[k & 1];
+    int8_t *dnext = A.dom8[1];
 #pragma unroll
     for (int t = 0; t < kMSub; ++t) {
         const int slot = st0 + t * 32 + col;
-        const int s = state_of(t * 32 + col);
+        const bool live = slot < nact;
         bool changed = false, nonempty = false;
-        if (s >= 0) {
-            const int8_t *src = dcur + (int64_t)s * A.N32 + (int64_t)x * 32;
-            int8_t *dst = dnext + (int64_t)s * A.N32 + (int64_t)x * 32;
+        if (live) {
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                // rows a = 8g + 4*half + r, r = 0..3, are consecutive bytes
-                const int a0 = 8 * g + 4 * half;
-                const uint32_t old = *reinterpret_cast<const uint32_t *>(src + a0);
+                // rows a = 8g + 4*half + r, r = 0..3: bytes of half g/2 at 8(g%2) + 4*half
+                const int64_t off = dom_off(A, x, g >> 1, slot) + 8 * (g & 1) + 4 * half;
+                const uint32_t old = *reinterpret_cast<const uint32_t *>(din + off);
                 uint32_t keep = 0;
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     if (rm[t][4 * g + r] != 0) keep |= 0xFFu << (8 * r);
                 const uint32_t nw = old & keep;
-                *reinterpret_cast<uint32_t *>(dst + a0) = nw;
+                *reinterpret_cast<uint32_t *>(dnext + off) = nw;
                 changed |= nw != old;
                 nonempty |= nw != 0;
             }
@@ -342,15 +349,14 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
         const int other_nonempty = __shfl_xor((int)nonempty, 32, 64);
         changed = changed || other_changed != 0;
         nonempty = nonempty || other_nonempty != 0;
-        const bool wiped = s >= 0 && !nonempty;
-        const uint64_t mc = __ballot(changed && s >= 0);
+        const bool wiped = live && !nonempty;
+        const uint64_t mc = __ballot(changed && live);
         const uint64_t mw = __ballot(wiped);
         if (lane == 0) {
             const int w = (st0 + t * 32) >> 5;
             A.chg[(int64_t)x * A.words + w] = (uint32_t)mc;
             A.wipe[(int64_t)x * A.words + w] = (uint32_t)mw;
         }
-        (void)slot;
     }
 }
 
@@ -395,7 +401,8 @@ __global__ void mfma_reduce_kernel(MArgs A, int k) {
     }
 }
 
-// Algorithm 1's loop test per state, and the next step's active list.
+// Algorithm 1's loop test per state, the next step's active list, and the
+// map from this step's slots to the next step's.
 __global__ __launch_bounds__(1024) void mfma_finalize_kernel(MArgs A, int k) {
     __shared__ int32_t s_wave_tot[16];
     __shared__ int32_t s_base;
@@ -435,6 +442,7 @@ __global__ __launch_bounds__(1024) void mfma_finalize_kernel(MArgs A, int k) {
             nxt[off + pre] = s;
             A.prev_slot[k & 1][off + pre] = slot;
         }
+        if (slot < nact) A.slot_map[slot] = keep ? off + pre : -1;
         __syncthreads();
         if (threadIdx.x == 0) {
             int tot = 0;
@@ -444,6 +452,29 @@ __global__ __launch_bounds__(1024) void mfma_finalize_kernel(MArgs A, int k) {
         __syncthreads();
     }
     if (threadIdx.x == 0) A.cnt[k & 1] = s_base;
+}
+
+// After step k: the domains of the states that go on move to their new slots
+// in the input buffer; the states that stopped write their final domains.
+__global__ void mfma_gather_kernel(MArgs A, int k) {
+    const int nact = A.cnt[(k - 1) & 1];
+    const int32_t *act = A.act[(k - 1) & 1];
+    const int64_t total = (int64_t)nact * A.n;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = tid; i < total; i += nth) {
+        const int32_t x = (int32_t)(i / nact);
+        const int32_t slot = (int32_t)(i - (int64_t)x * nact);
+        const uint4 lo = *reinterpret_cast<const uint4 *>(A.dom8[1] + dom_off(A, x, 0, slot));
+        const uint4 hi = *reinterpret_cast<const uint4 *>(A.dom8[1] + dom_off(A, x, 1, slot));
+        const int32_t j = A.slot_map[slot];
+        if (j >= 0) {
+            *reinterpret_cast<uint4 *>(A.dom8[0] + dom_off(A, x, 0, j)) = lo;
+            *reinterpret_cast<uint4 *>(A.dom8[0] + dom_off(A, x, 1, j)) = hi;
+        } else {
+            A.dout[(int64_t)act[slot] * A.n + x] = bytes_to_mask(lo, hi);
+        }
+    }
 }
 
 // Hand the P states still active after step k to the bit-row path: their
@@ -460,23 +491,16 @@ __global__ void mfma_handoff_kernel(MArgs A, int k, uint64_t *bits, uint8_t *cha
         const int32_t x = (int32_t)(i - q * A.n);
         const int32_t s = A.act[k & 1][q];
         const int32_t slot = A.prev_slot[k & 1][q];
-        const uint32_t *src =
-            reinterpret_cast<const uint32_t *>(A.dom8[k & 1] + (int64_t)s * A.N32 + (int64_t)x * 32);
-        uint64_t dm = 0;
-        for (int w = 0; w < 8; ++w) {
-            const uint32_t v = src[w];
-            for (int t = 0; t < 4; ++t)
-                if ((v >> (8 * t)) & 0xFFu) dm |= 1ull << (4 * w + t);
-        }
-        bits[i] = dm;
+        const uint4 lo = *reinterpret_cast<const uint4 *>(A.dom8[0] + dom_off(A, x, 0, (int32_t)q));
+        const uint4 hi = *reinterpret_cast<const uint4 *>(A.dom8[0] + dom_off(A, x, 1, (int32_t)q));
+        bits[i] = bytes_to_mask(lo, hi);
         changed[i] = (uint8_t)((A.chg[(int64_t)x * A.words + (slot >> 5)] >> (slot & 31)) & 1u);
         if (x == 0) ids[q] = s;
     }
 }
 
 // Results of the bit-row path for the handed-off states: steps continue the
-// count of the matrix-core steps, and the final domains go back to the byte
-// buffer that the pack kernel reads.
+// count of the matrix-core steps, and the final domains go to the output.
 __global__ void mfma_merge_kernel(MArgs A, int k, const uint64_t *bits, const int32_t *ids,
                                   const int32_t *it, const int32_t *stt, const long long *chk,
                                   const int32_t *brc) {
@@ -488,47 +512,22 @@ __global__ void mfma_merge_kernel(MArgs A, int k, const uint64_t *bits, const in
         const int64_t q = i / A.n;
         const int32_t x = (int32_t)(i - q * A.n);
         const int32_t s = ids[q];
-        const int32_t kf = k + it[q];
-        const uint64_t dm = bits[i];
-        uint32_t w[8];
-        for (int qq = 0; qq < 8; ++qq) {
-            uint32_t v = 0;
-            for (int t = 0; t < 4; ++t)
-                if ((dm >> (4 * qq + t)) & 1ull) v |= 1u << (8 * t);
-            w[qq] = v;
-        }
-        uint4 *dst = reinterpret_cast<uint4 *>(A.dom8[kf & 1] + (int64_t)s * A.N32 + (int64_t)x * 32);
-        dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
-        dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+        A.dout[(int64_t)s * A.n + x] = bits[i];
         if (x == 0) {
             MState &m = A.st[s];
-            m.iters = kf;
+            m.iters = k + it[q];
             m.status = stt[q];
             m.checks += chk[q];
             m.rc = (*brc & 1) ? RAC_ENOTCONVERGED : 0;
-            m.done = (*brc & 2) ? 0 : 1;
+            m.done = 1;
         }
     }
 }
 
+// Per-state outputs (the domains were written as the states stopped).
 __global__ void mfma_pack_kernel(MArgs A) {
-    const int64_t total = (int64_t)A.B * A.n;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = tid; i < total; i += nth) {
-        const int64_t s = i / A.n;
-        const int32_t x = (int32_t)(i - s * A.n);
-        const int32_t it = A.st[s].iters;
-        const uint32_t *src =
-            reinterpret_cast<const uint32_t *>(A.dom8[it & 1] + s * A.N32 + (int64_t)x * 32);
-        uint64_t dm = 0;
-        for (int q = 0; q < 8; ++q) {
-            const uint32_t v = src[q];
-            for (int t = 0; t < 4; ++t)
-                if ((v >> (8 * t)) & 0xFFu) dm |= 1ull << (4 * q + t);
-        }
-        A.dout[i] = dm;
-    }
     for (int64_t s = tid; s < A.B; s += nth) {
         const MState &m = A.st[s];
         if (A.iters_out) A.iters_out[s] = m.iters;
@@ -584,6 +583,7 @@ struct MfmaImpl {
     uint32_t *chg = nullptr, *wipe = nullptr;
     int32_t *act[2] = {nullptr, nullptr};
     int32_t *prev_slot[2] = {nullptr, nullptr};
+    int32_t *slot_map = nullptr;
     int32_t *ids = nullptr;
     int32_t *cnt = nullptr;
     MState *st = nullptr;
@@ -623,6 +623,7 @@ void mfma_release(MfmaData &md) {
     mfree(m->act[1]);
     mfree(m->prev_slot[0]);
     mfree(m->prev_slot[1]);
+    mfree(m->slot_map);
     mfree(m->ids);
     mfree(m->cnt);
     mfree(m->st);
@@ -704,7 +705,10 @@ int mfma_ensure(MfmaData &md, int32_t n, int32_t d, int64_t arcs, const int32_t 
     int32_t *d_src = nullptr;
     HIP_OK(hipMalloc(&m->row_ptr, ((size_t)n + 1) * 4));
     HIP_OK(hipMalloc(&m->nbr_s, std::max<size_t>(1, (size_t)arcs) * 4));
-    HIP_OK(hipMalloc(&m->r1, std::max<size_t>(1, (size_t)arcs) * 128));
+    // kMY zero arcs of padding: the step kernel copies 8 arcs from each
+    // block's first arc
+    HIP_OK(hipMalloc(&m->r1, ((size_t)arcs + kMY) * 128));
+    HIP_OK(hipMemset(m->r1, 0, ((size_t)arcs + kMY) * 128));
     HIP_OK(hipMalloc(&d_src, std::max<size_t>(1, (size_t)arcs) * 4));
     HIP_OK(hipMemcpy(m->row_ptr, row_ptr, ((size_t)n + 1) * 4, hipMemcpyDeviceToDevice));
     if (arcs > 0) {
@@ -717,6 +721,8 @@ int mfma_ensure(MfmaData &md, int32_t n, int32_t d, int64_t arcs, const int32_t 
         HIP_OK(hipStreamSynchronize(stream));
     }
     (void)hipFree(d_src);
+    HIP_OK(hipFuncSetAttribute((const void *)mfma_sweep_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMSmem));
     HIP_OK(hipHostMalloc((void **)&m->h_cnt, sizeof(int32_t) * 2, hipHostMallocDefault));
     HIP_OK(hipEventCreate(&m->ev0));
     HIP_OK(hipEventCreate(&m->ev1));
@@ -738,6 +744,7 @@ static int ensure_capacity(MfmaData &md, int32_t B) {
     mfree(m->act[1]);
     mfree(m->prev_slot[0]);
     mfree(m->prev_slot[1]);
+    mfree(m->slot_map);
     mfree(m->ids);
     mfree(m->cnt);
     mfree(m->st);
@@ -757,6 +764,7 @@ static int ensure_capacity(MfmaData &md, int32_t B) {
     HIP_OK(hipMalloc(&m->act[1], (size_t)capB * 4));
     HIP_OK(hipMalloc(&m->prev_slot[0], (size_t)capB * 4));
     HIP_OK(hipMalloc(&m->prev_slot[1], (size_t)capB * 4));
+    HIP_OK(hipMalloc(&m->slot_map, (size_t)capB * 4));
     HIP_OK(hipMalloc(&m->ids, (size_t)capB * 4));
     HIP_OK(hipMalloc(&m->cnt, 2 * 4));
     HIP_OK(hipMalloc(&m->st, (size_t)capB * sizeof(MState)));
@@ -778,7 +786,7 @@ static MArgs make_args(MfmaData &md, int32_t B, const uint64_t *din, uint64_t *d
     memset(&A, 0, sizeof(A));
     A.n = md.n;
     A.d = md.d;
-    A.N32 = md.n * 32;
+    A.capB = m->capB;
     A.row_ptr = m->row_ptr;
     A.nbr_s = m->nbr_s;
     A.deg = m->deg;
@@ -796,6 +804,7 @@ static MArgs make_args(MfmaData &md, int32_t B, const uint64_t *din, uint64_t *d
     A.act[1] = m->act[1];
     A.prev_slot[0] = m->prev_slot[0];
     A.prev_slot[1] = m->prev_slot[1];
+    A.slot_map = m->slot_map;
     A.cnt = m->cnt;
     A.st = m->st;
     A.mode = mode;
@@ -836,10 +845,12 @@ static int run_steps(MfmaData &md, const MArgs &A, bool profile, int32_t handoff
             ++k;
             const bool timed = profile && k <= 64;
             if (timed) HIP_OK(hipEventRecord(m->kev[2 * (k - 1)], stream));
-            hipLaunchKernelGGL(mfma_sweep_kernel, dim3(sweep_blocks), dim3(kMThreads), 0, stream, A, k);
+            hipLaunchKernelGGL(mfma_sweep_kernel, dim3(sweep_blocks), dim3(kMThreads), kMSmem, stream,
+                               A, k);
             if (timed) HIP_OK(hipEventRecord(m->kev[2 * (k - 1) + 1], stream));
             hipLaunchKernelGGL(mfma_reduce_kernel, dim3((A.B + 31) / 32), dim3(256), 0, stream, A, k);
             hipLaunchKernelGGL(mfma_finalize_kernel, dim3(1), dim3(1024), 0, stream, A, k);
+            hipLaunchKernelGGL(mfma_gather_kernel, dim3(init_blocks), dim3(256), 0, stream, A, k);
         }
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpyAsync(m->h_cnt, A.cnt + (k & 1), 4, hipMemcpyDeviceToHost, stream));
@@ -854,13 +865,13 @@ static int run_steps(MfmaData &md, const MArgs &A, bool profile, int32_t handoff
     return RAC_OK;
 }
 
-int mfma_start(MfmaData &md, int32_t B, const uint64_t *d_in, int32_t mode, int32_t max_sweeps,
-               int32_t profile, int32_t handoff, hipStream_t stream, int32_t *k_out,
-               int32_t *p_out) {
+int mfma_start(MfmaData &md, int32_t B, const uint64_t *d_in, uint64_t *d_out, int32_t mode,
+               int32_t max_sweeps, int32_t profile, int32_t handoff, hipStream_t stream,
+               int32_t *k_out, int32_t *p_out) {
     int rc = ensure_capacity(md, B);
     if (rc) return rc;
     MfmaImpl *m = impl(md);
-    MArgs A = make_args(md, B, d_in, nullptr, nullptr, nullptr, mode, max_sweeps);
+    MArgs A = make_args(md, B, d_in, d_out, nullptr, nullptr, mode, max_sweeps);
     m->last_B = B;
     return run_steps(md, A, profile != 0, handoff, stream, k_out, p_out);
 }
@@ -887,14 +898,12 @@ int mfma_merge(MfmaData &md, int32_t k, const uint64_t *d_bits, const int32_t *d
     return RAC_OK;
 }
 
-int mfma_finish(MfmaData &md, uint64_t *d_out, int32_t *d_iters, int32_t *d_status,
-                hipStream_t stream) {
+int mfma_finish(MfmaData &md, int32_t *d_iters, int32_t *d_status, hipStream_t stream) {
     MfmaImpl *m = impl(md);
     MArgs A = m->args;
-    A.dout = d_out;
     A.iters_out = d_iters;
     A.status_out = d_status;
-    const int blocks = (int)std::min<int64_t>(4096, ((int64_t)A.B * A.n + 255) / 256);
+    const int blocks = (int)std::min<int64_t>(4096, ((int64_t)A.B + 255) / 256);
     hipLaunchKernelGGL(mfma_pack_kernel, dim3(blocks), dim3(256), 0, stream, A);
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(m->ev1, stream));
@@ -921,7 +930,7 @@ static void collect_stats(MfmaData &md, int32_t B, const std::vector<long long> 
     (void)hipEventElapsedTime(&ms, m->ev0, m->ev1);
     stats->device_ms = ms;
     stats->path = RAC_PATH_MFMA;
-    stats->relation_bytes = md.arcs * 1024;
+    stats->relation_bytes = md.arcs * 128;
     // matrix-core steps performed: state s took part in steps 1..min(iters, last_k)
     long long mfma_state_steps = 0;
     for (int32_t s = 0; s < B; ++s) mfma_state_steps += std::min(iters[(size_t)s], m->last_k);

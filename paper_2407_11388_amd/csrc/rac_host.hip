@@ -1019,8 +1019,8 @@ static int run_mfma(rac_net *net, int32_t B, const uint64_t *d_in, uint64_t *d_o
     RAC_TRY(mfma_ensure(net->mfma, net->n, net->d, net->arcs, net->row_ptr, net->nbr, net->deg,
                         net->rel, net->arc_src, net->h_row_ptr, net->stream));
     int32_t k = 0, P = 0;
-    RAC_TRY(mfma_start(net->mfma, B, d_in, net->opt.mode, net->opt.max_sweeps, net->opt.profile,
-                       mfma_handoff_threshold(), s, &k, &P));
+    RAC_TRY(mfma_start(net->mfma, B, d_in, d_out, net->opt.mode, net->opt.max_sweeps,
+                       net->opt.profile, mfma_handoff_threshold(), s, &k, &P));
     if (P > 0) {
         RAC_TRY(ensure_path(net, RAC_PATH_BITS, call_target(net, P)));
         PathData &pd = net->bits;
@@ -1042,7 +1042,7 @@ static int run_mfma(rac_net *net, int32_t B, const uint64_t *d_in, uint64_t *d_o
                                 maxs - k, true, false));
         RAC_TRY(mfma_merge(net->mfma, k, r.dout, r.iters, r.status, r.checks, r.rc, s));
     }
-    RAC_TRY(mfma_finish(net->mfma, d_out, d_it, d_st, s));
+    RAC_TRY(mfma_finish(net->mfma, d_it, d_st, s));
     return RAC_OK;
 }
 

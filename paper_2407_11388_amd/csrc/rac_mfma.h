@@ -25,25 +25,26 @@ int mfma_ensure(MfmaData &md, int32_t n, int32_t d, int64_t arcs, const int32_t 
                 const int32_t *arc_src, const std::vector<int32_t> &h_row_ptr,
                 hipStream_t stream);
 // Enqueues the init kernel and matrix-core steps for B states (device input
-// d_in [B][n]). Stops when every state has stopped, at the step cap, or when
-// at most `handoff` states remain active (0: never hand off). *k_out is the
-// last step run, *p_out the number of states left for the caller to finish
-// with mfma_handoff / (another path) / mfma_merge. Waits on the device only to
-// read the active-state count between steps.
-int mfma_start(MfmaData &md, int32_t B, const uint64_t *d_in, int32_t mode, int32_t max_sweeps,
-               int32_t profile, int32_t handoff, hipStream_t stream, int32_t *k_out,
-               int32_t *p_out);
+// d_in [B][n]; the final domains of the states that stop go to d_out [B][n]).
+// Stops when every state has stopped, at the step cap, or when at most
+// `handoff` states remain active (0: never hand off). *k_out is the last step
+// run, *p_out the number of states left for the caller to finish with
+// mfma_handoff / (another path) / mfma_merge. Waits on the device only to read
+// the active-state count between steps.
+int mfma_start(MfmaData &md, int32_t B, const uint64_t *d_in, uint64_t *d_out, int32_t mode,
+               int32_t max_sweeps, int32_t profile, int32_t handoff, hipStream_t stream,
+               int32_t *k_out, int32_t *p_out);
 // Writes the P remaining states as bit masks [P][n] and their step-k change
 // flags [P][n] (the @changed set to continue from).
 int mfma_handoff(MfmaData &md, int32_t k, uint64_t *d_bits, uint8_t *d_changed, hipStream_t stream);
-// Takes back their results: domains [P][n], steps run after step k, status,
+// Takes back their results (the domains go to d_out): domains [P][n], steps
+// run after step k, status,
 // support checks of those steps, and the other path's return flags.
 int mfma_merge(MfmaData &md, int32_t k, const uint64_t *d_bits, const int32_t *d_it,
                const int32_t *d_st, const long long *d_chk, const int32_t *d_rc,
                hipStream_t stream);
-// Writes every state's domains, step count and status.
-int mfma_finish(MfmaData &md, uint64_t *d_out, int32_t *d_iters, int32_t *d_status,
-                hipStream_t stream);
+// Writes every state's step count and status (the domains are in d_out).
+int mfma_finish(MfmaData &md, int32_t *d_iters, int32_t *d_status, hipStream_t stream);
 // Waits for the last call and fills the counters; returns its error code.
 int mfma_collect(MfmaData &md, rac_stats *stats);
 void mfma_release(MfmaData &md);
