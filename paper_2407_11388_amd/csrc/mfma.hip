@@ -38,11 +38,13 @@ namespace rac {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kMX = 8;            // variables per workgroup (one per wave)
+constexpr int kMW = 8;            // waves per workgroup
+constexpr int kXW = 2;            // variables per wave
+constexpr int kMX = kMW * kXW;    // variables per workgroup
 constexpr int kMSub = 4;          // 32-state sub-tiles per wave
 constexpr int kMS = 32 * kMSub;   // states per workgroup
 constexpr int kMY = 8;            // neighbours per LDS block
-constexpr int kMThreads = 64 * kMX;
+constexpr int kMThreads = 64 * kMW;
 
 // 4 bits -> 4 bytes holding 0/1 (bit i of v becomes byte i). The factor places
 // copies of v 7 bits apart, so no two copies overlap and no carry occurs.
@@ -167,13 +169,13 @@ __device__ __forceinline__ void dma16(const void *g, void *lds) {
 
 constexpr int kStages = 3;                          // LDS ring depth (loads run 2 blocks ahead)
 constexpr int kBTile = kMY * 2 * kMS;               // v4i per domain tile (32 KiB)
-constexpr int kATile = kMX * kMY * 32 / 4;          // v4i per relation tile (8 KiB)
-constexpr size_t kMSmem = (size_t)kStages * (kBTile + kATile) * 16;   // 120 KiB
-constexpr int kDmaPerBlock = kMY * 2 * kMS / 64 / kMX + 1;           // per wave: 4 + 1
+constexpr int kATile = kMX * kMY * 32 / 4;          // v4i per relation tile (16 KiB)
+constexpr size_t kMSmem = (size_t)kStages * (kBTile + kATile) * 16;   // 144 KiB
+constexpr int kDmaPerBlock = kMY * 2 * kMS / 64 / kMW + kXW;        // per wave: 4 + 2
 
 __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
     extern __shared__ v4i s_lds[];   // kStages x {domain tile [kMY][2][kMS], relation tile
-                                     // [kMX waves][kMY arcs][32 rows] uint32}
+                                     // [kMX variables][kMY arcs][32 rows] uint32}
     const int nact = A.cnt[(k - 1) & 1];
     // workgroup -> (x-tile, state tile); the state tiles of one x-tile share
     // blockIdx % 8 and so an XCD
@@ -192,11 +194,20 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
     if (st0 >= nact || xt * kMX >= A.n) return;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int x = xt * kMX + wave;
-    const bool xv = x < A.n;                // wave-uniform
     const int nblk = A.nblk;
-    const int32_t *bst = A.bstart + (int64_t)(xv ? x : 0) * (nblk + 1);
-    const uint32_t *bmk = A.bmask + (int64_t)(xv ? x : 0) * nblk;
+    // this wave's variables x = xt*kMX + kXW*wave + i (i < kXW), and their
+    // neighbour tables (variable 0's for a variable past n, never used)
+    int xs[kXW];
+    bool xvs[kXW];
+    const int32_t *bsts[kXW];
+    const uint32_t *bmks[kXW];
+#pragma unroll
+    for (int i = 0; i < kXW; ++i) {
+        xs[i] = xt * kMX + kXW * wave + i;
+        xvs[i] = xs[i] < A.n;                       // wave-uniform
+        bsts[i] = A.bstart + (int64_t)(xvs[i] ? xs[i] : 0) * (nblk + 1);
+        bmks[i] = A.bmask + (int64_t)(xvs[i] ? xs[i] : 0) * nblk;
+    }
     const int8_t *din = A.dom8[0];
     const int half = lane >> 5, col = lane & 31;
     // the matrix-core operand of lane (col, half) for an arc: row a = col,
@@ -216,9 +227,9 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
     // consecutive slots, 2 KiB each in both memories; wave w copies rows 2w
     // and 2w+1 as 1 KiB halves. A neighbour past n copies variable n-1's row
     // (never a neighbour of anything); slots past the active ones are in the
-    // buffer and never used. The relation tile of a wave is the 8 arcs from
-    // the block's first arc (1 KiB; arcs past the block or past the last arc,
-    // where kMY zero arcs pad the array, are never used).
+    // buffer and never used. The relation tile of a variable is the 8 arcs
+    // from the block's first arc (1 KiB; arcs past the block or past the last
+    // arc, where kMY zero arcs pad the array, are never used).
     auto issue = [&](int stg, int blk) {
         v4i *bt = s_lds + stg * (kBTile + kATile);
 #pragma unroll
@@ -229,8 +240,12 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
             y = y < A.n ? y : A.n - 1;
             dma16(din + dom_off(A, y, h, st0 + part * 64 + lane), bt + (yl * 2 + h) * kMS + part * 64);
         }
-        const int32_t j0 = (int32_t)sload_u32(bst + blk);
-        dma16(A.r1 + ((int64_t)j0 * 32 + lane * 4), bt + kBTile + wave * (kMY * 32 / 4));
+#pragma unroll
+        for (int i = 0; i < kXW; ++i) {
+            const int32_t j0 = (int32_t)sload_u32(bsts[i] + blk);
+            dma16(A.r1 + ((int64_t)j0 * 32 + lane * 4),
+                  bt + kBTile + (kXW * wave + i) * (kMY * 32 / 4));
+        }
     };
     // waits until this wave's loads of the next block are in LDS (the loads of
     // the block after it may stay in flight), and its LDS reads are done;
@@ -239,11 +254,13 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
         asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(kDmaPerBlock) : "memory");
     };
 
-    v16i rm[kMSub];
+    v16i rm[kXW][kMSub];
 #pragma unroll
-    for (int t = 0; t < kMSub; ++t)
+    for (int i = 0; i < kXW; ++i)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) rm[t][v] = 0x7FFFFFFF;
+        for (int t = 0; t < kMSub; ++t)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) rm[i][t][v] = 0x7FFFFFFF;
 
     issue(0, 0);
     issue(1, nblk > 1 ? 1 : 0);
@@ -253,109 +270,117 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
         // the stage no one reads any more)
         issue((blk + 2) % kStages, blk + 2 < nblk ? blk + 2 : nblk - 1);
         const v4i *bt = s_lds + (blk % kStages) * (kBTile + kATile);
-        const uint32_t *at = reinterpret_cast<const uint32_t *>(bt + kBTile) + wave * (kMY * 32);
-        const uint32_t mcur = xv ? sload_u32(bmk + blk) : 0u;
 
-        // products of this block's arcs, two at a time: a fresh accumulator
-        // per arc, folded into the running minimum with one min3 per value.
-        // An odd last arc is paired with itself. Units u = pair * kMSub +
-        // sub-tile are software-pipelined: the LDS operands of unit u+1 are
-        // read and the products of unit u issued before the minimum of unit
-        // u-1 is folded.
-        const int cnt = __builtin_popcount(mcur);
-        const int npairs = (cnt + 1) >> 1;
-        int l0[kMY / 2], l1[kMY / 2];
-        {
-            uint32_t msk = mcur;
+        // Per variable: the products of this block's arcs, two at a time: a
+        // fresh accumulator per arc, folded into the running minimum with one
+        // min3 per value. An odd last arc is paired with itself. Units u =
+        // pair * kMSub + sub-tile are software-pipelined: the LDS operands of
+        // unit u+1 are read and the products of unit u issued before the
+        // minimum of unit u-1 is folded.
 #pragma unroll
-            for (int q = 0; q < kMY / 2; ++q) {
-                l0[q] = msk ? __builtin_ctz(msk) : 0;
-                msk &= msk - 1u;
-                l1[q] = msk ? __builtin_ctz(msk) : l0[q];
-                msk &= msk - 1u;
-            }
-        }
-        if (npairs > 0) {
-            auto lds_b = [&](int q, int t, v4i &b0, v4i &b1) {
-                b0 = bt[(l0[q] * 2 + half) * kMS + t * 32 + col];
-                b1 = bt[(l1[q] * 2 + half) * kMS + t * 32 + col];
-            };
-            auto fold = [&](v16i &r, const v16i &c0, const v16i &c1) {
+        for (int xi = 0; xi < kXW; ++xi) {
+            const uint32_t *at = reinterpret_cast<const uint32_t *>(bt + kBTile) +
+                                 (kXW * wave + xi) * (kMY * 32);
+            const uint32_t mcur = xvs[xi] ? sload_u32(bmks[xi] + blk) : 0u;
+            const int cnt = __builtin_popcount(mcur);
+            const int npairs = (cnt + 1) >> 1;
+            int l0[kMY / 2], l1[kMY / 2];
+            {
+                uint32_t msk = mcur;
 #pragma unroll
-                for (int v = 0; v < 16; ++v) r[v] = min(r[v], min(c0[v], c1[v]));
-            };
-            const v16i zero = {0};
-            v4i bn0, bn1;
-            lds_b(0, 0, bn0, bn1);
-            v16i cp0 = zero, cp1 = zero;
-#pragma unroll
-            for (int q = 0; q < kMY / 2; ++q) {
-                if (q >= npairs) break;
-                const int ja = 2 * q, jb = 2 * q + 1 < cnt ? 2 * q + 1 : cnt - 1;
-                const v4i a0 = expand_a(at[ja * 32 + col]), a1 = expand_a(at[jb * 32 + col]);
-#pragma unroll
-                for (int t = 0; t < kMSub; ++t) {
-                    const int u = q * kMSub + t;
-                    const v4i b0 = bn0, b1 = bn1;
-                    if (u + 1 < kMY / 2 * kMSub) {
-                        const int qn = (u + 1) / kMSub < npairs ? (u + 1) / kMSub : npairs - 1;
-                        lds_b(qn, (u + 1) % kMSub, bn0, bn1);
-                    }
-                    const v16i c0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, zero, 0, 0, 0);
-                    const v16i c1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, zero, 0, 0, 0);
-                    // keep the compiler from moving the fold next to the
-                    // products it would then wait for
-                    __builtin_amdgcn_sched_barrier(0);
-                    if (u > 0) fold(rm[(u - 1) % kMSub], cp0, cp1);
-                    __builtin_amdgcn_sched_barrier(0);
-                    cp0 = c0;
-                    cp1 = c1;
+                for (int q = 0; q < kMY / 2; ++q) {
+                    l0[q] = msk ? __builtin_ctz(msk) : 0;
+                    msk &= msk - 1u;
+                    l1[q] = msk ? __builtin_ctz(msk) : l0[q];
+                    msk &= msk - 1u;
                 }
             }
-            fold(rm[kMSub - 1], cp0, cp1);   // a pair's last unit is its last sub-tile
+            if (npairs > 0) {
+                auto lds_b = [&](int q, int t, v4i &b0, v4i &b1) {
+                    b0 = bt[(l0[q] * 2 + half) * kMS + t * 32 + col];
+                    b1 = bt[(l1[q] * 2 + half) * kMS + t * 32 + col];
+                };
+                auto fold = [&](v16i &r, const v16i &c0, const v16i &c1) {
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) r[v] = min(r[v], min(c0[v], c1[v]));
+                };
+                const v16i zero = {0};
+                v4i bn0, bn1;
+                lds_b(0, 0, bn0, bn1);
+                v16i cp0 = zero, cp1 = zero;
+#pragma unroll
+                for (int q = 0; q < kMY / 2; ++q) {
+                    if (q >= npairs) break;
+                    const int ja = 2 * q, jb = 2 * q + 1 < cnt ? 2 * q + 1 : cnt - 1;
+                    const v4i a0 = expand_a(at[ja * 32 + col]), a1 = expand_a(at[jb * 32 + col]);
+#pragma unroll
+                    for (int t = 0; t < kMSub; ++t) {
+                        const int u = q * kMSub + t;
+                        const v4i b0 = bn0, b1 = bn1;
+                        if (u + 1 < kMY / 2 * kMSub) {
+                            const int qn = (u + 1) / kMSub < npairs ? (u + 1) / kMSub : npairs - 1;
+                            lds_b(qn, (u + 1) % kMSub, bn0, bn1);
+                        }
+                        const v16i c0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, zero, 0, 0, 0);
+                        const v16i c1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, zero, 0, 0, 0);
+                        // keep the compiler from moving the fold next to the
+                        // products it would then wait for
+                        __builtin_amdgcn_sched_barrier(0);
+                        if (u > 0) fold(rm[xi][(u - 1) % kMSub], cp0, cp1);
+                        __builtin_amdgcn_sched_barrier(0);
+                        cp0 = c0;
+                        cp1 = c1;
+                    }
+                }
+                fold(rm[xi][kMSub - 1], cp0, cp1);   // a pair's last unit is its last sub-tile
+            }
         }
         ring_sync();
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // no copy may outlive the workgroup
 
     // epilogue: new domain bytes and per-state change / wipe-out masks
-    if (!xv) return;
     int8_t *dnext = A.dom8[1];
 #pragma unroll
-    for (int t = 0; t < kMSub; ++t) {
-        const int slot = st0 + t * 32 + col;
-        const bool live = slot < nact;
-        bool changed = false, nonempty = false;
-        if (live) {
+    for (int xi = 0; xi < kXW; ++xi) {
+        if (!xvs[xi]) continue;
+        const int x = xs[xi];
 #pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                // rows a = 8g + 4*half + r, r = 0..3: bytes of half g/2 at 8(g%2) + 4*half
-                const int64_t off = dom_off(A, x, g >> 1, slot) + 8 * (g & 1) + 4 * half;
-                const uint32_t old = *reinterpret_cast<const uint32_t *>(din + off);
-                uint32_t keep = 0;
+        for (int t = 0; t < kMSub; ++t) {
+            const int slot = st0 + t * 32 + col;
+            const bool live = slot < nact;
+            bool changed = false, nonempty = false;
+            if (live) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (rm[t][4 * g + r] != 0) keep |= 0xFFu << (8 * r);
-                const uint32_t nw = old & keep;
-                *reinterpret_cast<uint32_t *>(dnext + off) = nw;
-                changed |= nw != old;
-                nonempty |= nw != 0;
+                for (int g = 0; g < 4; ++g) {
+                    // rows a = 8g + 4*half + r, r = 0..3: bytes of half g/2 at 8(g%2) + 4*half
+                    const int64_t off = dom_off(A, x, g >> 1, slot) + 8 * (g & 1) + 4 * half;
+                    const uint32_t old = *reinterpret_cast<const uint32_t *>(din + off);
+                    uint32_t keep = 0;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (rm[xi][t][4 * g + r] != 0) keep |= 0xFFu << (8 * r);
+                    const uint32_t nw = old & keep;
+                    *reinterpret_cast<uint32_t *>(dnext + off) = nw;
+                    changed |= nw != old;
+                    nonempty |= nw != 0;
+                }
             }
-        }
-        // both lanes of a state column exchange their halves; the shuffles
-        // run in every lane (no short-circuit), as ds_bpermute reads the
-        // source lane's register
-        const int other_changed = __shfl_xor((int)changed, 32, 64);
-        const int other_nonempty = __shfl_xor((int)nonempty, 32, 64);
-        changed = changed || other_changed != 0;
-        nonempty = nonempty || other_nonempty != 0;
-        const bool wiped = live && !nonempty;
-        const uint64_t mc = __ballot(changed && live);
-        const uint64_t mw = __ballot(wiped);
-        if (lane == 0) {
-            const int w = (st0 + t * 32) >> 5;
-            A.chg[(int64_t)x * A.words + w] = (uint32_t)mc;
-            A.wipe[(int64_t)x * A.words + w] = (uint32_t)mw;
+            // both lanes of a state column exchange their halves; the shuffles
+            // run in every lane (no short-circuit), as ds_bpermute reads the
+            // source lane's register
+            const int other_changed = __shfl_xor((int)changed, 32, 64);
+            const int other_nonempty = __shfl_xor((int)nonempty, 32, 64);
+            changed = changed || other_changed != 0;
+            nonempty = nonempty || other_nonempty != 0;
+            const bool wiped = live && !nonempty;
+            const uint64_t mc = __ballot(changed && live);
+            const uint64_t mw = __ballot(wiped);
+            if (lane == 0) {
+                const int w = (st0 + t * 32) >> 5;
+                A.chg[(int64_t)x * A.words + w] = (uint32_t)mc;
+                A.wipe[(int64_t)x * A.words + w] = (uint32_t)mw;
+            }
         }
     }
 }
