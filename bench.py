@@ -40,14 +40,44 @@ KERNEL_SOURCES = {"mfma_sweep_kernel": ["mfma.hip", "rac_mfma.h"],
                   "revise_kernel": ["sweep.hip", "rac_internal.h", "rac_host.hip"]}
 
 
-def kernel_digest(kernel: str) -> str:
-    """sha256 over a kernel's sources; measured traffic is only reported while
-    it matches the digest recorded with the counters."""
+def _code_only(src: str) -> str:
+    """C/C++ source without comments and with whitespace runs collapsed, so
+    that a change of comments or layout keeps a kernel's digest."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
+def kernel_digest(kernel: str, read=None) -> str:
+    """sha256 over a kernel's sources (code only: comments and whitespace
+    runs do not count); measured traffic is only reported while it matches
+    the digest recorded with the counters."""
     import hashlib
     h = hashlib.sha256()
     for name in KERNEL_SOURCES[kernel]:
-        with open(os.path.join(CSRC, name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
+        if read is None:
+            with open(os.path.join(CSRC, name), encoding="utf-8") as f:
+                text = f.read()
+        else:
+            text = read(name)
+        h.update(name.encode() + b"\0" + _code_only(text).encode())
     return h.hexdigest()
 
 

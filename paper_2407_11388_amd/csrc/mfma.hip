@@ -12,14 +12,17 @@
 // keeps the running minimum of the counts over y; a value survives iff that
 // minimum is non-zero.
 //
-// Tiling. A workgroup of 8 waves owns 8 variables x (one per wave) and 128
-// states (4 sub-tiles of 32 per wave). It walks y = 0..n-1 in blocks of 8:
-// the domain bytes of the block for its 128 states are staged in LDS (double
-// buffered, shared by the 8 waves), and every wave multiplies its x's
-// relation blocks for the constrained y of the block (arcs sorted by y,
-// fetched one block ahead) with them, one v_mfma_i32_32x32x32_i8 per (arc,
-// sub-tile). Workgroups of one x-tile are placed on one XCD so that the
-// relation blocks they share meet in that XCD's L2.
+// Tiling. A workgroup of 8 waves owns 16 variables x (two per wave) and 128
+// states (4 sub-tiles of 32). It walks y = 0..n-1 in blocks of 8. The domain
+// bytes of the block for its 128 states (stored per variable in the order of
+// the active-state slots, so one (y, half) row of 128 slots is 2 KiB of
+// consecutive memory) and the relation rows of its 16 variables for the
+// block's arcs (arcs sorted by y) are copied straight from global memory into
+// a 3-stage LDS ring, two blocks ahead of the products; every wave then
+// multiplies each of its x's arcs in the block with the staged bytes, one
+// v_mfma_i32_32x32x32_i8 per (arc, sub-tile). Workgroups of one x-tile are
+// placed on one XCD so that the relation rows they share meet in that XCD's
+// L2.
 //
 // Steps. Each step writes the new domain bytes (double buffer), and per
 // (variable, slot word of 32 states) a change mask and a wipe-out mask. A
