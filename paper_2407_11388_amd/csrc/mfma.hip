@@ -2,15 +2,15 @@
 //
 // For B domain states of one network, the support counts of one step of
 // Eq. (1) are products of the 0/1 relation matrix R[(x,a),(y,b)] (int8) with
-// the 0/1 domain matrix Dom[(y,b), s] (int8): for a constrained pair (x,y),
+// the domain matrix Dom[(y,b), s] (int8): for a constrained pair (x,y),
 // count(x,a,y,s) = sum_b R[x,a,y,b] * Dom[y,b,s] (tensorRevise of
 // Algorithm 1; at most d <= 32, so int32 accumulation is exact). Unlike a
-// plain GEMM, the counts of different neighbours y are not summed: each
-// neighbour block gets a fresh int32 accumulator, and a value survives only
-// if every neighbour's count is non-zero (Algorithm 1 clamps the counts and
-// tests that the clamped sum equals the number of neighbours). The kernel
-// keeps the running minimum of the counts over y; a value survives iff that
-// minimum is non-zero.
+// plain GEMM, the counts of different neighbours y are not summed: a value
+// survives only if every neighbour's count is non-zero (Algorithm 1 clamps
+// the counts and tests that the clamped sum equals the number of neighbours).
+// The kernel turns each count into a zero flag inside the matrix-core
+// accumulator (two arcs per accumulator chain, see kBias below) and ORs the
+// flags over y.
 //
 // Tiling. A workgroup of 8 waves owns 16 variables x (two per wave) and 128
 // states (4 sub-tiles of 32). It walks y = 0..n-1 in blocks of 8. The domain
@@ -68,12 +68,15 @@ struct MArgs {
     const int32_t *deg;               // [n]
     const uint32_t *r1;               // [arcs + kMY][32] row a of each arc as bits (bit b: (a,b)
                                       // allowed); kMY zero arcs of padding at the end
-    const int32_t *bstart;            // [n][nblk+1] first arc of x with neighbour >= 8*b
-    const uint32_t *bmask;            // [n][nblk] bit l: x is constrained with y = 8*b + l
-                                      // (32-bit words, so that scalar loads read them)
+    const uint32_t *bm4;              // [n][nw4] neighbour masks of 4 blocks of 8 neighbours per
+                                      // word: bit 8q+l of word w: x is constrained with
+                                      // y = 8(4w+q) + l
+    const int32_t *bf4;               // [n][nw4] first arc of x in block 4w
+    int32_t nw4;                      // ceil(nblk / 4)
     int32_t nblk;                     // ceil(n / 8)
     int32_t narcs;                    // number of arcs
-    int8_t *dom8[2];                  // [n][2][capB][16]: bytes 16h .. 16h+15 of the 0/1 domain
+    int8_t *dom8[2];                  // [n][2][capB][16]: bytes 16h .. 16h+15 of the domain as
+                                      // bytes 0 / -1 (0xFF: value present)
                                       // of (x, state slot); [0]: the current step's input,
                                       // [1]: its output (same slot order)
     uint32_t *chg, *wipe;             // [n][words]
@@ -96,7 +99,7 @@ __device__ __forceinline__ int64_t dom_off(const MArgs &A, int32_t x, int h, int
     return (((int64_t)x * 2 + h) * A.capB + slot) * 16;
 }
 
-// 32 domain bytes (two 16-byte halves) -> bit mask, and back.
+// 32 domain bytes (two 16-byte halves, 0 or 0xFF) -> bit mask, and back.
 __device__ __forceinline__ uint64_t bytes_to_mask(const uint4 lo, const uint4 hi) {
     const uint32_t w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
     uint64_t m = 0;
@@ -110,7 +113,7 @@ __device__ __forceinline__ uint64_t bytes_to_mask(const uint4 lo, const uint4 hi
 __device__ __forceinline__ void mask_to_bytes(uint64_t m, uint4 &lo, uint4 &hi) {
     uint32_t w[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) w[q] = spread4((uint32_t)(m >> (4 * q)) & 0xFu);
+    for (int q = 0; q < 8; ++q) w[q] = spread4((uint32_t)(m >> (4 * q)) & 0xFu) * 0xFFu;
     lo = make_uint4(w[0], w[1], w[2], w[3]);
     hi = make_uint4(w[4], w[5], w[6], w[7]);
 }
@@ -148,37 +151,51 @@ __global__ void mfma_init_kernel(MArgs A) {
     }
 }
 
-// One wave-uniform 32-bit word through the scalar cache (read-only data).
-// The kernel's LDS copies keep the compiler from proving the neighbour tables
-// unmodified, and a vector load would wait for every copy in flight; this
-// load only waits for the scalar and LDS counter.
-__device__ __forceinline__ uint32_t sload_u32(const void *p) {
-    // readfirstlane returns a signed int: go through uint32_t so that the low
-    // word is zero-extended (sign extension would corrupt the high word)
-    const uint64_t a = (uint64_t)p;
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
-    const uint64_t u = (uint64_t)lo | ((uint64_t)hi << 32);
-    uint32_t v;
-    asm volatile("s_load_dword %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(u) : "memory");
-    return v;
-}
-
 // Direct global -> LDS copy of 16 bytes per lane: lane i writes lds + 16*i.
 __device__ __forceinline__ void dma16(const void *g, void *lds) {
     __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)g,
                                      (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
 }
 
+// 4 bits -> 4 bytes of 0/64 (bit i of v becomes bit 6 of byte i). The shift
+// comes after the product so that the product keeps 24-bit operands (a
+// full-rate multiply); the compiler would otherwise fold it into the factor.
+__device__ __forceinline__ uint32_t spread4_64(uint32_t v) {
+    uint32_t r;
+    asm("v_lshlrev_b32 %0, 6, %1" : "=v"(r) : "v"(spread4(v)));
+    return r;
+}
+
 constexpr int kStages = 3;                          // LDS ring depth (loads run 2 blocks ahead)
 constexpr int kBTile = kMY * 2 * kMS;               // v4i per domain tile (32 KiB)
 constexpr int kATile = kMX * kMY * 32 / 4;          // v4i per relation tile (16 KiB)
-constexpr size_t kMSmem = (size_t)kStages * (kBTile + kATile) * 16;   // 144 KiB
+constexpr int kOnes = 2 * kMS;                      // v4i of the all-present tile (4 KiB)
+constexpr size_t kMSmem = ((size_t)kStages * (kBTile + kATile) + kOnes) * 16;   // 148 KiB
 constexpr int kDmaPerBlock = kMY * 2 * kMS / 64 / kMW + kXW;        // per wave: 4 + 2
+constexpr int kChunkShift = 8;                      // lane tables cover 256 blocks (64 lanes x 4)
+
+// Zero-count flags. Domain bytes are 0 or -1 (0xFF). A wave owns two
+// variables x0, x1 and takes their arcs of a block in pairs (the j-th arc of
+// x0 with the j-th arc of x1). For such a pair (x0 -> y0, x1 -> y1) two
+// chained products give, per (value a, state),
+//   D = kBias + R0 . Dom(y0) + 64 R1 . Dom(y1) = -2016 - c0 - 64 c1
+//     = ~((c0 + 31) + 64 (c1 + 31)),
+// where R0, R1 are the relation rows of a as 0/1 bytes and c0, c1 <= 32 the
+// support counts of (x0, a) on y0 and of (x1, a) on y1. The two 6-bit fields
+// c + 31 do not carry into each other and have bit 5 set iff c > 0, so bit 5
+// (bit 11) of D is set iff (x0, a) ((x1, a)) has no support on that arc. The
+// kernel ORs these words over all arcs: a value survives iff its flag stays
+// clear (Eq. (1): it needs a support on every constraint). A variable with
+// fewer arcs than the other in a block fills its slots with a one-value row
+// times the all-present tile (a count of 1: no flag).
+constexpr int kBias = -2016;
+constexpr int kFlag0 = 1 << 5, kFlag1 = 1 << 11;
+static_assert(kXW == 2, "the zero-count flags pack exactly two variables per word");
 
 __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
     extern __shared__ v4i s_lds[];   // kStages x {domain tile [kMY][2][kMS], relation tile
-                                     // [kMX variables][kMY arcs][32 rows] uint32}
+                                     // [kMX variables][kMY arcs][32 rows] uint32}, then the
+                                     // all-present tile [2][kMS]
     const int nact = A.cnt[(k - 1) & 1];
     // workgroup -> (x-tile, state tile); the state tiles of one x-tile share
     // blockIdx % 8 and so an XCD
@@ -197,35 +214,58 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
     if (st0 >= nact || xt * kMX >= A.n) return;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int nblk = A.nblk;
-    // this wave's variables x = xt*kMX + kXW*wave + i (i < kXW), and their
-    // neighbour tables (variable 0's for a variable past n, never used)
+    const int nblk = A.nblk, nw4 = A.nw4;
+    // this wave's variables x = xt*kMX + kXW*wave + i (i < kXW)
     int xs[kXW];
     bool xvs[kXW];
-    const int32_t *bsts[kXW];
-    const uint32_t *bmks[kXW];
 #pragma unroll
     for (int i = 0; i < kXW; ++i) {
         xs[i] = xt * kMX + kXW * wave + i;
         xvs[i] = xs[i] < A.n;                       // wave-uniform
-        bsts[i] = A.bstart + (int64_t)(xvs[i] ? xs[i] : 0) * (nblk + 1);
-        bmks[i] = A.bmask + (int64_t)(xvs[i] ? xs[i] : 0) * nblk;
     }
     const int8_t *din = A.dom8[0];
     const int half = lane >> 5, col = lane & 31;
+    v4i *ones = s_lds + kStages * (kBTile + kATile);
+    if (tid < kOnes) ones[tid] = v4i{-1, -1, -1, -1};
+
+    // Lane tables of a chunk of 256 blocks: lane l holds, per variable, the
+    // neighbour masks of blocks 4l' .. 4l'+3 (l' = 256c/4 + l) as bytes and the
+    // first arc of block 4l'. One copy follows the blocks being copied (two
+    // ahead), one the blocks being multiplied; no memory access for the tables
+    // inside a chunk.
+    uint32_t tmI[kXW], tmC[kXW];
+    int32_t tfI[kXW];
+    int chunkI = -1;
+    auto load_tab = [&](int c) {
+        const int w0 = (c << (kChunkShift - 2)) + lane;
+        const int w = w0 < nw4 ? w0 : nw4 - 1;
+#pragma unroll
+        for (int i = 0; i < kXW; ++i) {
+            const int64_t o = (int64_t)(xvs[i] ? xs[i] : 0) * nw4 + w;
+            const uint32_t m = A.bm4[o];
+            const int32_t f = A.bf4[o];
+            tmI[i] = (xvs[i] && w0 < nw4) ? m : 0u;
+            tfI[i] = (xvs[i] && w0 < nw4) ? f : 0;
+        }
+    };
+    auto mask_of = [&](uint32_t tm, int b) -> uint32_t {
+        const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)tm, (b >> 2) & 63);
+        return (w >> (8 * (b & 3))) & 0xFFu;
+    };
     // the matrix-core operand of lane (col, half) for an arc: row a = col,
-    // bits 16*half .. 16*half+15 as 16 bytes of 0/1
-    auto expand_a = [&](uint32_t row) {
+    // bits 16*half .. 16*half+15 as 16 bytes of 0/1 (scale 1) or 0/64
+    auto expand1 = [&](uint32_t row) {
         const uint32_t h = row >> (16 * half);
-        v4i v;
-        v.x = (int)spread4(h & 0xFu);
-        v.y = (int)spread4((h >> 4) & 0xFu);
-        v.z = (int)spread4((h >> 8) & 0xFu);
-        v.w = (int)spread4((h >> 12) & 0xFu);
-        return v;
+        return v4i{(int)spread4(h & 0xFu), (int)spread4((h >> 4) & 0xFu),
+                   (int)spread4((h >> 8) & 0xFu), (int)spread4((h >> 12) & 0xFu)};
+    };
+    auto expand64 = [&](uint32_t row) {
+        const uint32_t h = row >> (16 * half);
+        return v4i{(int)spread4_64(h & 0xFu), (int)spread4_64((h >> 4) & 0xFu),
+                   (int)spread4_64((h >> 8) & 0xFu), (int)spread4_64((h >> 12) & 0xFu)};
     };
 
-    // Loads of block `blk` into ring stage `stg`, all direct to LDS (no
+    // Copies of block `blk` into ring stage `stg`, all direct to LDS (no
     // registers): the domain tile is 16 rows (neighbour yl, half h) of 128
     // consecutive slots, 2 KiB each in both memories; wave w copies rows 2w
     // and 2w+1 as 1 KiB halves. A neighbour past n copies variable n-1's row
@@ -234,6 +274,10 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
     // from the block's first arc (1 KiB; arcs past the block or past the last
     // arc, where kMY zero arcs pad the array, are never used).
     auto issue = [&](int stg, int blk) {
+        if ((blk >> kChunkShift) != chunkI) {
+            chunkI = blk >> kChunkShift;
+            load_tab(chunkI);
+        }
         v4i *bt = s_lds + stg * (kBTile + kATile);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -245,25 +289,32 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
         }
 #pragma unroll
         for (int i = 0; i < kXW; ++i) {
-            const int32_t j0 = (int32_t)sload_u32(bsts[i] + blk);
+            const int l = (blk >> 2) & 63;
+            const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)tmI[i], l);
+            const int32_t j0 = __builtin_amdgcn_readlane(tfI[i], l) +
+                               __builtin_popcount(w & ((1u << (8 * (blk & 3))) - 1u));
             dma16(A.r1 + ((int64_t)j0 * 32 + lane * 4),
                   bt + kBTile + (kXW * wave + i) * (kMY * 32 / 4));
         }
     };
-    // waits until this wave's loads of the next block are in LDS (the loads of
-    // the block after it may stay in flight), and its LDS reads are done;
+    // waits until this wave's copies of the next block are in LDS (the copies
+    // of the block after it may stay in flight), and its LDS reads are done;
     // then the workgroup barrier makes every wave's copies visible
     auto ring_sync = [&]() {
         asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(kDmaPerBlock) : "memory");
     };
 
-    v16i rm[kXW][kMSub];
+    v16i rf[kMSub];
 #pragma unroll
-    for (int i = 0; i < kXW; ++i)
+    for (int t = 0; t < kMSub; ++t)
 #pragma unroll
-        for (int t = 0; t < kMSub; ++t)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) rm[i][t][v] = 0x7FFFFFFF;
+        for (int v = 0; v < 16; ++v) rf[t][v] = 0;
+    v16i bias = {kBias, kBias, kBias, kBias, kBias, kBias, kBias, kBias,
+                 kBias, kBias, kBias, kBias, kBias, kBias, kBias, kBias};
+    asm volatile("" : "+v"(bias));   // kept in registers, not re-created per use
+    // byte offset of lane (col, half)'s 16 operand bytes within a domain row pair
+    const uint32_t lane_off = (uint32_t)(half * kMS + col) * 16u;
+    const uint32_t ones_off = (uint32_t)(kStages * (kBTile + kATile)) * 16u;
 
     issue(0, 0);
     issue(1, nblk > 1 ? 1 : 0);
@@ -272,71 +323,84 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
         // the block two ahead (past the end: a repeat of the last block into
         // the stage no one reads any more)
         issue((blk + 2) % kStages, blk + 2 < nblk ? blk + 2 : nblk - 1);
-        const v4i *bt = s_lds + (blk % kStages) * (kBTile + kATile);
-
-        // Per variable: the products of this block's arcs, two at a time: a
-        // fresh accumulator per arc, folded into the running minimum with one
-        // min3 per value. An odd last arc is paired with itself. Units u =
-        // pair * kMSub + sub-tile are software-pipelined: the LDS operands of
-        // unit u+1 are read and the products of unit u issued before the
-        // minimum of unit u-1 is folded.
+        if ((blk & ((1 << kChunkShift) - 1)) == 0) {
+            // the copy pointer (two blocks ahead, in the same chunk) loaded it
 #pragma unroll
-        for (int xi = 0; xi < kXW; ++xi) {
-            const uint32_t *at = reinterpret_cast<const uint32_t *>(bt + kBTile) +
-                                 (kXW * wave + xi) * (kMY * 32);
-            const uint32_t mcur = xvs[xi] ? sload_u32(bmks[xi] + blk) : 0u;
-            const int cnt = __builtin_popcount(mcur);
-            const int npairs = (cnt + 1) >> 1;
-            int l0[kMY / 2], l1[kMY / 2];
+            for (int i = 0; i < kXW; ++i) tmC[i] = tmI[i];
+        }
+        const int stg = blk % kStages;
+        const uint32_t stage_off = (uint32_t)(stg * (kBTile + kATile)) * 16u;
+        const uint32_t *at0 = reinterpret_cast<const uint32_t *>(s_lds + stg * (kBTile + kATile) + kBTile) +
+                              (kXW * wave) * (kMY * 32);
+        const uint32_t *at1 = at0 + kMY * 32;
+        const uint32_t m0 = mask_of(tmC[0], blk), m1 = mask_of(tmC[1], blk);
+        const int c0 = __builtin_popcount(m0), c1 = __builtin_popcount(m1);
+        const int cm = c0 > c1 ? c0 : c1;
+        if (cm > 0) {
+            // LDS byte offsets of the domain rows of slot j's neighbour, per
+            // variable (slots past a variable's arcs: the all-present tile)
+            uint32_t ob0[kMY], ob1[kMY];
             {
-                uint32_t msk = mcur;
+                uint32_t r0 = m0, r1 = m1;
 #pragma unroll
-                for (int q = 0; q < kMY / 2; ++q) {
-                    l0[q] = msk ? __builtin_ctz(msk) : 0;
-                    msk &= msk - 1u;
-                    l1[q] = msk ? __builtin_ctz(msk) : l0[q];
-                    msk &= msk - 1u;
+                for (int j = 0; j < kMY; ++j) {
+                    ob0[j] = (r0 ? stage_off + (uint32_t)__builtin_ctz(r0) * (2u * kMS * 16u) : ones_off) + lane_off;
+                    ob1[j] = (r1 ? stage_off + (uint32_t)__builtin_ctz(r1) * (2u * kMS * 16u) : ones_off) + lane_off;
+                    r0 &= r0 - 1u;
+                    r1 &= r1 - 1u;
                 }
             }
-            if (npairs > 0) {
-                auto lds_b = [&](int q, int t, v4i &b0, v4i &b1) {
-                    b0 = bt[(l0[q] * 2 + half) * kMS + t * 32 + col];
-                    b1 = bt[(l1[q] * 2 + half) * kMS + t * 32 + col];
-                };
-                auto fold = [&](v16i &r, const v16i &c0, const v16i &c1) {
+            const int npair = (cm + 1) >> 1;
+            const char *lds = reinterpret_cast<const char *>(s_lds);
+            // B operands of slot pair q, sub-tile t: (x0, 2q), (x1, 2q), (x0, 2q+1), (x1, 2q+1)
+            auto lds_b = [&](int q, int t, v4i (&b)[4]) {
+                b[0] = *reinterpret_cast<const v4i *>(lds + ob0[2 * q] + t * 512);
+                b[1] = *reinterpret_cast<const v4i *>(lds + ob1[2 * q] + t * 512);
+                b[2] = *reinterpret_cast<const v4i *>(lds + ob0[2 * q + 1] + t * 512);
+                b[3] = *reinterpret_cast<const v4i *>(lds + ob1[2 * q + 1] + t * 512);
+            };
+            // Units u = slot pair * kMSub + sub-tile are software-pipelined:
+            // the LDS operands of unit u+1 are read and the four products of
+            // unit u issued before the words of unit u-1 are OR-ed in.
+            v4i bn[4];
+            lds_b(0, 0, bn);
+            v16i pe = bias, po = bias;
 #pragma unroll
-                    for (int v = 0; v < 16; ++v) r[v] = min(r[v], min(c0[v], c1[v]));
-                };
-                const v16i zero = {0};
-                v4i bn0, bn1;
-                lds_b(0, 0, bn0, bn1);
-                v16i cp0 = zero, cp1 = zero;
+            for (int q = 0; q < kMY / 2; ++q) {
+                if (q >= npair) break;
+                const int je = 2 * q, jo = 2 * q + 1;
+                const v4i a0e = expand1(je < c0 ? at0[je * 32 + col] : 1u);
+                const v4i a1e = expand64(je < c1 ? at1[je * 32 + col] : 1u);
+                const v4i a0o = expand1(jo < c0 ? at0[jo * 32 + col] : 1u);
+                const v4i a1o = expand64(jo < c1 ? at1[jo * 32 + col] : 1u);
 #pragma unroll
-                for (int q = 0; q < kMY / 2; ++q) {
-                    if (q >= npairs) break;
-                    const int ja = 2 * q, jb = 2 * q + 1 < cnt ? 2 * q + 1 : cnt - 1;
-                    const v4i a0 = expand_a(at[ja * 32 + col]), a1 = expand_a(at[jb * 32 + col]);
+                for (int t = 0; t < kMSub; ++t) {
+                    const int u = q * kMSub + t;
+                    v4i b[4] = {bn[0], bn[1], bn[2], bn[3]};
+                    // (past the last slot pair: slots of absent arcs, read
+                    // and never used; a constant index keeps the offsets in
+                    // registers)
+                    if (u + 1 < kMY / 2 * kMSub) lds_b((u + 1) / kMSub, (u + 1) % kMSub, bn);
+                    v16i de = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0e, b[0], bias, 0, 0, 0);
+                    v16i dd = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0o, b[2], bias, 0, 0, 0);
+                    de = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1e, b[1], de, 0, 0, 0);
+                    dd = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1o, b[3], dd, 0, 0, 0);
+                    // keep the compiler from moving the OR next to the
+                    // products it would then wait for
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (u > 0) {
+                        v16i &r = rf[(u - 1) % kMSub];
 #pragma unroll
-                    for (int t = 0; t < kMSub; ++t) {
-                        const int u = q * kMSub + t;
-                        const v4i b0 = bn0, b1 = bn1;
-                        if (u + 1 < kMY / 2 * kMSub) {
-                            const int qn = (u + 1) / kMSub < npairs ? (u + 1) / kMSub : npairs - 1;
-                            lds_b(qn, (u + 1) % kMSub, bn0, bn1);
-                        }
-                        const v16i c0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, zero, 0, 0, 0);
-                        const v16i c1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, zero, 0, 0, 0);
-                        // keep the compiler from moving the fold next to the
-                        // products it would then wait for
-                        __builtin_amdgcn_sched_barrier(0);
-                        if (u > 0) fold(rm[xi][(u - 1) % kMSub], cp0, cp1);
-                        __builtin_amdgcn_sched_barrier(0);
-                        cp0 = c0;
-                        cp1 = c1;
+                        for (int v = 0; v < 16; ++v) r[v] = r[v] | pe[v] | po[v];
                     }
+                    __builtin_amdgcn_sched_barrier(0);
+                    pe = de;
+                    po = dd;
                 }
-                fold(rm[xi][kMSub - 1], cp0, cp1);   // a pair's last unit is its last sub-tile
             }
+            v16i &r = rf[kMSub - 1];   // a slot pair's last unit is its last sub-tile
+#pragma unroll
+            for (int v = 0; v < 16; ++v) r[v] = r[v] | pe[v] | po[v];
         }
         ring_sync();
     }
@@ -348,6 +412,7 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
     for (int xi = 0; xi < kXW; ++xi) {
         if (!xvs[xi]) continue;
         const int x = xs[xi];
+        const int flag = xi == 0 ? kFlag0 : kFlag1;
 #pragma unroll
         for (int t = 0; t < kMSub; ++t) {
             const int slot = st0 + t * 32 + col;
@@ -362,7 +427,7 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
                     uint32_t keep = 0;
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        if (rm[xi][t][4 * g + r] != 0) keep |= 0xFFu << (8 * r);
+                        if ((rf[t][4 * g + r] & flag) == 0) keep |= 0xFFu << (8 * r);
                     const uint32_t nw = old & keep;
                     *reinterpret_cast<uint32_t *>(dnext + off) = nw;
                     changed |= nw != old;
@@ -603,9 +668,9 @@ struct MfmaImpl {
     int32_t *row_ptr = nullptr, *nbr_s = nullptr;
     const int32_t *deg = nullptr;
     uint32_t *r1 = nullptr;
-    int32_t *bstart = nullptr;
-    uint32_t *bmask = nullptr;
-    int32_t nblk = 0;
+    uint32_t *bm4 = nullptr;
+    int32_t *bf4 = nullptr;
+    int32_t nblk = 0, nw4 = 0;
     int32_t capB = 0, words = 0;
     int8_t *dom8[2] = {nullptr, nullptr};
     uint32_t *chg = nullptr, *wipe = nullptr;
@@ -641,8 +706,8 @@ void mfma_release(MfmaData &md) {
     mfree(m->row_ptr);
     mfree(m->nbr_s);
     mfree(m->r1);
-    mfree(m->bstart);
-    mfree(m->bmask);
+    mfree(m->bm4);
+    mfree(m->bf4);
     mfree(m->dom8[0]);
     mfree(m->dom8[1]);
     mfree(m->chg);
@@ -708,28 +773,32 @@ int mfma_ensure(MfmaData &md, int32_t n, int32_t d, int64_t arcs, const int32_t 
             src_s[(size_t)j] = h_src[(size_t)perm[(size_t)(j - j0)]];
         }
     }
-    // per (variable, block of 8 neighbours): first arc and neighbour mask
+    // per (variable, 4 blocks of 8 neighbours): the blocks' neighbour masks
+    // as bytes and the first arc of the first block
     const int32_t nblk = (n + kMY - 1) / kMY;
-    std::vector<int32_t> bstart((size_t)n * (nblk + 1));
-    std::vector<uint32_t> bmask((size_t)n * nblk, 0);
+    const int32_t nw4 = (nblk + 3) / 4;
+    std::vector<uint32_t> bm4((size_t)n * nw4, 0);
+    std::vector<int32_t> bf4((size_t)n * nw4, 0);
     for (int32_t x = 0; x < n; ++x) {
         int32_t j = h_row_ptr[x];
         const int32_t j1 = h_row_ptr[x + 1];
-        for (int32_t b = 0; b <= nblk; ++b) {
-            while (j < j1 && nbr_s[(size_t)j] < b * kMY) ++j;
-            bstart[(size_t)x * (nblk + 1) + b] = j;
+        for (int32_t w = 0; w < nw4; ++w) {
+            while (j < j1 && nbr_s[(size_t)j] < 4 * w * kMY) ++j;
+            bf4[(size_t)x * nw4 + w] = j;
         }
         for (int32_t jj = h_row_ptr[x]; jj < j1; ++jj) {
             const int32_t y = nbr_s[(size_t)jj];
-            bmask[(size_t)x * nblk + y / kMY] |= 1u << (y % kMY);
+            bm4[(size_t)x * nw4 + y / (4 * kMY)] |= 1u << (y % (4 * kMY));
         }
     }
     m->nblk = nblk;
-    HIP_OK(hipMalloc(&m->bstart, bstart.size() * 4));
-    HIP_OK(hipMalloc(&m->bmask, std::max<size_t>(1, bmask.size()) * 4));
-    HIP_OK(hipMemcpy(m->bstart, bstart.data(), bstart.size() * 4, hipMemcpyHostToDevice));
-    if (!bmask.empty())
-        HIP_OK(hipMemcpy(m->bmask, bmask.data(), bmask.size() * 4, hipMemcpyHostToDevice));
+    m->nw4 = nw4;
+    HIP_OK(hipMalloc(&m->bm4, std::max<size_t>(1, bm4.size()) * 4));
+    HIP_OK(hipMalloc(&m->bf4, std::max<size_t>(1, bf4.size()) * 4));
+    if (!bm4.empty()) {
+        HIP_OK(hipMemcpy(m->bm4, bm4.data(), bm4.size() * 4, hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(m->bf4, bf4.data(), bf4.size() * 4, hipMemcpyHostToDevice));
+    }
     int32_t *d_src = nullptr;
     HIP_OK(hipMalloc(&m->row_ptr, ((size_t)n + 1) * 4));
     HIP_OK(hipMalloc(&m->nbr_s, std::max<size_t>(1, (size_t)arcs) * 4));
@@ -819,9 +888,10 @@ static MArgs make_args(MfmaData &md, int32_t B, const uint64_t *din, uint64_t *d
     A.nbr_s = m->nbr_s;
     A.deg = m->deg;
     A.r1 = m->r1;
-    A.bstart = m->bstart;
-    A.bmask = m->bmask;
+    A.bm4 = m->bm4;
+    A.bf4 = m->bf4;
     A.nblk = m->nblk;
+    A.nw4 = m->nw4;
     A.narcs = (int32_t)md.arcs;
     A.dom8[0] = m->dom8[0];
     A.dom8[1] = m->dom8[1];

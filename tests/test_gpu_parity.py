@@ -211,7 +211,10 @@ def test_dense_create_matches():
 
 
 MFMA_CASES = [(40, 32, 37, 0.6, 0.3), (45, 10, 130, 0.8, 0.5), (13, 4, 300, 1.0, 0.55),
-              (70, 17, 129, 0.4, 0.7), (9, 1, 64, 0.9, 0.0), (100, 32, 257, 0.8, 0.25)]
+              (70, 17, 129, 0.4, 0.7), (9, 1, 64, 0.9, 0.0), (100, 32, 257, 0.8, 0.25),
+              # more than 256 blocks of 8 neighbours: the step kernel's
+              # neighbour tables come in chunks of 256 blocks
+              (2200, 6, 33, 0.006, 0.35), (2100, 32, 20, 0.004, 0.35)]
 
 
 @pytest.mark.parametrize("handoff", ["0", "32", "100000"])
