@@ -216,6 +216,8 @@ struct rac_net {
     int32_t *row_ptr = nullptr, *nbr = nullptr, *deg = nullptr, *arc_src = nullptr;
     int32_t *gptr = nullptr, *nbrp = nullptr, *src_p = nullptr;   // 64-arc group layout
     int32_t *gown = nullptr;                                      // owner variable of each group
+    int32_t *rpos = nullptr;   // [arcs] group-layout position of each arc's reverse arc
+    int32_t max_deg = 0;
     int64_t groups = 0;
     uint64_t *rel = nullptr;   // [m][d] constraint rows, kept for lazily packed layouts
     PathData bits, i8;
@@ -264,6 +266,9 @@ static void release_runner(Runner &r) {
     dfree(r.ws.plan);
     dfree(r.ws.act);
     dfree(r.ws.act_off);
+    dfree(r.ws.act_push);
+    dfree(r.ws.clist[0]);
+    dfree(r.ws.clist[1]);
     dfree(r.hist);
     dfree(r.prob_net);
     dfree(r.prob_off);
@@ -301,6 +306,9 @@ static int ensure_runner(Runner &r, int32_t nprob, int64_t nvars) {
     RAC_TRY(dalloc(&r.ws.plan, 1));
     RAC_TRY(dalloc(&r.ws.act, nprob));
     RAC_TRY(dalloc(&r.ws.act_off, (size_t)nprob + 1));
+    RAC_TRY(dalloc(&r.ws.act_push, nprob));
+    RAC_TRY(dalloc(&r.ws.clist[0], nvars));
+    RAC_TRY(dalloc(&r.ws.clist[1], nvars));
     RAC_TRY(dalloc(&r.hist, kHist));
     RAC_TRY(dalloc(&r.prob_net, nprob));
     RAC_TRY(dalloc(&r.prob_off, (size_t)nprob + 1));
@@ -349,6 +357,7 @@ extern "C" void rac_destroy(rac_net *net) {
     dfree(net->gptr);
     dfree(net->nbrp);
     dfree(net->gown);
+    dfree(net->rpos);
     dfree(net->src_p);
     dfree(net->rel);
     if (net->stream) (void)hipStreamDestroy(net->stream);
@@ -478,6 +487,8 @@ static int ensure_path(rac_net *net, int32_t path, int32_t item_bytes) {
         pd.desc.gptr = net->gptr;
         pd.desc.nbrp = net->nbrp;
         pd.desc.gown = net->gown;
+        pd.desc.rpos = pd.kind == ROWI8 ? nullptr : net->rpos;
+        pd.desc.pchunks = std::max<int32_t>(1, (net->max_deg + kGroup - 1) / kGroup);
         pd.desc.deg = net->deg;
         pd.desc.rows = pd.rows;
         pd.desc.n = net->n;
@@ -580,6 +591,24 @@ static int create_common(int32_t n, int32_t d, int64_t m, const int32_t *edges,
         std::vector<int32_t> gown((size_t)net->groups);
         for (int32_t x = 0; x < n; ++x)
             for (int32_t g = net->h_gptr[x]; g < net->h_gptr[x + 1]; ++g) gown[(size_t)g] = x;
+        // the reverse of arc j (x -> y) is the arc of the same edge leaving y;
+        // rpos[j] is that arc's position in the group layout
+        std::vector<int32_t> apos((size_t)net->arcs), rpos((size_t)net->arcs);
+        std::vector<int32_t> arc_of_src((size_t)net->arcs);
+        for (int32_t x = 0; x < n; ++x)
+            for (int32_t j = net->h_row_ptr[x]; j < net->h_row_ptr[x + 1]; ++j) {
+                apos[(size_t)j] = net->h_gptr[x] * kGroup + (j - net->h_row_ptr[x]);
+                arc_of_src[(size_t)src[(size_t)j]] = j;
+            }
+        for (int64_t j = 0; j < net->arcs; ++j)
+            rpos[(size_t)j] = apos[(size_t)arc_of_src[(size_t)(src[(size_t)j] ^ 1)]];
+        for (int32_t x = 0; x < n; ++x) net->max_deg = std::max(net->max_deg, net->h_deg[x]);
+        if ((rc = dalloc(&net->rpos, std::max<size_t>(1, rpos.size())))) break;
+        if (!rpos.empty() &&
+            hipMemcpy(net->rpos, rpos.data(), rpos.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+            rc = set_error(RAC_EHIP, "hipMemcpy of the reverse-arc table failed");
+            break;
+        }
         if ((rc = dalloc(&net->gptr, (size_t)n + 1))) break;
         if ((rc = dalloc(&net->nbrp, nbrp.size()))) break;
         if ((rc = dalloc(&net->gown, gown.size()))) break;
@@ -731,6 +760,9 @@ static int build_round(Runner &r, int round, const Launch &L, const StepGrids &s
     if (round == 0) {
         void *pi[1] = {&args};
         RAC_TRY(add_node(rg.graph, &prev, (const void *)init_kernel, sg.init, dim3(256), 0, pi));
+        if (L.changed0)
+            RAC_TRY(add_node(rg.graph, &prev, (const void *)list_changed0_kernel, sg.init, dim3(256),
+                             0, pi));
         void *pp[2] = {&args, &one};
         RAC_TRY(add_node(rg.graph, &prev, (const void *)plan_kernel, dim3(1), dim3(1024), 0, pp));
     }
@@ -796,6 +828,8 @@ static int launch_fixpoint(Runner &r, int device, hipStream_t stream, const Laun
         } else {
             if (round == 0) {
                 hipLaunchKernelGGL(init_kernel, sg.init, dim3(256), 0, stream, L);
+                if (L.changed0)
+                    hipLaunchKernelGGL(list_changed0_kernel, sg.init, dim3(256), 0, stream, L);
                 hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, stream, L, 1);
             }
             for (int32_t i = 1; i <= K; ++i) {
@@ -845,6 +879,15 @@ static void revise_timing(Runner &r, double *ms, int64_t *launches) {
     }
 }
 
+// Steps k >= 2 that re-examine at most 1/ratio of a bit-row network's arcs go
+// variable by variable (the changed variables' arcs) instead of scanning
+// every group. RAC_PUSH_RATIO overrides the ratio (0: always scan).
+static int32_t push_ratio() {
+    const char *e = getenv("RAC_PUSH_RATIO");
+    if (e && *e) return (int32_t)std::max(0L, std::min(strtol(e, nullptr, 10), 1L << 30));
+    return 16;
+}
+
 static Launch base_launch(Runner &r, int32_t nprob, const rac_options &o) {
     Launch L;
     memset(&L, 0, sizeof(L));
@@ -857,6 +900,7 @@ static Launch base_launch(Runner &r, int32_t nprob, const rac_options &o) {
     L.rc_out = r.rc;
     L.checks_out = r.checks;
     L.arcs1 = 0;
+    L.push_ratio = push_ratio();
     return L;
 }
 

@@ -47,6 +47,9 @@ struct NetDesc {
     const int32_t *gptr;      // [n+1] group offsets (bit rows)
     const int32_t *nbrp;      // [groups*64] (bit rows)
     const int32_t *gown;      // [groups] the variable group g belongs to (bit rows)
+    const int32_t *rpos;      // [arcs] for arc j (y -> x in CSR order): the position g*64 + l
+                              // of the reverse arc x -> y in the group layout (bit rows),
+                              // or null (int8 rows)
     const int32_t *deg;       // [n]
     const void *rows;
     const int4 *items;        // [nitems] {x_begin, x_end, unit_begin, unit_end}; units are
@@ -54,6 +57,7 @@ struct NetDesc {
     const int32_t *pieces;    // [nitems] 0: whole variables; k >= 1: one piece of x split in k
     int32_t n, d, dp, kind;
     int32_t nitems, qpa;
+    int32_t pchunks;          // pieces of 64 arcs of the largest degree (bit rows)
     int64_t arcs;
 };
 
@@ -64,7 +68,8 @@ struct Ctrl {
     long long checks;       // support checks so far (d*d per re-examined arc)
     int32_t last_change;    // last step that removed a value (0 = none)
     int32_t wipe_step;      // first step after which some domain was empty (0 = none)
-    int32_t pad[8];         // 64 bytes
+    int32_t nchg[2];        // nchg[k & 1]: variables step k changed (listed in Workspace::clist)
+    int32_t pad[6];         // 64 bytes
 };
 
 // The problems that execute the next step and the prefix sums of their item
@@ -84,6 +89,8 @@ struct Workspace {
     Plan *plan;           // [1]
     int32_t *act;         // [nprob] problems of the next step
     int64_t *act_off;     // [nprob + 1] their item prefix sums
+    int32_t *act_push;    // [nprob] 1: the listed problem's items are its changed variables
+    int32_t *clist[2];    // clist[k & 1][off + i]: the i-th variable step k changed
 };
 
 // Everything one enforcement needs (passed by value to every kernel).
@@ -104,6 +111,8 @@ struct Launch {
     long long *checks_out;    // [nprob] or null
     long long arcs1;          // with changed0: arcs step 1 re-examines, per problem
     int32_t *rc_out;          // [1]: 1 if some problem reached max_sweeps unconverged
+    int32_t push_ratio;       // steps k >= 2 of a bit-row problem that re-examine at most
+                              // arcs / push_ratio arcs go variable by variable (0: never)
 };
 
 // Records a message for rac_last_error() and returns `code` (rac_host.hip).
@@ -111,6 +120,7 @@ int set_error(int code, const char *fmt, ...);
 
 // Kernel entry points (defined in sweep.hip), launched by rac_host.hip.
 __global__ void init_kernel(Launch L);
+__global__ void list_changed0_kernel(Launch L);
 __global__ void plan_kernel(Launch L, int k);
 __global__ void revise_kernel(Launch L, int k);
 __global__ void update_kernel(Launch L, int k);

@@ -405,6 +405,41 @@ DEV void process_i8_item(const Launch &L, const NetDesc &N, const DV &D, const i
     }
 }
 
+// One piece of a changed variable y of a bit-row problem, in a step that
+// re-examines few arcs (Proposition 2: only arcs x -> y into variables that
+// changed in the previous step). The arcs into y are found through y's own
+// arcs y -> x, whose reverse arc x -> y sits at rpos in the group layout;
+// piece c covers y's arcs 64c .. 64c+63, one per lane. A lane ORs the values
+// of x that have no support in D^(k-1)(y) into the accumulator of x.
+template <bool WIDE>
+DEV void process_push_item(const Launch &L, const NetDesc &N, int k, int64_t off, int32_t y,
+                           int32_t c) {
+    constexpr int RPQ = WIDE ? 2 : 4;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t j = N.row_ptr[y] + c * kWave + lane;
+    if (j >= N.row_ptr[y + 1]) return;
+    const GLOBAL u32x4 *rows = as_global((const u32x4 *)N.rows);
+    const uint64_t dy = L.ws.dom[(k - 1) & 1][off + y];
+    const int32_t pos = N.rpos[j];
+    const int32_t x = N.nbr[j];
+    const GLOBAL u32x4 *base = rows + (int64_t)(pos >> 6) * N.qpa * kGroup + (pos & (kGroup - 1));
+    uint64_t f = 0;
+    if (WIDE) {
+        for (int32_t q = 0; q < N.qpa; ++q)
+            f |= (uint64_t)quad_fail<true>(base[(int64_t)q * kGroup], dy) << (q * RPQ);
+    } else {
+        // qpa <= 8 for uint32 rows
+        u32x4 v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q < N.qpa) v[q] = base[q * kGroup];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q < N.qpa) f |= (uint64_t)quad_fail<false>(v[q], dy) << (q * RPQ);
+    }
+    if (f) or_fail(L, off + x, f);
+}
+
 // ---------------------------------------------------------------------------
 // Step control
 // ---------------------------------------------------------------------------
@@ -423,6 +458,13 @@ DEV bool active(const Launch &L, const NetDesc &N, const Ctrl &C, int k) {
     if (k > 1 && C.last_change < k - 1) return false;
     if (L.mode == RAC_STOP_ON_WIPEOUT && C.wipe_step != 0 && C.wipe_step < k) return false;
     return true;
+}
+
+// Does step k list its changed variables? Only when step k itself
+// re-examined few arcs (at most 4x the push bound): the change sets of later
+// steps are usually smaller, and dense steps skip the cost of the list.
+DEV bool listed_after(const Launch &L, const NetDesc &N, const Ctrl &C, int k) {
+    return L.push_ratio > 0 && N.rpos && C.arcs[(k + 2) % 3] * L.push_ratio <= 4 * N.arcs;
 }
 
 DEV int prob_of_var(const Launch &L, int64_t v) {
@@ -450,11 +492,23 @@ __global__ __launch_bounds__(1024) void plan_kernel(Launch L, int k) {
     for (int32_t p0 = 0; p0 < L.nprob; p0 += 1024) {
         const int32_t p = p0 + (int32_t)threadIdx.x;
         bool on = false;
+        int32_t push = 0;
         int64_t items = 0;
         if (p < L.nprob) {
             const NetDesc &N = L.nets[L.prob_net[p]];
-            on = active(L, N, L.ws.ctrl[p], k);
-            if (on) items = N.nitems;
+            const Ctrl &C = L.ws.ctrl[p];
+            on = active(L, N, C, k);
+            // few arcs to re-examine: the changed variables' pieces instead
+            // of a scan of every group (step 1 of an incremental start: the
+            // pieces of the listed @changed variables bound the arcs). Step
+            // k-1 listed its changed variables only if it was itself sparse.
+            if (on && L.push_ratio > 0 && N.rpos) {
+                if (k > 1)
+                    push = listed_after(L, N, C, k - 1) && C.arcs[(k - 1) % 3] * L.push_ratio <= N.arcs;
+                else if (L.changed0)
+                    push = (int64_t)C.nchg[0] * N.pchunks * kWave * L.push_ratio <= N.arcs;
+            }
+            if (on) items = push ? (int64_t)C.nchg[(k - 1) & 1] * N.pchunks : N.nitems;
         }
         // inclusive scan of the item counts within the wave, then across waves
         int64_t inc = items;
@@ -477,6 +531,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(Launch L, int k) {
         if (on) {
             L.ws.act[nbefore + rank] = p;
             L.ws.act_off[nbefore + rank] = before + inc - items;
+            L.ws.act_push[nbefore + rank] = push;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -566,6 +621,13 @@ __global__ __launch_bounds__(kWave) void revise_kernel(Launch L, int k) {
         const NetDesc &N = L.nets[L.prob_net[p]];
         const int64_t off = L.prob_off[p];
         const int32_t ci = (int32_t)(c - L.ws.act_off[a]);
+        if (L.ws.act_push[a]) {
+            const int32_t i = ci / N.pchunks;
+            const int32_t y = L.ws.clist[(k - 1) & 1][off + i];
+            if (N.kind == ROW64) process_push_item<true>(L, N, k, off, y, ci - i * N.pchunks);
+            else process_push_item<false>(L, N, k, off, y, ci - i * N.pchunks);
+            continue;
+        }
         const int4 it = N.items[ci];
         const int32_t pieces = N.pieces[ci];
         const uint64_t *gdom = L.ws.dom[(k - 1) & 1] + off;
@@ -603,25 +665,30 @@ struct UpdRed {
 };
 
 // Step k, update: D^(k)(v) = D^(k-1)(v) minus its accumulated failures, the
-// @changed flag of step k, and per problem the last step with a change, the
-// first step with a wipe-out, the arcs the next step re-examines (arcs into
-// changed variables) and the support checks of step k (d*d per arc it
-// re-examined).
+// @changed flag of step k (also as a list per problem), and per problem the
+// last step with a change, the first step with a wipe-out, the arcs the next
+// step re-examines (arcs into changed variables) and the support checks of
+// step k (d*d per arc it re-examined).
 __global__ __launch_bounds__(256) void update_kernel(Launch L, int k) {
     __shared__ UpdRed s_red;
     const int s_now = k % 3, s_prev = (k + 2) % 3, s_next = (k + 1) % 3;
     const int64_t nv = L.prob_off[L.nprob];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (blockIdx.x == 0)
-        for (int32_t p = threadIdx.x; p < L.nprob; p += blockDim.x) L.ws.ctrl[p].arcs[s_next] = 0;
+        for (int32_t p = threadIdx.x; p < L.nprob; p += blockDim.x) {
+            L.ws.ctrl[p].arcs[s_next] = 0;
+            L.ws.ctrl[p].nchg[(k + 1) & 1] = 0;   // the list step k+1 appends to
+        }
+    int32_t *clist = L.ws.clist[k & 1];
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nv;
          base += (int64_t)gridDim.x * blockDim.x) {
         const int64_t v = base + threadIdx.x;
         const int64_t vlast = base + blockDim.x - 1 < nv ? base + blockDim.x - 1 : nv - 1;
         const int pb0 = prob_of_var(L, base), pb1 = prob_of_var(L, vlast);
-        bool ch = false, wp = false;
+        bool ch = false, wp = false, lst = false;
         unsigned long long dg = 0;
         int p = -1;
+        int32_t x = 0;
         if (v < nv) {
             p = pb0 == pb1 ? pb0 : prob_of_var(L, v);
             const NetDesc &N = L.nets[L.prob_net[p]];
@@ -635,14 +702,25 @@ __global__ __launch_bounds__(256) void update_kernel(Launch L, int k) {
                 wp = nd == 0;
                 L.ws.dom[k & 1][v] = nd;
                 L.ws.chg[k & 1][v] = ch ? 1u : 0u;
-                const int32_t x = (int32_t)(v - L.prob_off[p]);
+                x = (int32_t)(v - L.prob_off[p]);
                 if (ch) dg = (unsigned long long)N.deg[x];
+                lst = ch && listed_after(L, N, C, k);
                 if (x == 0) C.checks += C.arcs[s_prev] * (long long)N.d * N.d;
             }
         }
         if (pb0 == pb1) {   // the whole block is one problem: one atomic per block
             const uint64_t mc = __ballot(ch), mw = __ballot(wp);
             const unsigned long long ws = wave_sum64(dg);
+            const uint64_t ml = __ballot(lst);
+            if (ml) {   // the wave's changed variables join the problem's list
+                const int leader = __ffsll((unsigned long long)ml) - 1;
+                int32_t at = 0;
+                if (lane == leader)
+                    at = __hip_atomic_fetch_add(&L.ws.ctrl[pb0].nchg[k & 1], __popcll(ml),
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                at = __shfl(at, leader, 64);
+                if (lst) clist[L.prob_off[pb0] + at + lane_rank(ml)] = x;
+            }
             if (lane == 0) {
                 s_red.deg[wave] = ws;
                 s_red.changed[wave] = mc != 0;
@@ -672,6 +750,11 @@ __global__ __launch_bounds__(256) void update_kernel(Launch L, int k) {
                 (void)__hip_atomic_fetch_add(&C.arcs[s_now], (long long)dg, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
                 C.last_change = k;
+                if (lst) {
+                    const int32_t r = __hip_atomic_fetch_add(&C.nchg[k & 1], 1, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                    clist[L.prob_off[p] + r] = x;
+                }
             }
             if (wp && C.wipe_step == 0) C.wipe_step = k;
         }
@@ -697,8 +780,41 @@ __global__ void init_kernel(Launch L) {
         C.checks = 0;
         C.last_change = 0;
         C.wipe_step = 0;
+        C.nchg[0] = 0;
+        C.nchg[1] = 0;
     }
     if (tid == 0 && L.rc_out) *L.rc_out = 0;
+}
+
+// With an initial @changed set: list its variables per problem (the
+// changed-variable list of "step 0"), after init_kernel has zeroed the counts.
+__global__ void list_changed0_kernel(Launch L) {
+    const int64_t nv = L.prob_off[L.nprob];
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = tid - lane; base < nv; base += nthreads) {
+        const int64_t v = base + lane;
+        const bool c = v < nv && L.changed0[v];
+        const int64_t vl = base + 63 < nv ? base + 63 : nv - 1;
+        const int p0 = prob_of_var(L, base), p1 = prob_of_var(L, vl);
+        const uint64_t m = __ballot(c);
+        if (!m) continue;
+        if (p0 == p1) {   // one problem: one atomic for the wave
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            int32_t at = 0;
+            if (lane == leader)
+                at = __hip_atomic_fetch_add(&L.ws.ctrl[p0].nchg[0], __popcll(m), __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+            at = __shfl(at, leader, 64);
+            if (c) L.ws.clist[0][L.prob_off[p0] + at + lane_rank(m)] = (int32_t)(v - L.prob_off[p0]);
+        } else if (c) {
+            const int p = prob_of_var(L, v);
+            const int32_t r = __hip_atomic_fetch_add(&L.ws.ctrl[p].nchg[0], 1, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+            L.ws.clist[0][L.prob_off[p] + r] = (int32_t)(v - L.prob_off[p]);
+        }
+    }
 }
 
 __global__ void finish_kernel(Launch L) {

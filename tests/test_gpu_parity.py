@@ -183,6 +183,25 @@ def test_group_of_networks(use_graph):
         n_.close()
 
 
+@pytest.mark.parametrize("ratio", ["0", "1"])
+def test_scan_and_changed_variable_steps(ratio, monkeypatch):
+    # Steps k >= 2 of the bit-row path either scan every group for arcs into
+    # changed variables, or walk the changed variables' own arcs (reverse-arc
+    # table). RAC_PUSH_RATIO 0 forces the scan, 1 the changed-variable walk;
+    # both must give the oracle's results, uint32 and uint64 rows alike.
+    monkeypatch.setenv("RAC_PUSH_RATIO", ratio)
+    for seed in range(1, 72, 5):
+        inst, dom = _tiny(seed)
+        for mode in (0, 1):
+            gpu_vs_oracle(f"tiny{seed}-r{ratio}", inst.n, inst.d, inst.edges, inst.rel_u8(), dom,
+                          rac.PATH_BITS, mode)
+    for d in (3, 32, 33, 64):
+        test_medium_bits(d, 0)
+    test_incremental_start()
+    test_batch_states_bits(True)
+    test_group_of_networks(True)
+
+
 def test_empty_domains_and_isolated_variables():
     n, d = 7, 5
     edges = np.array([[0, 1], [1, 2], [4, 5]], np.int32)
