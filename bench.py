@@ -189,6 +189,8 @@ def parse():
                     help="approximate budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-search", action="store_true",
+                    help="skip the MAC-search lines in the secondary results")
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the 256-instance uneven batch in the secondary results")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -256,6 +258,35 @@ def cpu_baseline_single(inst, dom, budget_s):
     return dict(value=checks / t, unit="support checks/s", cores=1, kind="oracle",
                 sample=f"oracle Eq. (1) recurrence, one thread, {reps} run(s) of the instance",
                 fixpoints_per_s=1.0 / t, ac3_fixpoints_per_s=1.0 / t_ac3)
+
+
+def search_lines():
+    """Batched MAC search (Algorithm 2) on two instances: every child of up to
+    1024 open nodes enforced together per round, against one node per round."""
+    import numpy as np
+
+    from paper_2407_11388_amd import gen, rac
+    out = {}
+    qe, qr = gen.queens(11)
+    mb = gen.model_b(110, 100, 10, 0.1, 0.4)
+    for name, (n, d, edges, rel) in (
+            ("mac-search queens-11 (all solutions)", (11, 11, qe, qr)),
+            ("mac-search model-B n=100 d=10 p1=0.1 p2=0.4 (complete, unsatisfiable)",
+             (100, 10, mb.edges, mb.rel_u8()))):
+        net = rac.Net.from_u8(n, d, edges, rel)
+        root = np.full(n, (1 << d) - 1, dtype=np.uint64)
+        line = {}
+        for b in (1024, 1):
+            net.search(root, batch=b, max_nodes=2000 if b == 1 else 0)   # warm-up
+            res, _ = net.search(root, batch=b, max_nodes=0 if b == 1024 else 20000)
+            line[f"batch{b}"] = dict(nodes=int(res.nodes), solutions=int(res.solutions),
+                                     failures=int(res.failures), complete=int(res.complete),
+                                     rounds=int(res.rounds), ms=res.search_ms,
+                                     nodes_per_s=res.nodes / (res.search_ms * 1e-3))
+        line["batched_vs_one_node"] = line["batch1024"]["nodes_per_s"] / line["batch1"]["nodes_per_s"]
+        out[name] = line
+        net.close()
+    return out
 
 
 def main():
@@ -428,6 +459,8 @@ def main():
             grp.close()
             for nt in nets:
                 nt.close()
+        if not args.no_search:
+            sec.update(search_lines())
         out["secondary"] = sec
 
     print(json.dumps(out), flush=True)

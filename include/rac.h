@@ -197,6 +197,39 @@ int rac_group_enforce_device(rac_group *g, uint64_t *d_dom, int32_t *d_iters,
 int rac_group_sync_status(rac_group *g);
 void rac_group_destroy(rac_group *g);
 
+/*
+ * Batched MAC search (Algorithm 2: depth-first search that enforces arc
+ * consistency after every assignment). The root domains `dom` ([n] host
+ * uint64) are enforced first. Every open node then branches on the variable
+ * with the smallest domain of size > 1 (lowest index on ties) into one child
+ * per value (ascending); each child is enforced with @changed = {that
+ * variable} (Proposition 2: its parent was arc consistent). A child whose
+ * enforcement empties a domain is a failure; one whose domains are all
+ * singletons is a solution (an arc-consistent state of singletons satisfies
+ * every constraint); the others stay open. Up to `batch` open nodes (0: 256)
+ * are taken from the top of a LIFO stack per round and all their children
+ * are enforced together on the device.
+ *   max_solutions, max_nodes: stop once that many solutions were found or
+ *     nodes enforced (0: no limit); the round in progress completes.
+ *   solution: [n] host uint64 or NULL; receives the lexicographically
+ *     smallest solution found (value of variable 0 first), if any.
+ * With no limit hit (out->complete = 1) the explored tree, the counts and the
+ * returned solution do not depend on `batch`. Domains and relations as for
+ * rac_enforce; uses the net's bit-row path (int8 if that is the net's path).
+ */
+typedef struct rac_search_result {
+    int64_t solutions;   /* solutions found */
+    int64_t nodes;       /* nodes enforced: the root and every child */
+    int64_t failures;    /* enforced nodes that wiped out */
+    int64_t rounds;      /* batched rounds (device enforcement calls after the root) */
+    int32_t complete;    /* 1: the whole tree was explored */
+    int32_t reserved;
+    double search_ms;    /* wall-clock time of the call */
+} rac_search_result;
+
+int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutions, int64_t max_nodes,
+               int32_t batch, uint64_t *solution, rac_search_result *out);
+
 /* Counters of the last call on a net / group (host-pointer calls, or after a
  * rac_sync_status / rac_group_sync_status). */
 int rac_net_stats(const rac_net *net, rac_stats *out);

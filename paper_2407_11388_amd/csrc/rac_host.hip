@@ -2,6 +2,7 @@
 // layout, device-side packing of relation rows, work items, and the launch of
 // the per-step fixpoint kernels (directly, or as replayed HIP graphs of rounds of steps).
 #include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -971,7 +972,7 @@ static int pick_path(const rac_net *net, int32_t B, int32_t requested) {
 
 // Bit / int8 path for B states already in r.din (host waits between rounds).
 static int run_states(rac_net *net, int32_t B, int32_t path, const uint8_t *d_changed,
-                      long long arcs1) {
+                      long long arcs1, bool allow_graph = true) {
     PathData &pd = path == RAC_PATH_INT8 ? net->i8 : net->bits;
     RAC_TRY(ensure_path(net, path, call_target(net, B)));
     Runner &r = net->run;
@@ -986,7 +987,7 @@ static int run_states(rac_net *net, int32_t B, int32_t path, const uint8_t *d_ch
     L.arcs1 = arcs1;
     RAC_TRY(launch_fixpoint(r, net->device, net->stream, L, (int64_t)B * net->n,
                             (int64_t)pd.nitems * B, step_cap(net->opt, (int64_t)net->n * net->d),
-                            net->opt.use_graph != 0, net->opt.profile != 0));
+                            allow_graph && net->opt.use_graph != 0, net->opt.profile != 0));
     return RAC_OK;
 }
 
@@ -1088,6 +1089,178 @@ static int run_mfma(rac_net *net, int32_t B, const uint64_t *d_in, uint64_t *d_o
     }
     RAC_TRY(mfma_finish(net->mfma, d_it, d_st, s));
     return RAC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched MAC search (Algorithm 2)
+// ---------------------------------------------------------------------------
+
+namespace {
+struct SearchBufs {
+    uint64_t *stack = nullptr, *best = nullptr;
+    int32_t *bvar = nullptr, *nchild = nullptr, *coff = nullptr, *has_best = nullptr;
+    int32_t *is_sol = nullptr, *is_open = nullptr, *sol_off = nullptr, *open_off = nullptr,
+            *sol_list = nullptr;
+    int64_t cap = 0;   // stack capacity in nodes
+    ~SearchBufs() {
+        dfree(stack);
+        dfree(best);
+        dfree(bvar);
+        dfree(nchild);
+        dfree(coff);
+        dfree(has_best);
+        dfree(is_sol);
+        dfree(is_open);
+        dfree(sol_off);
+        dfree(open_off);
+        dfree(sol_list);
+    }
+};
+
+bool all_singletons(const uint64_t *dom, int32_t n) {
+    for (int32_t x = 0; x < n; ++x)
+        if (__builtin_popcountll(dom[x]) != 1) return false;
+    return true;
+}
+}  // namespace
+
+extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutions,
+                          int64_t max_nodes, int32_t batch, uint64_t *solution,
+                          rac_search_result *out) {
+    if (!net || !dom || !out) return set_error(RAC_EINVAL, "net, dom or out is NULL");
+    if (batch < 0 || max_solutions < 0 || max_nodes < 0)
+        return set_error(RAC_EINVAL, "negative batch or limit");
+    const int32_t n = net->n, d = net->d;
+    if (n >= (1 << 20)) return set_error(RAC_EUNSUPPORTED, "search supports n < 2^20");
+    RAC_TRY(check_domains(dom, n, d));
+    HIP_TRY(hipSetDevice(net->device));
+    const auto t0 = std::chrono::steady_clock::now();
+    memset(out, 0, sizeof(*out));
+    if (batch == 0) batch = 256;
+    batch = std::min<int32_t>(batch, 1 << 16);
+    const int32_t path = net->opt.path == RAC_PATH_INT8 ? RAC_PATH_INT8 : RAC_PATH_BITS;
+    PathData &pd = path == RAC_PATH_INT8 ? net->i8 : net->bits;
+    // a wipe-out anywhere ends a node: stop on the first one (same status as
+    // running to the fixpoint, fewer steps)
+    struct ModeGuard {
+        rac_net *net;
+        int32_t mode;
+        ~ModeGuard() { net->opt.mode = mode; }
+    } guard{net, net->opt.mode};
+    net->opt.mode = RAC_STOP_ON_WIPEOUT;
+    Runner &r = net->run;
+    hipStream_t s = net->stream;
+
+    // the root: full enforcement
+    RAC_TRY(ensure_path(net, path, call_target(net, 1)));
+    RAC_TRY(prepare_net_runner(net, 1, pd));
+    HIP_TRY(hipMemcpyAsync(r.din, dom, (size_t)n * 8, hipMemcpyHostToDevice, s));
+    RAC_TRY(run_states(net, 1, path, nullptr, 0, false));
+    std::vector<uint64_t> root((size_t)n);
+    int32_t root_status = 0, hrc = 0;
+    HIP_TRY(hipMemcpyAsync(root.data(), r.dout, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&root_status, r.status, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&hrc, r.rc, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    RAC_TRY(rc_from_device(hrc));
+    out->nodes = 1;
+    auto finish = [&]() {
+        out->search_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return RAC_OK;
+    };
+    if (root_status == RAC_WIPEOUT) {
+        out->failures = 1;
+        out->complete = 1;
+        return finish();
+    }
+    if (all_singletons(root.data(), n)) {
+        out->solutions = 1;
+        out->complete = 1;
+        if (solution) memcpy(solution, root.data(), (size_t)n * 8);
+        return finish();
+    }
+
+    // device buffers: the stack and the per-round lists
+    const int32_t cmax = batch * d;
+    SearchBufs b;
+    b.cap = std::max<int64_t>(4 * (int64_t)cmax, 1024);
+    RAC_TRY(dalloc(&b.stack, (size_t)(b.cap * n)));
+    RAC_TRY(dalloc(&b.best, (size_t)n));
+    RAC_TRY(dalloc(&b.bvar, (size_t)batch));
+    RAC_TRY(dalloc(&b.nchild, (size_t)batch));
+    RAC_TRY(dalloc(&b.coff, (size_t)batch + 1));
+    RAC_TRY(dalloc(&b.has_best, 1));
+    RAC_TRY(dalloc(&b.is_sol, (size_t)cmax));
+    RAC_TRY(dalloc(&b.is_open, (size_t)cmax));
+    RAC_TRY(dalloc(&b.sol_off, (size_t)cmax + 1));
+    RAC_TRY(dalloc(&b.open_off, (size_t)cmax + 1));
+    RAC_TRY(dalloc(&b.sol_list, (size_t)cmax));
+    HIP_TRY(hipMemsetAsync(b.has_best, 0, 4, s));
+    HIP_TRY(hipMemcpyAsync(b.stack, root.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+    RAC_TRY(ensure_path(net, path, call_target(net, cmax)));
+    RAC_TRY(ensure_runner(r, cmax, (int64_t)cmax * n));
+    int64_t ssize = 1;
+    while (true) {
+        if (ssize == 0) {
+            out->complete = 1;
+            break;
+        }
+        if (max_solutions > 0 && out->solutions >= max_solutions) break;
+        if (max_nodes > 0 && out->nodes >= max_nodes) break;
+        const int32_t P = (int32_t)std::min<int64_t>(ssize, batch);
+        const int64_t base = ssize - P;   // the top P nodes
+        const uint64_t *top = b.stack + base * n;
+        hipLaunchKernelGGL(search_branch_kernel, dim3((unsigned)P), dim3(64), 0, s, top, n, b.bvar,
+                           b.nchild);
+        hipLaunchKernelGGL(search_offsets_kernel, dim3(1), dim3(1024), 0, s, b.nchild, P, b.coff);
+        int32_t C = 0;
+        HIP_TRY(hipMemcpyAsync(&C, b.coff + P, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        RAC_TRY(prepare_net_runner(net, C, pd));
+        hipLaunchKernelGGL(search_expand_kernel, dim3((unsigned)P), dim3(256), 0, s, top, n, b.bvar,
+                           b.coff, r.din, r.changed);
+        HIP_TRY(hipGetLastError());
+        ssize = base;
+        RAC_TRY(run_states(net, C, path, r.changed, -1, false));
+        hipLaunchKernelGGL(search_classify_kernel, dim3((unsigned)C), dim3(64), 0, s, r.dout,
+                           r.status, n, b.is_sol, b.is_open);
+        hipLaunchKernelGGL(search_lists_kernel, dim3(1), dim3(1024), 0, s, b.is_sol, b.is_open, C,
+                           b.sol_off, b.open_off);
+        int32_t cnt[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(&cnt[0], b.sol_off + C, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&cnt[1], b.open_off + C, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&hrc, r.rc, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        RAC_TRY(rc_from_device(hrc));
+        const int32_t nsol = cnt[0], nopen = cnt[1];
+        if (ssize + nopen > b.cap) {   // grow the stack (device copy of the live part)
+            const int64_t ncap = std::max<int64_t>(2 * b.cap, ssize + nopen);
+            uint64_t *ns = nullptr;
+            RAC_TRY(dalloc(&ns, (size_t)(ncap * n)));
+            HIP_TRY(hipMemcpyAsync(ns, b.stack, (size_t)(ssize * n) * 8, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            dfree(b.stack);
+            b.stack = ns;
+            b.cap = ncap;
+        }
+        hipLaunchKernelGGL(search_push_kernel, dim3((unsigned)C), dim3(256), 0, s, r.dout, n, C,
+                           b.is_sol, b.is_open, b.sol_off, b.open_off, b.stack, ssize, b.sol_list);
+        if (nsol > 0)
+            hipLaunchKernelGGL(search_best_kernel, dim3(1), dim3(1024), 0, s, r.dout, n, b.sol_list,
+                               b.sol_off, C, b.best, b.has_best);
+        HIP_TRY(hipGetLastError());
+        out->nodes += C;
+        out->solutions += nsol;
+        out->failures += C - nsol - nopen;
+        ssize += nopen;
+        out->rounds += 1;
+    }
+    int32_t has = 0;
+    HIP_TRY(hipMemcpyAsync(&has, b.has_best, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (has && solution)
+        HIP_TRY(hipMemcpy(solution, b.best, (size_t)n * 8, hipMemcpyDeviceToHost));
+    return finish();
 }
 
 extern "C" int rac_enforce_batch(rac_net *net, int32_t B, uint64_t *dom, int32_t *iters,

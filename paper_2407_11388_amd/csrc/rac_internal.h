@@ -110,6 +110,7 @@ struct Launch {
     const uint8_t *changed0;  // [prob_off[nprob]] initial @changed flags, or null (= all)
     long long *checks_out;    // [nprob] or null
     long long arcs1;          // with changed0: arcs step 1 re-examines, per problem
+                              // (< 0: each problem's sum of deg over its @changed set)
     int32_t *rc_out;          // [1]: 1 if some problem reached max_sweeps unconverged
     int32_t push_ratio;       // steps k >= 2 of a bit-row problem that re-examine at most
                               // arcs / push_ratio arcs go variable by variable (0: never)
@@ -129,5 +130,23 @@ __global__ void pack_bits_kernel(const uint64_t *rel, const int32_t *src_p, int6
                                  int32_t d, int32_t qpa, int32_t kind, uint4 *out);
 __global__ void pack_i8_kernel(const uint64_t *rel, const int32_t *arc_src, int64_t arcs,
                                int32_t d, int32_t rows_per_arc, int32_t dp, int8_t *out);
+
+// Batched MAC search (search.hip).
+__global__ void search_branch_kernel(const uint64_t *nodes, int32_t n, int32_t *bvar,
+                                     int32_t *nchild);
+__global__ void search_offsets_kernel(const int32_t *nchild, int32_t P, int32_t *coff);
+__global__ void search_expand_kernel(const uint64_t *nodes, int32_t n, const int32_t *bvar,
+                                     const int32_t *coff, uint64_t *cdom, uint8_t *cchg);
+__global__ void search_classify_kernel(const uint64_t *cres, const int32_t *status, int32_t n,
+                                       int32_t *is_sol, int32_t *is_open);
+__global__ void search_lists_kernel(const int32_t *is_sol, const int32_t *is_open, int32_t C,
+                                    int32_t *sol_off, int32_t *open_off);
+__global__ void search_push_kernel(const uint64_t *cres, int32_t n, int32_t C, const int32_t *is_sol,
+                                   const int32_t *is_open, const int32_t *sol_off,
+                                   const int32_t *open_off, uint64_t *stack, int64_t base,
+                                   int32_t *sol_list);
+__global__ void search_best_kernel(const uint64_t *cres, int32_t n, const int32_t *sol_list,
+                                   const int32_t *sol_off, int32_t C, uint64_t *best,
+                                   int32_t *has_best);
 
 }  // namespace rac

@@ -1,0 +1,184 @@
+// Kernels of the batched MAC search (Algorithm 2: depth-first search that
+// enforces arc consistency after every assignment). A round takes the top P
+// nodes of the device stack, branches each on one variable, enforces all
+// children together (the bit-row step kernels, @changed = the assigned
+// variable, Proposition 2), and sorts the children into failures, solutions
+// and nodes pushed back onto the stack.
+#include "rac.h"
+#include "rac_internal.h"
+
+namespace rac {
+
+namespace {
+
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Exclusive prefix sums of cnt[0..N) into off[0..N], off[N] = total, by one
+// workgroup of 1024 threads (16 waves), in chunks of 1024.
+__device__ void block_scan(const int32_t *cnt, int32_t N, int32_t *off) {
+    __shared__ int32_t s_wave[16];
+    __shared__ int32_t s_base;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_base = 0;
+    __syncthreads();
+    for (int32_t c0 = 0; c0 < N; c0 += 1024) {
+        const int32_t i = c0 + (int32_t)threadIdx.x;
+        const int32_t v = i < N ? cnt[i] : 0;
+        int32_t inc = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += t;
+        }
+        if (lane == 63) s_wave[wave] = inc;
+        __syncthreads();
+        int32_t before = s_base;
+        for (int w = 0; w < wave; ++w) before += s_wave[w];
+        if (i < N) off[i] = before + inc - v;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int w = 0; w < 16; ++w) s_base += s_wave[w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) off[N] = s_base;
+}
+
+}  // namespace
+
+// Branching choice of node i (one wave per node): the variable with the
+// smallest domain of size > 1 (lowest index on ties), and its domain size
+// (the node's number of children). Nodes on the stack are arc consistent,
+// not wiped out and not yet solutions, so such a variable exists.
+__global__ __launch_bounds__(64) void search_branch_kernel(const uint64_t *nodes, int32_t n,
+                                                           int32_t *bvar, int32_t *nchild) {
+    const int32_t i = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint64_t *dom = nodes + (int64_t)i * n;
+    int best = 0x7FFFFFFF;   // (size << 20) | variable, sizes <= 64, n < 2^20
+    for (int32_t x = lane; x < n; x += 64) {
+        const int s = __popcll(dom[x]);
+        if (s > 1) best = min(best, (s << 20) | x);
+    }
+    best = wave_min_int(best);
+    if (lane == 0) {
+        bvar[i] = best & 0xFFFFF;
+        nchild[i] = best >> 20;
+    }
+}
+
+// Child offsets: coff[i] = children of nodes 0..i-1, coff[P] = all children.
+__global__ __launch_bounds__(1024) void search_offsets_kernel(const int32_t *nchild, int32_t P,
+                                                              int32_t *coff) {
+    block_scan(nchild, P, coff);
+}
+
+// Children of node i (one workgroup per node): child j takes the j-th value
+// of the branching variable (ascending); its @changed set is that variable.
+__global__ __launch_bounds__(256) void search_expand_kernel(const uint64_t *nodes, int32_t n,
+                                                            const int32_t *bvar,
+                                                            const int32_t *coff, uint64_t *cdom,
+                                                            uint8_t *cchg) {
+    const int32_t i = blockIdx.x;
+    const int32_t xb = bvar[i];
+    const uint64_t *dom = nodes + (int64_t)i * n;
+    const int32_t c0 = coff[i], c1 = coff[i + 1];
+    uint64_t rest = dom[xb];
+    for (int32_t c = c0; c < c1; ++c) {
+        const uint64_t v = rest & (~rest + 1ull);   // lowest remaining value
+        rest &= rest - 1ull;
+        uint64_t *out = cdom + (int64_t)c * n;
+        uint8_t *chg = cchg + (int64_t)c * n;
+        for (int32_t x = threadIdx.x; x < n; x += blockDim.x) {
+            out[x] = x == xb ? v : dom[x];
+            chg[x] = x == xb ? 1 : 0;
+        }
+    }
+}
+
+// Kind of each enforced child, as 0/1 flags for the list scans that follow:
+// a solution (not wiped out, every domain a singleton) or open (not wiped
+// out, some domain larger); neither means a failure. One wave per child.
+__global__ __launch_bounds__(64) void search_classify_kernel(const uint64_t *cres,
+                                                             const int32_t *status, int32_t n,
+                                                             int32_t *is_sol, int32_t *is_open) {
+    const int32_t c = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint64_t *dom = cres + (int64_t)c * n;
+    int multi = 0;
+    for (int32_t x = lane; x < n; x += 64) multi |= __popcll(dom[x]) > 1;
+    multi = __any(multi) ? 1 : 0;
+    if (lane == 0) {
+        const bool wiped = status[c] == RAC_WIPEOUT;
+        is_sol[c] = (!wiped && !multi) ? 1 : 0;
+        is_open[c] = (!wiped && multi) ? 1 : 0;
+    }
+}
+
+// Offsets of the solution and open lists (two scans in one workgroup).
+__global__ __launch_bounds__(1024) void search_lists_kernel(const int32_t *is_sol,
+                                                            const int32_t *is_open, int32_t C,
+                                                            int32_t *sol_off, int32_t *open_off) {
+    block_scan(is_sol, C, sol_off);
+    __syncthreads();
+    block_scan(is_open, C, open_off);
+}
+
+// Open children go onto the stack above `base`, the last child lowest, so
+// that the first child (the smallest value of the first node) ends on top;
+// solutions are listed in child order.
+__global__ __launch_bounds__(256) void search_push_kernel(const uint64_t *cres, int32_t n, int32_t C,
+                                                          const int32_t *is_sol,
+                                                          const int32_t *is_open,
+                                                          const int32_t *sol_off,
+                                                          const int32_t *open_off, uint64_t *stack,
+                                                          int64_t base, int32_t *sol_list) {
+    const int32_t c = blockIdx.x;
+    if (c >= C) return;
+    if (is_sol[c] && threadIdx.x == 0) sol_list[sol_off[c]] = c;
+    if (!is_open[c]) return;
+    const int32_t nopen = open_off[C];
+    const int64_t at = base + (nopen - 1 - open_off[c]);
+    const uint64_t *src = cres + (int64_t)c * n;
+    uint64_t *dst = stack + at * n;
+    for (int32_t x = threadIdx.x; x < n; x += blockDim.x) dst[x] = src[x];
+}
+
+// The lexicographically smallest solution (value of variable 0 first, then
+// 1, ...) among `best` (if has_best) and the listed solutions. One
+// workgroup: per candidate, the first variable where it differs from the
+// current best decides.
+__global__ __launch_bounds__(1024) void search_best_kernel(const uint64_t *cres, int32_t n,
+                                                           const int32_t *sol_list,
+                                                           const int32_t *sol_off, int32_t C,
+                                                           uint64_t *best, int32_t *has_best) {
+    __shared__ int32_t s_first;
+    const int32_t ns = sol_off[C];
+    for (int32_t k = 0; k < ns; ++k) {
+        const uint64_t *cand = cres + (int64_t)sol_list[k] * n;
+        if (*has_best == 0) {
+            for (int32_t x = threadIdx.x; x < n; x += blockDim.x) best[x] = cand[x];
+            __syncthreads();
+            if (threadIdx.x == 0) *has_best = 1;
+            __syncthreads();
+            continue;
+        }
+        if (threadIdx.x == 0) s_first = n;
+        __syncthreads();
+        for (int32_t x = threadIdx.x; x < n; x += blockDim.x)
+            if (cand[x] != best[x]) atomicMin(&s_first, x);
+        __syncthreads();
+        const int32_t f = s_first;
+        // singletons: the lower bit is the smaller value
+        const bool smaller = f < n && cand[f] < best[f];
+        __syncthreads();
+        if (smaller)
+            for (int32_t x = threadIdx.x; x < n; x += blockDim.x) best[x] = cand[x];
+        __syncthreads();
+    }
+}
+
+}  // namespace rac

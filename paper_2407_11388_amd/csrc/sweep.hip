@@ -774,7 +774,8 @@ __global__ void init_kernel(Launch L) {
     for (int64_t p = tid; p < L.nprob; p += nthreads) {
         const NetDesc &N = L.nets[L.prob_net[p]];
         Ctrl &C = L.ws.ctrl[p];
-        C.arcs[0] = L.changed0 ? L.arcs1 : N.arcs;   // arcs step 1 re-examines
+        // arcs step 1 re-examines (arcs1 < 0: summed by list_changed0_kernel)
+        C.arcs[0] = L.changed0 ? (L.arcs1 < 0 ? 0 : L.arcs1) : N.arcs;
         C.arcs[1] = 0;
         C.arcs[2] = 0;
         C.checks = 0;
@@ -787,7 +788,8 @@ __global__ void init_kernel(Launch L) {
 }
 
 // With an initial @changed set: list its variables per problem (the
-// changed-variable list of "step 0"), after init_kernel has zeroed the counts.
+// changed-variable list of "step 0"), after init_kernel has zeroed the counts;
+// with arcs1 < 0 also each problem's arcs into them (sum of deg).
 __global__ void list_changed0_kernel(Launch L) {
     const int64_t nv = L.prob_off[L.nprob];
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -808,11 +810,23 @@ __global__ void list_changed0_kernel(Launch L) {
                                             __HIP_MEMORY_SCOPE_AGENT);
             at = __shfl(at, leader, 64);
             if (c) L.ws.clist[0][L.prob_off[p0] + at + lane_rank(m)] = (int32_t)(v - L.prob_off[p0]);
+            if (L.arcs1 < 0) {
+                const NetDesc &N = L.nets[L.prob_net[p0]];
+                const unsigned long long dg =
+                    wave_sum64(c ? (unsigned long long)N.deg[v - L.prob_off[p0]] : 0ull);
+                if (lane == leader)
+                    (void)__hip_atomic_fetch_add(&L.ws.ctrl[p0].arcs[0], (long long)dg,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         } else if (c) {
             const int p = prob_of_var(L, v);
             const int32_t r = __hip_atomic_fetch_add(&L.ws.ctrl[p].nchg[0], 1, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT);
             L.ws.clist[0][L.prob_off[p] + r] = (int32_t)(v - L.prob_off[p]);
+            if (L.arcs1 < 0)
+                (void)__hip_atomic_fetch_add(&L.ws.ctrl[p].arcs[0],
+                                             (long long)L.nets[L.prob_net[p]].deg[v - L.prob_off[p]],
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }

@@ -204,3 +204,18 @@ def random_tiny(seed: int, n: int, d: int, p1: float, p2: float, dom_keep: float
                     mask[x] |= np.uint64(1) << np.uint64(a)
         dom = dom & mask
     return inst, dom
+
+
+def queens(n: int):
+    """The n-queens problem as a binary CSP: variable i is the column of the
+    queen in row i; every pair of rows needs different columns and different
+    diagonals. Returns (edges int32 [m, 2], relations uint8 [m, n, n])."""
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n)]
+    edges = np.array(pairs, dtype=np.int32).reshape(-1, 2)
+    a = np.arange(n).reshape(-1, 1)
+    b = np.arange(n).reshape(1, -1)
+    rel = np.zeros((len(pairs), n, n), dtype=np.uint8)
+    for e, (i, j) in enumerate(pairs):
+        rel[e] = ((a != b) & (np.abs(a - b) != j - i)).astype(np.uint8)
+    return edges, rel
+

@@ -40,7 +40,7 @@ EXPORTED = [
     "rac_enforce", "rac_enforce_batch", "rac_enforce_batch_device", "rac_sync_status",
     "rac_enforce_multi", "rac_group_create", "rac_group_enforce", "rac_group_enforce_device",
     "rac_group_sync_status", "rac_group_destroy", "rac_net_stats", "rac_group_stats",
-    "rac_net_info", "rac_strerror", "rac_last_error",
+    "rac_net_info", "rac_search", "rac_strerror", "rac_last_error",
 ]
 
 
@@ -63,6 +63,13 @@ class rac_stats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int64),
                 ("algo_ops", ctypes.c_int64), ("path", ctypes.c_int32),
                 ("item_bytes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+
+
+class rac_search_result(ctypes.Structure):
+    _fields_ = [("solutions", ctypes.c_int64), ("nodes", ctypes.c_int64),
+                ("failures", ctypes.c_int64), ("rounds", ctypes.c_int64),
+                ("complete", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("search_ms", ctypes.c_double)]
 
 
 def _share_runtime_with_torch():
@@ -103,6 +110,7 @@ def _load():
         "rac_net_stats": ([vp, vp], ctypes.c_int),
         "rac_group_stats": ([vp, vp], ctypes.c_int),
         "rac_net_info": ([vp, vp, vp, vp, vp], ctypes.c_int),
+        "rac_search": ([vp, vp, i64, i64, i32, vp, vp], ctypes.c_int),
         "rac_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "rac_last_error": ([], ctypes.c_char_p),
     }
@@ -223,6 +231,17 @@ class Net:
         _check(lib.rac_enforce_batch_device(self.handle, B, _ptr(d_in), _ptr(d_out), _ptr(d_iters),
                                             _ptr(d_status), stream or None),
                "rac_enforce_batch_device")
+
+    def search(self, dom: np.ndarray, max_solutions: int = 0, max_nodes: int = 0,
+               batch: int = 0):
+        """Batched MAC search from root domains [n]: returns (rac_search_result,
+        the lexicographically smallest solution found as [n] uint64, or None)."""
+        root = np.ascontiguousarray(dom, dtype=np.uint64).reshape(self.n)
+        sol = np.zeros(self.n, dtype=np.uint64)
+        res = rac_search_result()
+        _check(lib.rac_search(self.handle, _ptr(root), max_solutions, max_nodes, batch, _ptr(sol),
+                              ctypes.byref(res)), "rac_search")
+        return res, (sol if res.solutions > 0 else None)
 
     def sync(self):
         _check(lib.rac_sync_status(self.handle), "rac_sync_status")

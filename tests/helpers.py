@@ -94,3 +94,15 @@ def oracle_expect(n, d, edges, rel_u8, dom_masks, mode=0, changed=None, max_step
         assert np.array_equal(dac, r["dom"]), "oracle disagrees with itself"
         assert status == r["status"]
     return u8_to_masks(r["dom"]), r["iters"], r["status"], r["checks"], r["converged"]
+
+
+def queens(n):
+    """The n-queens problem (the generator's builder): (edges, relations)."""
+    from paper_2407_11388_amd import gen
+    return gen.queens(n)
+
+
+def cycle_colouring(n, k):
+    """Proper k-colourings of the cycle on n >= 3 vertices."""
+    neq = [(a, b) for a in range(k) for b in range(k) if a != b]
+    return instance_from_pairs(n, k, [(i, (i + 1) % n, neq) for i in range(n)])

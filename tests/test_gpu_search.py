@@ -1,0 +1,108 @@
+"""GPU batched MAC search vs the oracle's MAC search: solution count, node
+and failure counts, and the lexicographically smallest solution, on the
+closed-form families and random instances, for several batch sizes (the
+explored tree of a complete search does not depend on the batch)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.search import mac_search
+from paper_2407_11388_amd import gen
+
+from helpers import cycle_colouring, instance_from_pairs, masks_to_u8, queens
+
+pytestmark = pytest.mark.gpu
+
+rac = pytest.importorskip("paper_2407_11388_amd.rac")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def full_masks(n, d):
+    return np.full(n, (1 << d) - 1 if d < 64 else 0xFFFFFFFFFFFFFFFF, dtype=np.uint64)
+
+
+def check(name, n, d, edges, rel, dom_masks, batches=(1, 5, 256), path=None):
+    exp = mac_search(n, d, edges, rel, masks_to_u8(dom_masks, d))
+    kw = {} if path is None else dict(path=path)
+    net = rac.Net.from_u8(n, d, edges, rel, **kw)
+    for b in batches:
+        say(f"[gpu] search {name} n={n} d={d} batch={b}")
+        res, sol = net.search(dom_masks, batch=b)
+        assert res.complete == 1
+        assert res.solutions == exp["solutions"], f"{name} batch {b}"
+        assert res.nodes == exp["nodes"], f"{name} batch {b}: nodes {res.nodes} != {exp['nodes']}"
+        assert res.failures == exp["failures"]
+        if exp["best"] is None:
+            assert sol is None
+        else:
+            assert [int(v).bit_length() - 1 for v in sol] == exp["best"].tolist()
+    net.close()
+
+
+@pytest.mark.parametrize("n", [4, 5, 6, 7, 8])
+def test_queens(n):
+    edges, rel = queens(n)
+    check(f"queens{n}", n, n, edges, rel, full_masks(n, n))
+
+
+def test_queens10_large_batches():
+    # 5889 nodes: rounds of up to 1024 open nodes, and the stack growing past
+    # its first allocation with batch 1
+    edges, rel = queens(10)
+    check("queens10", 10, 10, edges, rel, full_masks(10, 10), batches=(1, 1024))
+
+
+@pytest.mark.parametrize("n,k", [(3, 3), (5, 3), (6, 2), (7, 2), (6, 3)])
+def test_cycle_colourings(n, k):
+    edges, rel = cycle_colouring(n, k)
+    check(f"cycle{n}-{k}", n, k, edges, rel, full_masks(n, k))
+
+
+# model-B instances with small trees: many solutions, none, long failures
+RANDOM = [(12, 4, 0.5, 0.3, 0), (12, 4, 0.5, 0.3, 1), (12, 4, 0.5, 0.3, 2),
+          (30, 5, 0.2, 0.35, 2), (20, 6, 0.4, 0.4, 2), (25, 8, 0.3, 0.45, 1),
+          (16, 33, 0.6, 0.6, 0), (16, 33, 0.6, 0.6, 2), (20, 40, 0.5, 0.7, 1)]
+
+
+@pytest.mark.parametrize("n,d,p1,p2,seed", RANDOM)
+def test_random(n, d, p1, p2, seed):
+    inst = gen.model_b(800 + seed + 10 * n, n, d, p1, p2)
+    check(f"random-n{n}-d{d}-s{seed}", n, d, inst.edges, inst.rel_u8(), full_masks(n, d),
+          batches=(3, 64))
+
+
+def test_int8_path():
+    edges, rel = queens(6)
+    check("queens6-int8", 6, 6, edges, rel, full_masks(6, 6), batches=(4,), path=rac.PATH_INT8)
+
+
+def test_root_cases():
+    # root wiped out
+    edges, rel = instance_from_pairs(2, 2, [(0, 1, [(0, 1)])])
+    net = rac.Net.from_u8(2, 2, edges, rel)
+    res, sol = net.search(np.array([1, 1], np.uint64))   # x0 = 0 needs x1 = 1
+    assert (res.solutions, res.nodes, res.failures, res.complete) == (0, 1, 1, 1) and sol is None
+    # root already a solution
+    res, sol = net.search(np.array([1, 2], np.uint64))
+    assert (res.solutions, res.nodes, res.failures, res.complete) == (1, 1, 0, 1)
+    assert sol.tolist() == [1, 2]
+    net.close()
+
+
+def test_limits():
+    edges, rel = queens(8)
+    net = rac.Net.from_u8(8, 8, edges, rel)
+    res, sol = net.search(full_masks(8, 8), max_solutions=1, batch=1)
+    assert res.solutions >= 1 and res.complete == 0
+    s = [int(v).bit_length() - 1 for v in sol]
+    for i in range(8):
+        for j in range(i + 1, 8):
+            assert s[i] != s[j] and abs(s[i] - s[j]) != j - i
+    res, _ = net.search(full_masks(8, 8), max_nodes=50, batch=4)
+    assert res.nodes >= 50 and res.complete == 0
+    net.close()
