@@ -17,7 +17,9 @@ What it computes (all in plain C on 0/1 bytes, ``rac_oracle.c``):
 
 ``brute.py`` holds the definitions themselves (union of all arc-consistent
 subsets; enumeration of all solutions) for tiny instances; they pin the two
-algorithms above.
+algorithms above. ``search.py`` holds the MAC search of Algorithm 2 (every
+node's closure by ``ac3``), pinned by ``brute.solutions`` and closed-form
+solution counts.
 
 Pins (see ``tests/test_oracle.py``): brute force on tiny instances, the closed
 forms of chains / cliques / empty and universal relations, hand-worked golden
