@@ -80,6 +80,8 @@ struct MArgs {
                                       // of (x, state slot); [0]: the current step's input,
                                       // [1]: its output (same slot order)
     uint32_t *chg, *wipe;             // [n][words]
+    uint32_t *kill;                   // [n][capB] values of (x, slot) left without support by
+                                      // a split step (bit a), zero between steps
     int32_t words;                    // capB / 32
     int32_t *act[2];                  // active state lists (by step parity)
     int32_t *prev_slot[2];            // slot each listed state had in the previous step
@@ -192,7 +194,11 @@ constexpr int kBias = -2016;
 constexpr int kFlag0 = 1 << 5, kFlag1 = 1 << 11;
 static_assert(kXW == 2, "the zero-count flags pack exactly two variables per word");
 
-__global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
+// nseg > 1 splits the neighbour blocks of every (x-tile, state tile) over
+// nseg workgroups (for steps with few active states, so that the grid still
+// fills the chip); each ORs its flags into A.kill and mfma_split_finish_kernel
+// applies them.
+__global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, int nseg) {
     extern __shared__ v4i s_lds[];   // kStages x {domain tile [kMY][2][kMS], relation tile
                                      // [kMX variables][kMY arcs][32 rows] uint32}, then the
                                      // all-present tile [2][kMS]
@@ -200,21 +206,26 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
     // workgroup -> (x-tile, state tile); the state tiles of one x-tile share
     // blockIdx % 8 and so an XCD
     const int ntiles_s = (A.words * 32 + kMS - 1) / kMS;
-    int xt, stile;
+    int xt, stile, seg;
     if (A.xcd_map) {
         const int b = blockIdx.x;
-        const int xcd = b & 7, r = b >> 3;
+        const int xcd = b & 7, r = (b >> 3) / nseg;
+        seg = (b >> 3) % nseg;
         stile = r % ntiles_s;
         xt = (r / ntiles_s) * 8 + xcd;
     } else {
-        stile = blockIdx.x % ntiles_s;
-        xt = blockIdx.x / ntiles_s;
+        seg = blockIdx.x % nseg;
+        const int r = blockIdx.x / nseg;
+        stile = r % ntiles_s;
+        xt = r / ntiles_s;
     }
     const int st0 = stile * kMS;
     if (st0 >= nact || xt * kMX >= A.n) return;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int nblk = A.nblk, nw4 = A.nw4;
+    const int nw4 = A.nw4;
+    // this workgroup's neighbour blocks [blo, bhi) (all of them unless split)
+    const int blo = (int)((int64_t)seg * A.nblk / nseg), bhi = (int)((int64_t)(seg + 1) * A.nblk / nseg);
     // this wave's variables x = xt*kMX + kXW*wave + i (i < kXW)
     int xs[kXW];
     bool xvs[kXW];
@@ -316,19 +327,19 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
     const uint32_t lane_off = (uint32_t)(half * kMS + col) * 16u;
     const uint32_t ones_off = (uint32_t)(kStages * (kBTile + kATile)) * 16u;
 
-    issue(0, 0);
-    issue(1, nblk > 1 ? 1 : 0);
+    issue(0, blo);
+    issue(1, blo + 1 < bhi ? blo + 1 : bhi - 1);
     ring_sync();
-    for (int blk = 0; blk < nblk; ++blk) {
+    for (int blk = blo; blk < bhi; ++blk) {
         // the block two ahead (past the end: a repeat of the last block into
         // the stage no one reads any more)
-        issue((blk + 2) % kStages, blk + 2 < nblk ? blk + 2 : nblk - 1);
-        if ((blk & ((1 << kChunkShift) - 1)) == 0) {
+        issue((blk - blo + 2) % kStages, blk + 2 < bhi ? blk + 2 : bhi - 1);
+        if (blk == blo || (blk & ((1 << kChunkShift) - 1)) == 0) {
             // the copy pointer (two blocks ahead, in the same chunk) loaded it
 #pragma unroll
             for (int i = 0; i < kXW; ++i) tmC[i] = tmI[i];
         }
-        const int stg = blk % kStages;
+        const int stg = (blk - blo) % kStages;
         const uint32_t stage_off = (uint32_t)(stg * (kBTile + kATile)) * 16u;
         const uint32_t *at0 = reinterpret_cast<const uint32_t *>(s_lds + stg * (kBTile + kATile) + kBTile) +
                               (kXW * wave) * (kMY * 32);
@@ -406,6 +417,29 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // no copy may outlive the workgroup
 
+    if (nseg > 1) {
+        // split step: OR this workgroup's unsupported values into A.kill
+#pragma unroll
+        for (int xi = 0; xi < kXW; ++xi) {
+            if (!xvs[xi]) continue;
+            const int flag = xi == 0 ? kFlag0 : kFlag1;
+#pragma unroll
+            for (int t = 0; t < kMSub; ++t) {
+                const int slot = st0 + t * 32 + col;
+                uint32_t m = 0;
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (rf[t][4 * g + r] & flag) m |= 1u << (8 * g + 4 * half + r);
+                m |= (uint32_t)__shfl_xor((int)m, 32, 64);   // every lane executes it
+                if (half == 0 && slot < nact && m)
+                    atomicOr(A.kill + (int64_t)xs[xi] * A.capB + slot, m);
+            }
+        }
+        return;
+    }
+
     // epilogue: new domain bytes and per-state change / wipe-out masks
     int8_t *dnext = A.dom8[1];
 #pragma unroll
@@ -449,6 +483,50 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k) {
                 A.chg[(int64_t)x * A.words + w] = (uint32_t)mc;
                 A.wipe[(int64_t)x * A.words + w] = (uint32_t)mw;
             }
+        }
+    }
+}
+
+// After a split step: new domain bytes of every (x, active slot) from
+// A.kill (which it clears), and the per-word change and wipe-out masks, as
+// the unsplit kernel's epilogue writes them. Threads cover 64 slots of one
+// variable per wave.
+__global__ void mfma_split_finish_kernel(MArgs A, int k) {
+    const int nact = A.cnt[(k - 1) & 1];
+    const int64_t s64 = ((int64_t)nact + 63) / 64 * 64;
+    const int64_t total = s64 * A.n;
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const bool in = i < total;
+        const int32_t x = in ? (int32_t)(i / s64) : 0;
+        const int32_t slot = in ? (int32_t)(i - (int64_t)x * s64) : 0;
+        const bool live = in && slot < nact;
+        bool changed = false, nonempty = false;
+        if (live) {
+            uint32_t *kp = A.kill + (int64_t)x * A.capB + slot;
+            const uint32_t m = *kp;
+            if (m) *kp = 0;
+            uint4 klo, khi;
+            mask_to_bytes(~(uint64_t)m & 0xFFFFFFFFull, klo, khi);
+            const uint4 lo = *reinterpret_cast<const uint4 *>(A.dom8[0] + dom_off(A, x, 0, slot));
+            const uint4 hi = *reinterpret_cast<const uint4 *>(A.dom8[0] + dom_off(A, x, 1, slot));
+            const uint4 nlo = make_uint4(lo.x & klo.x, lo.y & klo.y, lo.z & klo.z, lo.w & klo.w);
+            const uint4 nhi = make_uint4(hi.x & khi.x, hi.y & khi.y, hi.z & khi.z, hi.w & khi.w);
+            *reinterpret_cast<uint4 *>(A.dom8[1] + dom_off(A, x, 0, slot)) = nlo;
+            *reinterpret_cast<uint4 *>(A.dom8[1] + dom_off(A, x, 1, slot)) = nhi;
+            changed = m != 0 && ((nlo.x ^ lo.x) | (nlo.y ^ lo.y) | (nlo.z ^ lo.z) | (nlo.w ^ lo.w) |
+                                 (nhi.x ^ hi.x) | (nhi.y ^ hi.y) | (nhi.z ^ hi.z) | (nhi.w ^ hi.w)) != 0;
+            nonempty = (nlo.x | nlo.y | nlo.z | nlo.w | nhi.x | nhi.y | nhi.z | nhi.w) != 0;
+        }
+        const uint64_t mc = __ballot(changed);
+        const uint64_t mw = __ballot(live && !nonempty);
+        // a wave holds slots 64j .. 64j+63 of one variable: two mask words
+        if (in && (lane & 31) == 0 && slot < nact) {
+            const int w = slot >> 5;
+            A.chg[(int64_t)x * A.words + w] = (uint32_t)(lane ? mc >> 32 : mc);
+            A.wipe[(int64_t)x * A.words + w] = (uint32_t)(lane ? mw >> 32 : mw);
         }
     }
 }
@@ -673,7 +751,7 @@ struct MfmaImpl {
     int32_t nblk = 0, nw4 = 0;
     int32_t capB = 0, words = 0;
     int8_t *dom8[2] = {nullptr, nullptr};
-    uint32_t *chg = nullptr, *wipe = nullptr;
+    uint32_t *chg = nullptr, *wipe = nullptr, *kill = nullptr;
     int32_t *act[2] = {nullptr, nullptr};
     int32_t *prev_slot[2] = {nullptr, nullptr};
     int32_t *slot_map = nullptr;
@@ -711,6 +789,7 @@ void mfma_release(MfmaData &md) {
     mfree(m->dom8[0]);
     mfree(m->dom8[1]);
     mfree(m->chg);
+    mfree(m->kill);
     mfree(m->wipe);
     mfree(m->act[0]);
     mfree(m->act[1]);
@@ -836,6 +915,7 @@ static int ensure_capacity(MfmaData &md, int32_t B) {
     mfree(m->dom8[0]);
     mfree(m->dom8[1]);
     mfree(m->chg);
+    mfree(m->kill);
     mfree(m->wipe);
     mfree(m->act[0]);
     mfree(m->act[1]);
@@ -856,6 +936,8 @@ static int ensure_capacity(MfmaData &md, int32_t B) {
     HIP_OK(hipMalloc(&m->dom8[0], (size_t)capB * N32));
     HIP_OK(hipMalloc(&m->dom8[1], (size_t)capB * N32));
     HIP_OK(hipMalloc(&m->chg, (size_t)md.n * words * 4));
+    HIP_OK(hipMalloc(&m->kill, (size_t)md.n * capB * 4));
+    HIP_OK(hipMemset(m->kill, 0, (size_t)md.n * capB * 4));
     HIP_OK(hipMalloc(&m->wipe, (size_t)md.n * words * 4));
     HIP_OK(hipMalloc(&m->act[0], (size_t)capB * 4));
     HIP_OK(hipMalloc(&m->act[1], (size_t)capB * 4));
@@ -896,6 +978,7 @@ static MArgs make_args(MfmaData &md, int32_t B, const uint64_t *din, uint64_t *d
     A.dom8[0] = m->dom8[0];
     A.dom8[1] = m->dom8[1];
     A.chg = m->chg;
+    A.kill = m->kill;
     A.wipe = m->wipe;
     A.words = m->words;   // row stride of the mask matrices (capacity / 32)
     A.act[0] = m->act[0];
@@ -933,6 +1016,18 @@ static int run_steps(MfmaData &md, const MArgs &A, bool profile, int32_t handoff
     const int sweep_blocks = ((ntiles_x + 7) / 8) * 8 * ntiles_s;
     const int init_blocks = (int)std::min<int64_t>(4096, ((int64_t)A.B * A.n + 255) / 256);
     const int32_t maxs = A.max_sweeps > 0 ? A.max_sweeps : A.n * A.d + 1;
+    int dev = 0, cus = 0;
+    HIP_OK(hipGetDevice(&dev));
+    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    // one workgroup per CU (the LDS ring): a step whose active states fill
+    // fewer tiles than CUs splits its neighbour blocks over up to 4
+    // workgroups per tile
+    auto segments = [&](int64_t active) {
+        const int64_t tiles = (int64_t)ntiles_x * ((active + kMS - 1) / kMS);
+        int64_t sg = tiles > 0 ? cus / tiles : 1;
+        sg = std::max<int64_t>(1, std::min<int64_t>({sg, 4, (int64_t)A.nblk}));
+        return (int)sg;
+    };
     HIP_OK(hipEventRecord(m->ev0, stream));
     hipLaunchKernelGGL(mfma_init_kernel, dim3(init_blocks), dim3(256), 0, stream, A);
     int k = 0;
@@ -942,9 +1037,17 @@ static int run_steps(MfmaData &md, const MArgs &A, bool profile, int32_t handoff
         for (int i = 0; i < steps && k < maxs; ++i) {
             ++k;
             const bool timed = profile && k <= 64;
+            // step 2 runs before its active count is read: no split
+            const int nseg = k == 2 ? 1 : segments(left);
             if (timed) HIP_OK(hipEventRecord(m->kev[2 * (k - 1)], stream));
-            hipLaunchKernelGGL(mfma_sweep_kernel, dim3(sweep_blocks), dim3(kMThreads), kMSmem, stream,
-                               A, k);
+            hipLaunchKernelGGL(mfma_sweep_kernel, dim3(sweep_blocks * nseg), dim3(kMThreads), kMSmem,
+                               stream, A, k, nseg);
+            if (nseg > 1) {
+                const int64_t thr = ((int64_t)left + 63) / 64 * 64 * A.n;
+                hipLaunchKernelGGL(mfma_split_finish_kernel,
+                                   dim3((unsigned)std::min<int64_t>(4096, (thr + 255) / 256)), dim3(256),
+                                   0, stream, A, k);
+            }
             if (timed) HIP_OK(hipEventRecord(m->kev[2 * (k - 1) + 1], stream));
             hipLaunchKernelGGL(mfma_reduce_kernel, dim3((A.B + 31) / 32), dim3(256), 0, stream, A, k);
             hipLaunchKernelGGL(mfma_finalize_kernel, dim3(1), dim3(1024), 0, stream, A, k);
