@@ -189,6 +189,9 @@ def parse():
                     help="approximate budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--table1", action="store_true",
+                    help="only run the Table 1-style MAC-search grid (steps and AC-3 revisions "
+                         "per assignment, time per node) and print it as one JSON line")
     ap.add_argument("--no-search", action="store_true",
                     help="skip the MAC-search lines in the secondary results")
     ap.add_argument("--no-uneven", action="store_true",
@@ -289,6 +292,46 @@ def search_lines():
     return out
 
 
+def table1_grid(oracle_nodes: int = 100, gpu_nodes: int = 20000):
+    """Table 1 analogue: MAC search on model-B instances over n x density
+    (d = 10, p2 = 0.3; the paper's own instances and heuristic are not
+    published). Per grid point: the GPU search (batch 1024, up to `gpu_nodes`
+    nodes): recurrence steps per enforcement and time per node; the oracle's
+    search on its first `oracle_nodes` nodes (depth-first): recurrence steps
+    and AC-3 revisions per enforcement."""
+    import numpy as np
+
+    import oracle.search as osearch
+    from paper_2407_11388_amd import gen, rac
+    rows = []
+    for n in (100, 200, 400):
+        for p1 in (0.1, 0.3, 0.5, 1.0):
+            d, p2 = 10, 0.3
+            inst = gen.model_b(1000 + n + int(100 * p1), n, d, p1, p2)
+            rel = inst.rel_u8()
+            net = rac.Net.from_u8(n, d, inst.edges, rel)
+            root = np.full(n, (1 << d) - 1, dtype=np.uint64)
+            net.search(root, batch=1024, max_nodes=2000)   # warm-up
+            res, _ = net.search(root, batch=1024, max_nodes=gpu_nodes)
+            net.close()
+            t0 = time.perf_counter()
+            o = osearch.mac_search(n, d, inst.edges, rel, np.ones((n, d), np.uint8),
+                                   stop_after=oracle_nodes)
+            o_s = time.perf_counter() - t0
+            rows.append(dict(
+                n=n, p1=p1, d=d, p2=p2, edges=int(inst.edges.shape[0]),
+                gpu=dict(nodes=int(res.nodes), complete=int(res.complete),
+                         solutions=int(res.solutions),
+                         steps_per_node=res.sweeps / res.nodes,
+                         us_per_node=res.search_ms * 1e3 / res.nodes),
+                cpu_baseline=dict(kind="oracle", nodes=o["nodes"],
+                                  steps_per_node=o["steps"] / o["nodes"],
+                                  ac3_revisions_per_node=o["revisions"] / o["nodes"],
+                                  us_per_node=o_s * 1e6 / o["nodes"])))
+            print(f"[table1] n={n} p1={p1}: {rows[-1]}", file=sys.stderr, flush=True)
+    return rows
+
+
 def main():
     args = parse()
     if args.profile_report:
@@ -308,6 +351,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.table1:
+        print(json.dumps(dict(table1=table1_grid())), flush=True)
+        return
     if args.copy_calibration > 0:
         src = torch.ones(args.copy_calibration, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

@@ -222,6 +222,8 @@ typedef struct rac_search_result {
     int64_t nodes;       /* nodes enforced: the root and every child */
     int64_t failures;    /* enforced nodes that wiped out */
     int64_t rounds;      /* batched rounds (device enforcement calls after the root) */
+    int64_t sweeps;      /* recurrence steps of all enforced nodes (Table 1's #Recurrence
+                            summed; each child stops at its first wipe-out) */
     int32_t complete;    /* 1: the whole tree was explored */
     int32_t reserved;
     double search_ms;    /* wall-clock time of the call */

@@ -1099,6 +1099,7 @@ namespace {
 struct SearchBufs {
     uint64_t *stack = nullptr, *best = nullptr;
     int32_t *bvar = nullptr, *nchild = nullptr, *coff = nullptr, *has_best = nullptr;
+    long long *steps = nullptr;
     int32_t *is_sol = nullptr, *is_open = nullptr, *sol_off = nullptr, *open_off = nullptr,
             *sol_list = nullptr;
     int64_t cap = 0;   // stack capacity in nodes
@@ -1114,6 +1115,7 @@ struct SearchBufs {
         dfree(sol_off);
         dfree(open_off);
         dfree(sol_list);
+        dfree(steps);
     }
 };
 
@@ -1157,13 +1159,15 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
     HIP_TRY(hipMemcpyAsync(r.din, dom, (size_t)n * 8, hipMemcpyHostToDevice, s));
     RAC_TRY(run_states(net, 1, path, nullptr, 0, false));
     std::vector<uint64_t> root((size_t)n);
-    int32_t root_status = 0, hrc = 0;
+    int32_t root_status = 0, hrc = 0, root_iters = 0;
     HIP_TRY(hipMemcpyAsync(root.data(), r.dout, (size_t)n * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&root_status, r.status, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&root_iters, r.iters, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&hrc, r.rc, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     RAC_TRY(rc_from_device(hrc));
     out->nodes = 1;
+    out->sweeps = root_iters;
     auto finish = [&]() {
         out->search_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         return RAC_OK;
@@ -1195,6 +1199,7 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
     RAC_TRY(dalloc(&b.sol_off, (size_t)cmax + 1));
     RAC_TRY(dalloc(&b.open_off, (size_t)cmax + 1));
     RAC_TRY(dalloc(&b.sol_list, (size_t)cmax));
+    RAC_TRY(dalloc(&b.steps, 1));
     HIP_TRY(hipMemsetAsync(b.has_best, 0, 4, s));
     HIP_TRY(hipMemcpyAsync(b.stack, root.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
     RAC_TRY(ensure_path(net, path, call_target(net, cmax)));
@@ -1224,9 +1229,11 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
         RAC_TRY(run_states(net, C, path, r.changed, -1, false));
         hipLaunchKernelGGL(search_classify_kernel, dim3((unsigned)C), dim3(64), 0, s, r.dout,
                            r.status, n, b.is_sol, b.is_open);
-        hipLaunchKernelGGL(search_lists_kernel, dim3(1), dim3(1024), 0, s, b.is_sol, b.is_open, C,
-                           b.sol_off, b.open_off);
+        hipLaunchKernelGGL(search_lists_kernel, dim3(1), dim3(1024), 0, s, b.is_sol, b.is_open,
+                           r.iters, C, b.sol_off, b.open_off, b.steps);
         int32_t cnt[2] = {0, 0};
+        long long steps = 0;
+        HIP_TRY(hipMemcpyAsync(&steps, b.steps, 8, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(&cnt[0], b.sol_off + C, 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(&cnt[1], b.open_off + C, 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(&hrc, r.rc, 4, hipMemcpyDeviceToHost, s));
@@ -1250,6 +1257,7 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
                                b.sol_off, C, b.best, b.has_best);
         HIP_TRY(hipGetLastError());
         out->nodes += C;
+        out->sweeps += steps;
         out->solutions += nsol;
         out->failures += C - nsol - nopen;
         ssize += nopen;

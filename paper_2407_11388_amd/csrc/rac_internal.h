@@ -139,8 +139,9 @@ __global__ void search_expand_kernel(const uint64_t *nodes, int32_t n, const int
                                      const int32_t *coff, uint64_t *cdom, uint8_t *cchg);
 __global__ void search_classify_kernel(const uint64_t *cres, const int32_t *status, int32_t n,
                                        int32_t *is_sol, int32_t *is_open);
-__global__ void search_lists_kernel(const int32_t *is_sol, const int32_t *is_open, int32_t C,
-                                    int32_t *sol_off, int32_t *open_off);
+__global__ void search_lists_kernel(const int32_t *is_sol, const int32_t *is_open,
+                                    const int32_t *iters, int32_t C, int32_t *sol_off,
+                                    int32_t *open_off, long long *steps);
 __global__ void search_push_kernel(const uint64_t *cres, int32_t n, int32_t C, const int32_t *is_sol,
                                    const int32_t *is_open, const int32_t *sol_off,
                                    const int32_t *open_off, uint64_t *stack, int64_t base,

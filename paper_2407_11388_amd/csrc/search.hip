@@ -118,13 +118,25 @@ __global__ __launch_bounds__(64) void search_classify_kernel(const uint64_t *cre
     }
 }
 
-// Offsets of the solution and open lists (two scans in one workgroup).
+// Offsets of the solution and open lists (two scans in one workgroup), and
+// the recurrence steps of all C children.
 __global__ __launch_bounds__(1024) void search_lists_kernel(const int32_t *is_sol,
-                                                            const int32_t *is_open, int32_t C,
-                                                            int32_t *sol_off, int32_t *open_off) {
+                                                            const int32_t *is_open,
+                                                            const int32_t *iters, int32_t C,
+                                                            int32_t *sol_off, int32_t *open_off,
+                                                            long long *steps) {
+    __shared__ long long s_steps;
     block_scan(is_sol, C, sol_off);
     __syncthreads();
     block_scan(is_open, C, open_off);
+    if (threadIdx.x == 0) s_steps = 0;
+    __syncthreads();
+    long long t = 0;
+    for (int32_t c = threadIdx.x; c < C; c += blockDim.x) t += iters[c];
+    for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd((unsigned long long *)&s_steps, (unsigned long long)t);
+    __syncthreads();
+    if (threadIdx.x == 0) *steps = s_steps;
 }
 
 // Open children go onto the stack above `base`, the last child lowest, so

@@ -68,6 +68,7 @@ class rac_stats(ctypes.Structure):
 class rac_search_result(ctypes.Structure):
     _fields_ = [("solutions", ctypes.c_int64), ("nodes", ctypes.c_int64),
                 ("failures", ctypes.c_int64), ("rounds", ctypes.c_int64),
+                ("sweeps", ctypes.c_int64),
                 ("complete", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("search_ms", ctypes.c_double)]
 

@@ -37,6 +37,7 @@ def check(name, n, d, edges, rel, dom_masks, batches=(1, 5, 256), path=None):
         assert res.solutions == exp["solutions"], f"{name} batch {b}"
         assert res.nodes == exp["nodes"], f"{name} batch {b}: nodes {res.nodes} != {exp['nodes']}"
         assert res.failures == exp["failures"]
+        assert res.sweeps == exp["steps"], f"{name} batch {b}: steps {res.sweeps} != {exp['steps']}"
         if exp["best"] is None:
             assert sol is None
         else:

@@ -37,6 +37,8 @@ def test_unconstrained_tree(n, d):
     assert r["solutions"] == d ** n
     assert r["failures"] == 0
     assert r["nodes"] == sum(d ** i for i in range(n + 1))
+    # nothing to propagate: every enforcement takes exactly one step
+    assert r["steps"] == r["nodes"]
     assert r["best"].tolist() == [0] * n
 
 
