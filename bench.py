@@ -285,6 +285,7 @@ def search_lines():
             line[f"batch{b}"] = dict(nodes=int(res.nodes), solutions=int(res.solutions),
                                      failures=int(res.failures), complete=int(res.complete),
                                      rounds=int(res.rounds), ms=res.search_ms,
+                                     steps_per_node=res.sweeps / res.nodes,
                                      nodes_per_s=res.nodes / (res.search_ms * 1e-3))
         line["batched_vs_one_node"] = line["batch1024"]["nodes_per_s"] / line["batch1"]["nodes_per_s"]
         out[name] = line
