@@ -31,6 +31,7 @@
 // states that go on into the next step's active list.
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -1022,9 +1023,12 @@ static int run_steps(MfmaData &md, const MArgs &A, bool profile, int32_t handoff
     // one workgroup per CU (the LDS ring): a step whose active states fill
     // fewer tiles than CUs splits its neighbour blocks over up to 4
     // workgroups per tile
+    // RAC_MFMA_SEGMENTS forces the split of every step (tests)
+    const char *env_seg = getenv("RAC_MFMA_SEGMENTS");
+    const int force_seg = env_seg && *env_seg ? atoi(env_seg) : 0;
     auto segments = [&](int64_t active) {
         const int64_t tiles = (int64_t)ntiles_x * ((active + kMS - 1) / kMS);
-        int64_t sg = tiles > 0 ? cus / tiles : 1;
+        int64_t sg = force_seg > 0 ? force_seg : (tiles > 0 ? cus / tiles : 1);
         sg = std::max<int64_t>(1, std::min<int64_t>({sg, 4, (int64_t)A.nblk}));
         return (int)sg;
     };
@@ -1038,7 +1042,7 @@ static int run_steps(MfmaData &md, const MArgs &A, bool profile, int32_t handoff
             ++k;
             const bool timed = profile && k <= 64;
             // step 2 runs before its active count is read: no split
-            const int nseg = k == 2 ? 1 : segments(left);
+            const int nseg = k == 2 && force_seg <= 0 ? 1 : segments(left);
             if (timed) HIP_OK(hipEventRecord(m->kev[2 * (k - 1)], stream));
             hipLaunchKernelGGL(mfma_sweep_kernel, dim3(sweep_blocks * nseg), dim3(kMThreads), kMSmem,
                                stream, A, k, nseg);

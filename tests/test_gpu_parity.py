@@ -263,6 +263,27 @@ def test_batch_states_mfma(n, d, B, p1, p2, handoff, monkeypatch):
         net.close()
 
 
+@pytest.mark.parametrize("segments", ["2", "3", "4"])
+@pytest.mark.parametrize("n,d,B,p1,p2", [(45, 10, 130, 0.8, 0.5), (2200, 6, 33, 0.006, 0.35),
+                                         (100, 32, 257, 0.8, 0.25)])
+def test_batch_states_mfma_split_steps(n, d, B, p1, p2, segments, monkeypatch):
+    # every step's neighbour blocks split over 2-4 workgroups per tile (the
+    # segments cross the 256-block chunks of the neighbour tables for n = 2200)
+    monkeypatch.setenv("RAC_MFMA_SEGMENTS", segments)
+    monkeypatch.setenv("RAC_MFMA_HANDOFF", "0")
+    inst = gen.model_b(40 + n + d, n, d, p1, p2)
+    doms, _ = gen.partial_assign_states(41 + B, n, d, B, min(n, 12))
+    rel = inst.rel_u8()
+    say(f"[gpu] batch mfma split={segments} n={n} d={d} B={B}")
+    net = rac.Net.from_u8(n, d, inst.edges, rel, path=rac.PATH_MFMA)
+    got, iters, status = net.enforce_batch(doms)
+    for s in range(B):
+        exp, e_it, e_st, _, _ = oracle_expect(n, d, inst.edges, rel, doms[s])
+        assert np.array_equal(got[s], exp), f"state {s}"
+        assert iters[s] == e_it and status[s] == e_st, f"state {s}"
+    net.close()
+
+
 def test_mfma_rejects_wide_domains():
     inst = gen.model_b(3, 10, 40, 0.5, 0.3)
     net = rac.Net.from_instance(inst, path=rac.PATH_MFMA)
