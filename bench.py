@@ -441,6 +441,15 @@ def main():
         tp = (time.perf_counter() - tp0) / P
         net_plain.close()
 
+        # end to end: the host-pointer call, PCIe copies of the domains included
+        for _ in range(2):
+            net.enforce_batch(doms)
+        te0 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            net.enforce_batch(doms)
+        te = (time.perf_counter() - te0) / reps
+
         fix_s = B / t
         plain_fix_s = 1.0 / tp
         achieved = ops / (kms * 1e-3) / 1e12 if kms > 0 else None
@@ -454,6 +463,9 @@ def main():
             plain_loop=dict(fixpoints_per_s=plain_fix_s, states=P, path="bits",
                             note="sequential rac_enforce calls, host round trip each"),
             batched_vs_plain=fix_s / plain_fix_s,
+            end_to_end=dict(ms_per_batch=te * 1e3, fixpoints_per_s=B / te,
+                            note="rac_enforce_batch on host buffers: the "
+                                 f"{B * n * 8 / 1e6:.0f} MB of domains copied in and out"),
             steps_hist=np.bincount(iters).tolist(), wiped_states=int(status.sum()),
             roofline=dict(kernel="mfma_sweep_kernel", bound="mfma", achieved=achieved,
                           peak=INT8_PEAK_TOPS, unit="TOP/s",
@@ -495,6 +507,38 @@ def main():
 
     if not args.no_secondary and args.workload == "batch-states":
         sec = {}
+        # small and mid single instances: time per fixpoint through the host
+        # call, and (mid) the sweep's bandwidth with warm and flushed caches
+        flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        for wname in ("single_small", "single_mid"):
+            ws = getattr(workloads, wname)()
+            inst, dom = ws.instances[0], ws.domains[0]
+            net = rac.Net.from_instance(inst, path=rac.PATH_BITS, profile=True)
+            for _ in range(5):
+                net.enforce(dom)
+            t_host, best, reps = 0.0, 1e9, 20
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                net.enforce(dom)
+                t_host += time.perf_counter() - t0
+                best = min(best, net.stats().kernel_ms)
+            stt = net.stats()
+            line = dict(us_per_fixpoint_host_call=t_host / reps * 1e6,
+                        fixpoints_per_s=reps / t_host, kernel_ms=best,
+                        warm_relation_GBs=stt.relation_bytes / (best * 1e-3) / 1e9,
+                        steps=int(stt.sweeps))
+            if wname == "single_mid":
+                cold = 0.0
+                for _ in range(5):
+                    flush.fill_(1)      # 1 GiB through L2 and the Infinity Cache
+                    torch.cuda.synchronize()
+                    net.enforce(dom)
+                    cold += net.stats().kernel_ms
+                line["cold_relation_GBs"] = stt.relation_bytes / (cold / 5 * 1e-3) / 1e9
+            sec[ws.name] = line
+            net.close()
+        del flush
+
         wl = workloads.single_large()
         inst, dom = wl.instances[0], wl.domains[0]
         for pname, p in (("bits", rac.PATH_BITS), ("int8", rac.PATH_INT8)):
