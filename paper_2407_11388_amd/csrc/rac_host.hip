@@ -192,8 +192,13 @@ struct Runner {
     int64_t *prob_off = nullptr;
     int64_t tables_key = -1;   // (B, nitems) the problem tables were last written for
     uint64_t *din = nullptr, *dout = nullptr;
+    // per-problem results in one device block, read back with one copy:
+    // checks [cap] | iters [cap] | status [cap] | rc
+    uint8_t *res = nullptr;
     int32_t *iters = nullptr, *status = nullptr, *rc = nullptr;
     long long *checks = nullptr;
+    uint8_t *h_res = nullptr;       // pinned mirror of res
+    uint64_t *h_dom = nullptr;      // pinned staging of host-pointer domains [cap_vars]
     uint8_t *changed = nullptr;
     int32_t *h_nact = nullptr;      // pinned: problems still running after a round
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_round = nullptr;
@@ -276,10 +281,13 @@ static void release_runner(Runner &r) {
     r.tables_key = -1;
     dfree(r.din);
     dfree(r.dout);
-    dfree(r.iters);
-    dfree(r.status);
-    dfree(r.rc);
-    dfree(r.checks);
+    dfree(r.res);
+    r.iters = r.status = r.rc = nullptr;
+    r.checks = nullptr;
+    if (r.h_res) (void)hipHostFree(r.h_res);
+    if (r.h_dom) (void)hipHostFree(r.h_dom);
+    r.h_res = nullptr;
+    r.h_dom = nullptr;
     dfree(r.changed);
     if (r.h_nact) (void)hipHostFree(r.h_nact);
     r.h_nact = nullptr;
@@ -293,6 +301,27 @@ static void release_runner(Runner &r) {
     }
     r.cap_probs = 0;
     r.cap_vars = 0;
+}
+
+static size_t res_bytes(int32_t nprob) { return (size_t)nprob * 16 + 8; }
+
+// Reads back B problems' domains (into dom, if not null) and results with two
+// copies into pinned memory and one wait.
+static int read_results(Runner &r, hipStream_t s, int32_t B, int64_t nvars, uint64_t *dom,
+                        std::vector<long long> &checks, std::vector<int32_t> &iters,
+                        std::vector<int32_t> &status, int32_t *rc) {
+    if (dom) HIP_TRY(hipMemcpyAsync(r.h_dom, r.dout, (size_t)nvars * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(r.h_res, r.res, res_bytes(r.cap_probs), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (dom) memcpy(dom, r.h_dom, (size_t)nvars * 8);
+    const size_t cap = (size_t)r.cap_probs;
+    checks.assign(reinterpret_cast<const long long *>(r.h_res),
+                  reinterpret_cast<const long long *>(r.h_res) + B);
+    const int32_t *hi = reinterpret_cast<const int32_t *>(r.h_res + cap * 8);
+    iters.assign(hi, hi + B);
+    status.assign(hi + cap, hi + cap + B);
+    *rc = hi[2 * cap];
+    return RAC_OK;
 }
 
 static int ensure_runner(Runner &r, int32_t nprob, int64_t nvars) {
@@ -315,10 +344,13 @@ static int ensure_runner(Runner &r, int32_t nprob, int64_t nvars) {
     RAC_TRY(dalloc(&r.prob_off, (size_t)nprob + 1));
     RAC_TRY(dalloc(&r.din, nvars));
     RAC_TRY(dalloc(&r.dout, nvars));
-    RAC_TRY(dalloc(&r.iters, nprob));
-    RAC_TRY(dalloc(&r.status, nprob));
-    RAC_TRY(dalloc(&r.rc, 1));
-    RAC_TRY(dalloc(&r.checks, nprob));
+    RAC_TRY(dalloc(&r.res, res_bytes(nprob)));
+    r.checks = reinterpret_cast<long long *>(r.res);
+    r.iters = reinterpret_cast<int32_t *>(r.res + (size_t)nprob * 8);
+    r.status = r.iters + nprob;
+    r.rc = r.status + nprob;
+    HIP_TRY(hipHostMalloc((void **)&r.h_res, res_bytes(nprob), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&r.h_dom, (size_t)nvars * 8, hipHostMallocDefault));
     RAC_TRY(dalloc(&r.changed, nvars));
     HIP_TRY(hipHostMalloc((void **)&r.h_nact, 4, hipHostMallocDefault));
     HIP_TRY(hipEventCreate(&r.ev0));
@@ -995,15 +1027,10 @@ static int collect_bits(rac_net *net, int32_t B, int32_t path, uint64_t *dom, in
                         int32_t *status) {
     Runner &r = net->run;
     PathData &pd = path == RAC_PATH_INT8 ? net->i8 : net->bits;
-    std::vector<int32_t> hi((size_t)B), hs((size_t)B);
-    std::vector<long long> hc((size_t)B);
+    std::vector<int32_t> hi, hs;
+    std::vector<long long> hc;
     int32_t hrc = 0;
-    HIP_TRY(hipMemcpyAsync(dom, r.dout, (size_t)B * net->n * 8, hipMemcpyDeviceToHost, net->stream));
-    HIP_TRY(hipMemcpyAsync(hi.data(), r.iters, (size_t)B * 4, hipMemcpyDeviceToHost, net->stream));
-    HIP_TRY(hipMemcpyAsync(hs.data(), r.status, (size_t)B * 4, hipMemcpyDeviceToHost, net->stream));
-    HIP_TRY(hipMemcpyAsync(hc.data(), r.checks, (size_t)B * 8, hipMemcpyDeviceToHost, net->stream));
-    HIP_TRY(hipMemcpyAsync(&hrc, r.rc, 4, hipMemcpyDeviceToHost, net->stream));
-    HIP_TRY(hipStreamSynchronize(net->stream));
+    RAC_TRY(read_results(r, net->stream, B, (int64_t)B * net->n, dom, hc, hi, hs, &hrc));
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, r.ev0, r.ev1);
     fill_stats_bits(net->last, hc, hi, path, pd, ms);
@@ -1025,7 +1052,8 @@ extern "C" int rac_enforce(rac_net *net, uint64_t *dom, const int32_t *changed, 
     RAC_TRY(ensure_path(net, path, call_target(net, 1)));
     RAC_TRY(prepare_net_runner(net, 1, path == RAC_PATH_INT8 ? net->i8 : net->bits));
     Runner &r = net->run;
-    HIP_TRY(hipMemcpyAsync(r.din, dom, (size_t)net->n * 8, hipMemcpyHostToDevice, net->stream));
+    memcpy(r.h_dom, dom, (size_t)net->n * 8);
+    HIP_TRY(hipMemcpyAsync(r.din, r.h_dom, (size_t)net->n * 8, hipMemcpyHostToDevice, net->stream));
     const uint8_t *d_changed = nullptr;
     long long arcs1 = 0;
     if (changed) {
@@ -1306,8 +1334,9 @@ extern "C" int rac_enforce_batch(rac_net *net, int32_t B, uint64_t *dom, int32_t
     }
     RAC_TRY(ensure_path(net, path, call_target(net, B)));
     RAC_TRY(prepare_net_runner(net, B, path == RAC_PATH_INT8 ? net->i8 : net->bits));
-    HIP_TRY(hipMemcpyAsync(net->run.din, dom, (size_t)B * net->n * 8, hipMemcpyHostToDevice,
-                           net->stream));
+    memcpy(net->run.h_dom, dom, (size_t)B * net->n * 8);
+    HIP_TRY(hipMemcpyAsync(net->run.din, net->run.h_dom, (size_t)B * net->n * 8,
+                           hipMemcpyHostToDevice, net->stream));
     RAC_TRY(run_states(net, B, path, nullptr, 0));
     return collect_bits(net, B, path, dom, iters, status);
 }
@@ -1489,22 +1518,17 @@ extern "C" int rac_group_enforce(rac_group *g, uint64_t *const *dom, int32_t *it
     for (int32_t i = 0; i < g->k; ++i) {
         if (!dom[i]) return set_error(RAC_EINVAL, "dom[%d] is NULL", i);
         RAC_TRY(check_domains(dom[i], g->nets[(size_t)i]->n, g->nets[(size_t)i]->d));
-        memcpy(h.data() + g->h_off[(size_t)i], dom[i], (size_t)g->nets[(size_t)i]->n * 8);
+        memcpy(r.h_dom + g->h_off[(size_t)i], dom[i], (size_t)g->nets[(size_t)i]->n * 8);
     }
-    HIP_TRY(hipMemcpyAsync(r.din, h.data(), h.size() * 8, hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipMemcpyAsync(r.din, r.h_dom, h.size() * 8, hipMemcpyHostToDevice, g->stream));
     Launch L = group_launch(g, r.din, r.dout, r.iters, r.status);
     RAC_TRY(launch_fixpoint(r, g->device, g->stream, L, g->total_vars, g->total_items,
                             step_cap(g->opt, g->max_nd), g->opt.use_graph != 0,
                             g->opt.profile != 0));
-    std::vector<int32_t> hi((size_t)g->k), hs((size_t)g->k);
-    std::vector<long long> hc((size_t)g->k);
+    std::vector<int32_t> hi, hs;
+    std::vector<long long> hc;
     int32_t hrc = 0;
-    HIP_TRY(hipMemcpyAsync(h.data(), r.dout, h.size() * 8, hipMemcpyDeviceToHost, g->stream));
-    HIP_TRY(hipMemcpyAsync(hi.data(), r.iters, (size_t)g->k * 4, hipMemcpyDeviceToHost, g->stream));
-    HIP_TRY(hipMemcpyAsync(hs.data(), r.status, (size_t)g->k * 4, hipMemcpyDeviceToHost, g->stream));
-    HIP_TRY(hipMemcpyAsync(hc.data(), r.checks, (size_t)g->k * 8, hipMemcpyDeviceToHost, g->stream));
-    HIP_TRY(hipMemcpyAsync(&hrc, r.rc, 4, hipMemcpyDeviceToHost, g->stream));
-    HIP_TRY(hipStreamSynchronize(g->stream));
+    RAC_TRY(read_results(r, g->stream, g->k, g->total_vars, h.data(), hc, hi, hs, &hrc));
     for (int32_t i = 0; i < g->k; ++i)
         memcpy(dom[i], h.data() + g->h_off[(size_t)i], (size_t)g->nets[(size_t)i]->n * 8);
     if (iters) memcpy(iters, hi.data(), (size_t)g->k * 4);
