@@ -199,6 +199,8 @@ struct Runner {
     long long *checks = nullptr;
     uint8_t *h_res = nullptr;       // pinned mirror of res
     uint64_t *h_dom = nullptr;      // pinned staging of host-pointer domains [cap_vars]
+    int64_t prefetched_vars = -1;   // >= 0: results (and that many domain words) already in
+                                    // h_res / h_dom, copied by the last round of steps
     uint8_t *changed = nullptr;
     int32_t *h_nact = nullptr;      // pinned: problems still running after a round
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_round = nullptr;
@@ -310,9 +312,14 @@ static size_t res_bytes(int32_t nprob) { return (size_t)nprob * 16 + 8; }
 static int read_results(Runner &r, hipStream_t s, int32_t B, int64_t nvars, uint64_t *dom,
                         std::vector<long long> &checks, std::vector<int32_t> &iters,
                         std::vector<int32_t> &status, int32_t *rc) {
-    if (dom) HIP_TRY(hipMemcpyAsync(r.h_dom, r.dout, (size_t)nvars * 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(r.h_res, r.res, res_bytes(r.cap_probs), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    if (r.prefetched_vars >= (dom ? nvars : 0)) {
+        r.prefetched_vars = -1;   // the last round copied them and was waited for
+    } else {
+        r.prefetched_vars = -1;
+        if (dom) HIP_TRY(hipMemcpyAsync(r.h_dom, r.dout, (size_t)nvars * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(r.h_res, r.res, res_bytes(r.cap_probs), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     if (dom) memcpy(dom, r.h_dom, (size_t)nvars * 8);
     const size_t cap = (size_t)r.cap_probs;
     checks.assign(reinterpret_cast<const long long *>(r.h_res),
@@ -820,8 +827,12 @@ static int build_round(Runner &r, int round, const Launch &L, const StepGrids &s
 // the plan reports that no problem runs the next step (the host reads one
 // counter per round), then finish. `nv` variables in all; `kcap` bounds the
 // steps of every problem.
+// rb_vars >= 0: after every round also run the finish kernel and copy the
+// results and the first rb_vars words of L.dout to r.h_res / r.h_dom before the
+// round's wait, so that a run that ends there needs no further wait.
 static int launch_fixpoint(Runner &r, int device, hipStream_t stream, const Launch &L, int64_t nv,
-                           int64_t total_items, int32_t kcap, bool use_graph, bool profile = false) {
+                           int64_t total_items, int32_t kcap, bool use_graph, bool profile = false,
+                           int64_t rb_vars = -1) {
     StepGrids sg;
     sg.smem = stage_bytes(L.stage_vars);
     int64_t g = 0;
@@ -881,13 +892,28 @@ static int launch_fixpoint(Runner &r, int device, hipStream_t stream, const Laun
         }
         k += K;
         HIP_TRY(hipMemcpyAsync(r.h_nact, &L.ws.plan->nact, 4, hipMemcpyDeviceToHost, stream));
+        if (rb_vars >= 0) {
+            hipLaunchKernelGGL(finish_kernel, sg.init, dim3(256), 0, stream, L);
+            HIP_TRY(hipEventRecord(r.ev1, stream));
+            if (rb_vars > 0)
+                HIP_TRY(hipMemcpyAsync(r.h_dom, L.dout, (size_t)rb_vars * 8, hipMemcpyDeviceToHost,
+                                       stream));
+            HIP_TRY(hipMemcpyAsync(r.h_res, r.res, res_bytes(r.cap_probs), hipMemcpyDeviceToHost,
+                                   stream));
+        }
         HIP_TRY(hipEventRecord(r.ev_round, stream));
         HIP_TRY(hipEventSynchronize(r.ev_round));
         if (*r.h_nact == 0 || k >= kcap) break;
     }
-    hipLaunchKernelGGL(finish_kernel, sg.init, dim3(256), 0, stream, L);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipEventRecord(r.ev1, stream));
+    if (rb_vars >= 0) {
+        HIP_TRY(hipGetLastError());
+        r.prefetched_vars = rb_vars;
+    } else {
+        hipLaunchKernelGGL(finish_kernel, sg.init, dim3(256), 0, stream, L);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipEventRecord(r.ev1, stream));
+        r.prefetched_vars = -1;
+    }
     r.steps_launched = k;
     return RAC_OK;
 }
@@ -1004,7 +1030,7 @@ static int pick_path(const rac_net *net, int32_t B, int32_t requested) {
 
 // Bit / int8 path for B states already in r.din (host waits between rounds).
 static int run_states(rac_net *net, int32_t B, int32_t path, const uint8_t *d_changed,
-                      long long arcs1, bool allow_graph = true) {
+                      long long arcs1, bool allow_graph = true, bool readback = false) {
     PathData &pd = path == RAC_PATH_INT8 ? net->i8 : net->bits;
     RAC_TRY(ensure_path(net, path, call_target(net, B)));
     Runner &r = net->run;
@@ -1019,7 +1045,8 @@ static int run_states(rac_net *net, int32_t B, int32_t path, const uint8_t *d_ch
     L.arcs1 = arcs1;
     RAC_TRY(launch_fixpoint(r, net->device, net->stream, L, (int64_t)B * net->n,
                             (int64_t)pd.nitems * B, step_cap(net->opt, (int64_t)net->n * net->d),
-                            allow_graph && net->opt.use_graph != 0, net->opt.profile != 0));
+                            allow_graph && net->opt.use_graph != 0, net->opt.profile != 0,
+                            readback ? (int64_t)B * net->n : -1));
     return RAC_OK;
 }
 
@@ -1071,7 +1098,7 @@ extern "C" int rac_enforce(rac_net *net, uint64_t *dom, const int32_t *changed, 
         d_changed = r.changed;
         arcs1 = degs;
     }
-    RAC_TRY(run_states(net, 1, path, d_changed, arcs1));
+    RAC_TRY(run_states(net, 1, path, d_changed, arcs1, true, true));
     return collect_bits(net, 1, path, dom, iters, status);
 }
 
@@ -1337,7 +1364,7 @@ extern "C" int rac_enforce_batch(rac_net *net, int32_t B, uint64_t *dom, int32_t
     memcpy(net->run.h_dom, dom, (size_t)B * net->n * 8);
     HIP_TRY(hipMemcpyAsync(net->run.din, net->run.h_dom, (size_t)B * net->n * 8,
                            hipMemcpyHostToDevice, net->stream));
-    RAC_TRY(run_states(net, B, path, nullptr, 0));
+    RAC_TRY(run_states(net, B, path, nullptr, 0, true, true));
     return collect_bits(net, B, path, dom, iters, status);
 }
 
@@ -1524,7 +1551,7 @@ extern "C" int rac_group_enforce(rac_group *g, uint64_t *const *dom, int32_t *it
     Launch L = group_launch(g, r.din, r.dout, r.iters, r.status);
     RAC_TRY(launch_fixpoint(r, g->device, g->stream, L, g->total_vars, g->total_items,
                             step_cap(g->opt, g->max_nd), g->opt.use_graph != 0,
-                            g->opt.profile != 0));
+                            g->opt.profile != 0, g->total_vars));
     std::vector<int32_t> hi, hs;
     std::vector<long long> hc;
     int32_t hrc = 0;
