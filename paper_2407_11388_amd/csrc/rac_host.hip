@@ -1258,7 +1258,9 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
     HIP_TRY(hipMemsetAsync(b.has_best, 0, 4, s));
     HIP_TRY(hipMemcpyAsync(b.stack, root.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
     RAC_TRY(ensure_path(net, path, call_target(net, cmax)));
-    RAC_TRY(ensure_runner(r, cmax, (int64_t)cmax * n));
+    // problem tables for cmax states once: a round with C <= cmax children uses
+    // their prefix (problem s at s*n)
+    RAC_TRY(prepare_net_runner(net, cmax, pd));
     int64_t ssize = 1;
     while (true) {
         if (ssize == 0) {
@@ -1276,7 +1278,6 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
         int32_t C = 0;
         HIP_TRY(hipMemcpyAsync(&C, b.coff + P, 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        RAC_TRY(prepare_net_runner(net, C, pd));
         hipLaunchKernelGGL(search_expand_kernel, dim3((unsigned)P), dim3(256), 0, s, top, n, b.bvar,
                            b.coff, r.din, r.changed);
         HIP_TRY(hipGetLastError());
