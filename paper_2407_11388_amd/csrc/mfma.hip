@@ -28,7 +28,10 @@
 // (variable, slot word of 32 states) a change mask and a wipe-out mask. A
 // reduce kernel folds those masks over the variables per state; a one-block
 // finalise kernel applies Algorithm 1's loop test per state and compacts the
-// states that go on into the next step's active list.
+// states that go on into the next step's active list; a gather kernel moves
+// their domain bytes to their new slots. A step with too few active states to
+// fill the chip splits every tile's neighbour blocks over several workgroups
+// (mfma_split_finish_kernel applies their flags).
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
