@@ -210,6 +210,20 @@ def parse():
     return ap.parse_args()
 
 
+def host_cpu():
+    """The host's CPU model and logical core count (from /proc/cpuinfo)."""
+    model, count = "unknown", 0
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    count += 1
+                    model = line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return dict(model=model, logical_cores=count or (os.cpu_count() or 0))
+
+
 def cpu_baseline_batch(inst, doms, budget_s):
     """The CPU oracle on the first states of the batch until the time budget
     is used (one thread): its Eq. (1) recurrence (the same steps and support
@@ -220,7 +234,7 @@ def cpu_baseline_batch(inst, doms, budget_s):
     n, d = inst.n, inst.d
     rel = inst.rel_u8()
     t_rec = t_ac3 = 0.0
-    checks = 0
+    checks = revisions = lookups = 0
     done = 0
     for s in range(doms.shape[0]):
         du8 = oracle.dom_masks_to_u8(doms[s], d)
@@ -229,15 +243,20 @@ def cpu_baseline_batch(inst, doms, budget_s):
         t_rec += time.perf_counter() - t0
         checks += r["checks"]
         t0 = time.perf_counter()
-        oracle.ac3(n, d, inst.edges, rel, du8)
+        _, _, rv, lk = oracle.ac3(n, d, inst.edges, rel, du8)
         t_ac3 += time.perf_counter() - t0
+        revisions += rv
+        lookups += lk
         done += 1
         if t_rec >= budget_s:
             break
     out = dict(value=checks / t_rec, unit="support checks/s", cores=1, kind="oracle",
                sample=f"oracle Eq. (1) recurrence on the first {done} of {doms.shape[0]} "
                       f"states, one thread, {t_rec:.1f} s",
-               fixpoints_per_s=done / t_rec, ac3_fixpoints_per_s=done / t_ac3)
+               fixpoints_per_s=done / t_rec, ac3_fixpoints_per_s=done / t_ac3,
+               ac3_revisions_per_state=revisions / max(done, 1),
+               ac3_lookups_per_state=lookups / max(done, 1),
+               rac_support_checks_per_state=checks / max(done, 1), host=host_cpu())
     # the same oracle on the following states from a pool of threads (the C
     # recurrence runs without the interpreter lock), for about a third of the
     # budget: all host cores (up to 16, the host share of one GPU)
@@ -282,11 +301,13 @@ def cpu_baseline_single(inst, dom, budget_s):
             break
     t = (time.perf_counter() - t0) / reps
     t1 = time.perf_counter()
-    oracle.ac3(n, d, inst.edges, rel, du8)
+    _, _, revisions, lookups = oracle.ac3(n, d, inst.edges, rel, du8)
     t_ac3 = time.perf_counter() - t1
     return dict(value=checks / t, unit="support checks/s", cores=1, kind="oracle",
                 sample=f"oracle Eq. (1) recurrence, one thread, {reps} run(s) of the instance",
-                fixpoints_per_s=1.0 / t, ac3_fixpoints_per_s=1.0 / t_ac3)
+                fixpoints_per_s=1.0 / t, ac3_fixpoints_per_s=1.0 / t_ac3,
+                ac3_revisions=revisions, ac3_lookups=lookups, rac_support_checks=checks,
+                host=host_cpu())
 
 
 def search_lines():
