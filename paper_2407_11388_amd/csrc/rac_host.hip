@@ -1029,13 +1029,16 @@ static int pick_path(const rac_net *net, int32_t B, int32_t requested) {
 }
 
 // Bit / int8 path for B states already in r.din (host waits between rounds).
+// item_bytes > 0 fixes the work-item size (else the default for B states).
 static int run_states(rac_net *net, int32_t B, int32_t path, const uint8_t *d_changed,
-                      long long arcs1, bool allow_graph = true, bool readback = false) {
+                      long long arcs1, bool allow_graph = true, bool readback = false,
+                      int32_t item_bytes = 0) {
     PathData &pd = path == RAC_PATH_INT8 ? net->i8 : net->bits;
-    RAC_TRY(ensure_path(net, path, call_target(net, B)));
+    RAC_TRY(ensure_path(net, path, item_bytes > 0 ? item_bytes : call_target(net, B)));
     Runner &r = net->run;
     Launch L = base_launch(r, B, net->opt);
     L.nets = pd.d_desc;
+    L.uniform_n = net->n;   // problem s at s*n
     L.stage_vars = stage_vars_for(net->n);
     L.din = r.din;
     L.dout = r.dout;
@@ -1129,6 +1132,7 @@ static int run_mfma(rac_net *net, int32_t B, const uint64_t *d_in, uint64_t *d_o
         RAC_TRY(mfma_handoff(net->mfma, k, r.din, r.changed, s));
         Launch L = base_launch(r, P, net->opt);
         L.nets = pd.d_desc;
+        L.uniform_n = net->n;   // problem s at s*n
         L.stage_vars = stage_vars_for(net->n);
         L.din = r.din;
         L.dout = r.dout;
@@ -1154,11 +1158,13 @@ namespace {
 struct SearchBufs {
     uint64_t *stack = nullptr, *best = nullptr;
     int32_t *bvar = nullptr, *nchild = nullptr, *coff = nullptr, *has_best = nullptr;
-    long long *steps = nullptr;
+    long long *stats = nullptr;
     int32_t *is_sol = nullptr, *is_open = nullptr, *sol_off = nullptr, *open_off = nullptr,
             *sol_list = nullptr;
+    long long *h_stats = nullptr;   // pinned: a round's summary, then the child count
     int64_t cap = 0;   // stack capacity in nodes
     ~SearchBufs() {
+        if (h_stats) (void)hipHostFree(h_stats);
         dfree(stack);
         dfree(best);
         dfree(bvar);
@@ -1170,7 +1176,7 @@ struct SearchBufs {
         dfree(sol_off);
         dfree(open_off);
         dfree(sol_list);
-        dfree(steps);
+        dfree(stats);
     }
 };
 
@@ -1254,10 +1260,14 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
     RAC_TRY(dalloc(&b.sol_off, (size_t)cmax + 1));
     RAC_TRY(dalloc(&b.open_off, (size_t)cmax + 1));
     RAC_TRY(dalloc(&b.sol_list, (size_t)cmax));
-    RAC_TRY(dalloc(&b.steps, 1));
+    RAC_TRY(dalloc(&b.stats, 4));
+    HIP_TRY(hipHostMalloc((void **)&b.h_stats, 8 * sizeof(long long), hipHostMallocDefault));
     HIP_TRY(hipMemsetAsync(b.has_best, 0, 4, s));
     HIP_TRY(hipMemcpyAsync(b.stack, root.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
     RAC_TRY(ensure_path(net, path, call_target(net, cmax)));
+    // one work-item size for every round (the one for cmax states), so that
+    // rounds of different sizes reuse the item table
+    const int32_t item_bytes = pd.item_bytes;
     // problem tables for cmax states once: a round with C <= cmax children uses
     // their prefix (problem s at s*n)
     RAC_TRY(prepare_net_runner(net, cmax, pd));
@@ -1275,27 +1285,24 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
         hipLaunchKernelGGL(search_branch_kernel, dim3((unsigned)P), dim3(64), 0, s, top, n, b.bvar,
                            b.nchild);
         hipLaunchKernelGGL(search_offsets_kernel, dim3(1), dim3(1024), 0, s, b.nchild, P, b.coff);
-        int32_t C = 0;
-        HIP_TRY(hipMemcpyAsync(&C, b.coff + P, 4, hipMemcpyDeviceToHost, s));
+        int32_t *h_c = (int32_t *)(b.h_stats + 4);
+        HIP_TRY(hipMemcpyAsync(h_c, b.coff + P, 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        const int32_t C = *h_c;
         hipLaunchKernelGGL(search_expand_kernel, dim3((unsigned)P), dim3(256), 0, s, top, n, b.bvar,
                            b.coff, r.din, r.changed);
         HIP_TRY(hipGetLastError());
         ssize = base;
-        RAC_TRY(run_states(net, C, path, r.changed, -1, false));
+        RAC_TRY(run_states(net, C, path, r.changed, -1, false, false, item_bytes));
         hipLaunchKernelGGL(search_classify_kernel, dim3((unsigned)C), dim3(64), 0, s, r.dout,
                            r.status, n, b.is_sol, b.is_open);
         hipLaunchKernelGGL(search_lists_kernel, dim3(1), dim3(1024), 0, s, b.is_sol, b.is_open,
-                           r.iters, C, b.sol_off, b.open_off, b.steps);
-        int32_t cnt[2] = {0, 0};
-        long long steps = 0;
-        HIP_TRY(hipMemcpyAsync(&steps, b.steps, 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(&cnt[0], b.sol_off + C, 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(&cnt[1], b.open_off + C, 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(&hrc, r.rc, 4, hipMemcpyDeviceToHost, s));
+                           r.iters, C, r.rc, b.sol_off, b.open_off, b.stats);
+        HIP_TRY(hipMemcpyAsync(b.h_stats, b.stats, 4 * sizeof(long long), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        RAC_TRY(rc_from_device(hrc));
-        const int32_t nsol = cnt[0], nopen = cnt[1];
+        RAC_TRY(rc_from_device((int32_t)b.h_stats[3]));
+        const long long steps = b.h_stats[0];
+        const int32_t nsol = (int32_t)b.h_stats[1], nopen = (int32_t)b.h_stats[2];
         if (ssize + nopen > b.cap) {   // grow the stack (device copy of the live part)
             const int64_t ncap = std::max<int64_t>(2 * b.cap, ssize + nopen);
             uint64_t *ns = nullptr;
@@ -1394,6 +1401,7 @@ extern "C" int rac_enforce_batch_device(rac_net *net, int32_t B, const uint64_t 
     Runner &r = net->run;
     Launch L = base_launch(r, B, net->opt);
     L.nets = pd.d_desc;
+    L.uniform_n = net->n;   // problem s at s*n
     L.stage_vars = stage_vars_for(net->n);
     L.din = d_dom_in;
     L.dout = d_dom_out;

@@ -114,6 +114,8 @@ struct Launch {
     int32_t *rc_out;          // [1]: 1 if some problem reached max_sweeps unconverged
     int32_t push_ratio;       // steps k >= 2 of a bit-row problem that re-examine at most
                               // arcs / push_ratio arcs go variable by variable (0: never)
+    int32_t uniform_n;        // > 0: every problem has uniform_n variables, prob_off[p] =
+                              // p * uniform_n (else 0)
 };
 
 // Records a message for rac_last_error() and returns `code` (rac_host.hip).
@@ -140,8 +142,8 @@ __global__ void search_expand_kernel(const uint64_t *nodes, int32_t n, const int
 __global__ void search_classify_kernel(const uint64_t *cres, const int32_t *status, int32_t n,
                                        int32_t *is_sol, int32_t *is_open);
 __global__ void search_lists_kernel(const int32_t *is_sol, const int32_t *is_open,
-                                    const int32_t *iters, int32_t C, int32_t *sol_off,
-                                    int32_t *open_off, long long *steps);
+                                    const int32_t *iters, int32_t C, const int32_t *rc,
+                                    int32_t *sol_off, int32_t *open_off, long long *stats);
 __global__ void search_push_kernel(const uint64_t *cres, int32_t n, int32_t C, const int32_t *is_sol,
                                    const int32_t *is_open, const int32_t *sol_off,
                                    const int32_t *open_off, uint64_t *stack, int64_t base,

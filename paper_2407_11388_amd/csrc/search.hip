@@ -119,24 +119,32 @@ __global__ __launch_bounds__(64) void search_classify_kernel(const uint64_t *cre
 }
 
 // Offsets of the solution and open lists (two scans in one workgroup), and
-// the recurrence steps of all C children.
+// the round's summary for the host in one block: stats[0] = recurrence steps
+// of all C children, stats[1] = solutions, stats[2] = open children,
+// stats[3] = the step kernels' return flags (*rc).
 __global__ __launch_bounds__(1024) void search_lists_kernel(const int32_t *is_sol,
                                                             const int32_t *is_open,
                                                             const int32_t *iters, int32_t C,
-                                                            int32_t *sol_off, int32_t *open_off,
-                                                            long long *steps) {
+                                                            const int32_t *rc, int32_t *sol_off,
+                                                            int32_t *open_off, long long *stats) {
     __shared__ long long s_steps;
     block_scan(is_sol, C, sol_off);
+    // thread 0 wrote sol_off[C] itself
+    if (threadIdx.x == 0) stats[1] = sol_off[C];
     __syncthreads();
     block_scan(is_open, C, open_off);
-    if (threadIdx.x == 0) s_steps = 0;
+    if (threadIdx.x == 0) {
+        stats[2] = open_off[C];
+        stats[3] = *rc;
+        s_steps = 0;
+    }
     __syncthreads();
     long long t = 0;
     for (int32_t c = threadIdx.x; c < C; c += blockDim.x) t += iters[c];
     for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o, 64);
     if ((threadIdx.x & 63) == 0) atomicAdd((unsigned long long *)&s_steps, (unsigned long long)t);
     __syncthreads();
-    if (threadIdx.x == 0) *steps = s_steps;
+    if (threadIdx.x == 0) stats[0] = s_steps;
 }
 
 // Open children go onto the stack above `base`, the last child lowest, so
@@ -159,37 +167,58 @@ __global__ __launch_bounds__(256) void search_push_kernel(const uint64_t *cres, 
     for (int32_t x = threadIdx.x; x < n; x += blockDim.x) dst[x] = src[x];
 }
 
+namespace {
+
+// Whether assignment a is lexicographically smaller than b (n singleton
+// domains each; the first variable where they differ decides, and there the
+// lower bit is the smaller value). Whole wave, uniform result.
+__device__ __forceinline__ bool wave_lex_less(const uint64_t *a, const uint64_t *b, int32_t n) {
+    const int lane = threadIdx.x & 63;
+    for (int32_t x0 = 0; x0 < n; x0 += 64) {
+        const int32_t x = x0 + lane;
+        const uint64_t va = x < n ? a[x] : 0ull, vb = x < n ? b[x] : 0ull;
+        const uint64_t diff = __ballot(va != vb);
+        if (diff) {
+            const int f = __ffsll((unsigned long long)diff) - 1;
+            return __shfl((int)(va < vb), f, 64) != 0;
+        }
+    }
+    return false;
+}
+
+}  // namespace
+
 // The lexicographically smallest solution (value of variable 0 first, then
-// 1, ...) among `best` (if has_best) and the listed solutions. One
-// workgroup: per candidate, the first variable where it differs from the
-// current best decides.
+// 1, ...) among `best` (if has_best) and the listed solutions. One workgroup
+// of 16 waves: each wave keeps the smallest of every 16th listed solution,
+// then wave 0 merges the wave results with `best`.
 __global__ __launch_bounds__(1024) void search_best_kernel(const uint64_t *cres, int32_t n,
                                                            const int32_t *sol_list,
                                                            const int32_t *sol_off, int32_t C,
                                                            uint64_t *best, int32_t *has_best) {
-    __shared__ int32_t s_first;
+    __shared__ int32_t s_win[16];
     const int32_t ns = sol_off[C];
-    for (int32_t k = 0; k < ns; ++k) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int32_t win = -1;   // index into sol_list
+    for (int32_t k = wave; k < ns; k += 16) {
+        if (win < 0 || wave_lex_less(cres + (int64_t)sol_list[k] * n,
+                                     cres + (int64_t)sol_list[win] * n, n))
+            win = k;
+    }
+    if (lane == 0) s_win[wave] = win;
+    __syncthreads();
+    if (wave != 0) return;
+    const bool had = *has_best != 0;
+    const uint64_t *cur = had ? best : nullptr;
+    for (int w = 0; w < 16; ++w) {
+        const int32_t k = s_win[w];
+        if (k < 0) continue;
         const uint64_t *cand = cres + (int64_t)sol_list[k] * n;
-        if (*has_best == 0) {
-            for (int32_t x = threadIdx.x; x < n; x += blockDim.x) best[x] = cand[x];
-            __syncthreads();
-            if (threadIdx.x == 0) *has_best = 1;
-            __syncthreads();
-            continue;
-        }
-        if (threadIdx.x == 0) s_first = n;
-        __syncthreads();
-        for (int32_t x = threadIdx.x; x < n; x += blockDim.x)
-            if (cand[x] != best[x]) atomicMin(&s_first, x);
-        __syncthreads();
-        const int32_t f = s_first;
-        // singletons: the lower bit is the smaller value
-        const bool smaller = f < n && cand[f] < best[f];
-        __syncthreads();
-        if (smaller)
-            for (int32_t x = threadIdx.x; x < n; x += blockDim.x) best[x] = cand[x];
-        __syncthreads();
+        if (!cur || wave_lex_less(cand, cur, n)) cur = cand;
+    }
+    if (cur && cur != best) {
+        for (int32_t x = lane; x < n; x += 64) best[x] = cur[x];
+        if (lane == 0) *has_best = 1;
     }
 }
 

@@ -468,6 +468,7 @@ DEV bool listed_after(const Launch &L, const NetDesc &N, const Ctrl &C, int k) {
 }
 
 DEV int prob_of_var(const Launch &L, int64_t v) {
+    if (L.uniform_n > 0) return (int)(v / L.uniform_n);
     int lo = 0, hi = L.nprob - 1;   // largest p with prob_off[p] <= v
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -477,7 +478,11 @@ DEV int prob_of_var(const Launch &L, int64_t v) {
 }
 
 // The problems that execute step k, in order, with the prefix sums of their
-// item counts. One workgroup of 1024 threads.
+// item counts. One workgroup of 1024 threads; a pass gives each thread up to
+// kPlanPer consecutive problems, whose loads are all issued before any is
+// used (clamped indices), so that a pass costs about one memory latency.
+constexpr int kPlanPer = 8;
+
 __global__ __launch_bounds__(1024) void plan_kernel(Launch L, int k) {
     __shared__ int64_t s_wave[16];
     __shared__ int64_t s_base_items;
@@ -489,50 +494,72 @@ __global__ __launch_bounds__(1024) void plan_kernel(Launch L, int k) {
         s_base_n = 0;
     }
     __syncthreads();
-    for (int32_t p0 = 0; p0 < L.nprob; p0 += 1024) {
-        const int32_t p = p0 + (int32_t)threadIdx.x;
-        bool on = false;
-        int32_t push = 0;
-        int64_t items = 0;
-        if (p < L.nprob) {
-            const NetDesc &N = L.nets[L.prob_net[p]];
-            const Ctrl &C = L.ws.ctrl[p];
-            on = active(L, N, C, k);
+    for (int32_t p0 = 0; p0 < L.nprob; p0 += 1024 * kPlanPer) {
+        const int32_t left = L.nprob - p0;
+        const int32_t per = left >= 1024 * kPlanPer ? kPlanPer : (left + 1023) / 1024;
+        const int32_t pt = p0 + (int32_t)threadIdx.x * per;   // this thread's first problem
+        int64_t items[kPlanPer];
+        uint32_t on_m = 0, push_m = 0;
+        int64_t tot = 0;
+#pragma unroll
+        for (int i = 0; i < kPlanPer; ++i) {
+            const int32_t p = pt + i;
+            const bool valid = i < per && p < L.nprob;
+            const int32_t pc = valid ? p : L.nprob - 1;
+            const NetDesc &N = L.nets[L.prob_net[pc]];
+            const Ctrl &C = L.ws.ctrl[pc];
+            const bool on = valid && active(L, N, C, k);
             // few arcs to re-examine: the changed variables' pieces instead
             // of a scan of every group (step 1 of an incremental start: the
             // pieces of the listed @changed variables bound the arcs). Step
             // k-1 listed its changed variables only if it was itself sparse.
-            if (on && L.push_ratio > 0 && N.rpos) {
+            bool push = false;
+            if (L.push_ratio > 0 && N.rpos) {
                 if (k > 1)
-                    push = listed_after(L, N, C, k - 1) && C.arcs[(k - 1) % 3] * L.push_ratio <= N.arcs;
+                    push = listed_after(L, N, C, k - 1) &&
+                           C.arcs[(k - 1) % 3] * L.push_ratio <= N.arcs;
                 else if (L.changed0)
                     push = (int64_t)C.nchg[0] * N.pchunks * kWave * L.push_ratio <= N.arcs;
             }
-            if (on) items = push ? (int64_t)C.nchg[(k - 1) & 1] * N.pchunks : N.nitems;
+            push = push && on;
+            items[i] = !on ? 0 : push ? (int64_t)C.nchg[(k - 1) & 1] * N.pchunks : N.nitems;
+            on_m |= (uint32_t)on << i;
+            push_m |= (uint32_t)push << i;
+            tot += items[i];
         }
-        // inclusive scan of the item counts within the wave, then across waves
-        int64_t inc = items;
+        const int32_t cnt = __popc(on_m);
+        // inclusive scans of the thread totals within the wave, then across waves
+        int64_t inc = tot;
+        int32_t incn = cnt;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const int64_t t = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += t;
+            const int32_t tn = __shfl_up(incn, o, 64);
+            if (lane >= o) {
+                inc += t;
+                incn += tn;
+            }
         }
-        const uint64_t bal = __ballot(on);
-        const int rank = lane_rank(bal);
-        if (lane == 63) s_wave[wave] = inc;
-        if (lane == 0) s_wave_n[wave] = __popcll(bal);
+        if (lane == 63) {
+            s_wave[wave] = inc;
+            s_wave_n[wave] = incn;
+        }
         __syncthreads();
-        int64_t before = s_base_items;
-        int32_t nbefore = s_base_n;
+        int64_t before = s_base_items + inc - tot;
+        int32_t nbefore = s_base_n + incn - cnt;
         for (int w = 0; w < wave; ++w) {
             before += s_wave[w];
             nbefore += s_wave_n[w];
         }
-        if (on) {
-            L.ws.act[nbefore + rank] = p;
-            L.ws.act_off[nbefore + rank] = before + inc - items;
-            L.ws.act_push[nbefore + rank] = push;
-        }
+#pragma unroll
+        for (int i = 0; i < kPlanPer; ++i)
+            if ((on_m >> i) & 1u) {
+                L.ws.act[nbefore] = pt + i;
+                L.ws.act_off[nbefore] = before;
+                L.ws.act_push[nbefore] = (int32_t)((push_m >> i) & 1u);
+                before += items[i];
+                ++nbefore;
+            }
         __syncthreads();
         if (threadIdx.x == 0) {
             for (int w = 0; w < 16; ++w) {
