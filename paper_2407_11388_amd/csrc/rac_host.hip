@@ -202,6 +202,8 @@ struct Runner {
     int64_t prefetched_vars = -1;   // >= 0: results (and that many domain words) already in
                                     // h_res / h_dom, copied by the last round of steps
     uint8_t *changed = nullptr;
+    int32_t *count = nullptr;       // a device problem count (Launch::nprob_dev) of a caller
+                                    // that decides it on the device
     int32_t *h_nact = nullptr;      // pinned: problems still running after a round
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_round = nullptr;
     hipEvent_t kev[2 * kProfSteps] = {};
@@ -291,6 +293,7 @@ static void release_runner(Runner &r) {
     r.h_res = nullptr;
     r.h_dom = nullptr;
     dfree(r.changed);
+    dfree(r.count);
     if (r.h_nact) (void)hipHostFree(r.h_nact);
     r.h_nact = nullptr;
     if (r.ev0) (void)hipEventDestroy(r.ev0);
@@ -359,6 +362,7 @@ static int ensure_runner(Runner &r, int32_t nprob, int64_t nvars) {
     HIP_TRY(hipHostMalloc((void **)&r.h_res, res_bytes(nprob), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void **)&r.h_dom, (size_t)nvars * 8, hipHostMallocDefault));
     RAC_TRY(dalloc(&r.changed, nvars));
+    RAC_TRY(dalloc(&r.count, 1));
     HIP_TRY(hipHostMalloc((void **)&r.h_nact, 4, hipHostMallocDefault));
     HIP_TRY(hipEventCreate(&r.ev0));
     HIP_TRY(hipEventCreate(&r.ev1));
@@ -1030,9 +1034,11 @@ static int pick_path(const rac_net *net, int32_t B, int32_t requested) {
 
 // Bit / int8 path for B states already in r.din (host waits between rounds).
 // item_bytes > 0 fixes the work-item size (else the default for B states).
+// d_count non-null: the first *d_count of the B states run (a device count,
+// see Launch::nprob_dev).
 static int run_states(rac_net *net, int32_t B, int32_t path, const uint8_t *d_changed,
                       long long arcs1, bool allow_graph = true, bool readback = false,
-                      int32_t item_bytes = 0) {
+                      int32_t item_bytes = 0, const int32_t *d_count = nullptr) {
     PathData &pd = path == RAC_PATH_INT8 ? net->i8 : net->bits;
     RAC_TRY(ensure_path(net, path, item_bytes > 0 ? item_bytes : call_target(net, B)));
     Runner &r = net->run;
@@ -1046,6 +1052,7 @@ static int run_states(rac_net *net, int32_t B, int32_t path, const uint8_t *d_ch
     L.status_out = r.status;
     L.changed0 = d_changed;
     L.arcs1 = arcs1;
+    L.nprob_dev = d_count;
     RAC_TRY(launch_fixpoint(r, net->device, net->stream, L, (int64_t)B * net->n,
                             (int64_t)pd.nitems * B, step_cap(net->opt, (int64_t)net->n * net->d),
                             allow_graph && net->opt.use_graph != 0, net->opt.profile != 0,
@@ -1161,7 +1168,7 @@ struct SearchBufs {
     long long *stats = nullptr;
     int32_t *is_sol = nullptr, *is_open = nullptr, *sol_off = nullptr, *open_off = nullptr,
             *sol_list = nullptr;
-    long long *h_stats = nullptr;   // pinned: a round's summary, then the child count
+    long long *h_stats = nullptr;   // pinned: a round's summary
     int64_t cap = 0;   // stack capacity in nodes
     ~SearchBufs() {
         if (h_stats) (void)hipHostFree(h_stats);
@@ -1260,7 +1267,7 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
     RAC_TRY(dalloc(&b.sol_off, (size_t)cmax + 1));
     RAC_TRY(dalloc(&b.open_off, (size_t)cmax + 1));
     RAC_TRY(dalloc(&b.sol_list, (size_t)cmax));
-    RAC_TRY(dalloc(&b.stats, 4));
+    RAC_TRY(dalloc(&b.stats, 8));
     HIP_TRY(hipHostMalloc((void **)&b.h_stats, 8 * sizeof(long long), hipHostMallocDefault));
     HIP_TRY(hipMemsetAsync(b.has_best, 0, 4, s));
     HIP_TRY(hipMemcpyAsync(b.stack, root.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
@@ -1281,30 +1288,11 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
         if (max_nodes > 0 && out->nodes >= max_nodes) break;
         const int32_t P = (int32_t)std::min<int64_t>(ssize, batch);
         const int64_t base = ssize - P;   // the top P nodes
-        const uint64_t *top = b.stack + base * n;
-        hipLaunchKernelGGL(search_branch_kernel, dim3((unsigned)P), dim3(64), 0, s, top, n, b.bvar,
-                           b.nchild);
-        hipLaunchKernelGGL(search_offsets_kernel, dim3(1), dim3(1024), 0, s, b.nchild, P, b.coff);
-        int32_t *h_c = (int32_t *)(b.h_stats + 4);
-        HIP_TRY(hipMemcpyAsync(h_c, b.coff + P, 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        const int32_t C = *h_c;
-        hipLaunchKernelGGL(search_expand_kernel, dim3((unsigned)P), dim3(256), 0, s, top, n, b.bvar,
-                           b.coff, r.din, r.changed);
-        HIP_TRY(hipGetLastError());
-        ssize = base;
-        RAC_TRY(run_states(net, C, path, r.changed, -1, false, false, item_bytes));
-        hipLaunchKernelGGL(search_classify_kernel, dim3((unsigned)C), dim3(64), 0, s, r.dout,
-                           r.status, n, b.is_sol, b.is_open);
-        hipLaunchKernelGGL(search_lists_kernel, dim3(1), dim3(1024), 0, s, b.is_sol, b.is_open,
-                           r.iters, C, r.rc, b.sol_off, b.open_off, b.stats);
-        HIP_TRY(hipMemcpyAsync(b.h_stats, b.stats, 4 * sizeof(long long), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        RAC_TRY(rc_from_device((int32_t)b.h_stats[3]));
-        const long long steps = b.h_stats[0];
-        const int32_t nsol = (int32_t)b.h_stats[1], nopen = (int32_t)b.h_stats[2];
-        if (ssize + nopen > b.cap) {   // grow the stack (device copy of the live part)
-            const int64_t ncap = std::max<int64_t>(2 * b.cap, ssize + nopen);
+        // at most P*d children, so at most that many open ones go back above
+        // base: grow the stack first (device copy of the live part)
+        const int32_t cbound = P * d;
+        if (base + cbound > b.cap) {
+            const int64_t ncap = std::max<int64_t>(2 * b.cap, base + cbound);
             uint64_t *ns = nullptr;
             RAC_TRY(dalloc(&ns, (size_t)(ncap * n)));
             HIP_TRY(hipMemcpyAsync(ns, b.stack, (size_t)(ssize * n) * 8, hipMemcpyDeviceToDevice, s));
@@ -1313,12 +1301,36 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
             b.stack = ns;
             b.cap = ncap;
         }
-        hipLaunchKernelGGL(search_push_kernel, dim3((unsigned)C), dim3(256), 0, s, r.dout, n, C,
-                           b.is_sol, b.is_open, b.sol_off, b.open_off, b.stack, ssize, b.sol_list);
-        if (nsol > 0)
-            hipLaunchKernelGGL(search_best_kernel, dim3(1), dim3(1024), 0, s, r.dout, n, b.sol_list,
-                               b.sol_off, C, b.best, b.has_best);
+        const uint64_t *top = b.stack + base * n;
+        // the child count C stays on the device (r.count): the kernels below
+        // read it, and the host learns it with the round's summary
+        hipLaunchKernelGGL(search_branch_kernel, dim3((unsigned)P), dim3(64), 0, s, top, n, b.bvar,
+                           b.nchild);
+        hipLaunchKernelGGL(search_offsets_kernel, dim3(1), dim3(1024), 0, s, b.nchild, P, b.coff,
+                           r.count);
+        hipLaunchKernelGGL(search_expand_kernel, dim3((unsigned)P), dim3(256), 0, s, top, n, b.bvar,
+                           b.coff, r.din, r.changed);
         HIP_TRY(hipGetLastError());
+        ssize = base;
+        // launched for cmax states with the count on the device: the same
+        // arguments every round, so the captured step graphs are reused
+        RAC_TRY(run_states(net, cmax, path, r.changed, -1, true, false, item_bytes, r.count));
+        hipLaunchKernelGGL(search_classify_kernel, dim3((unsigned)cbound), dim3(64), 0, s, r.dout,
+                           r.status, n, r.count, b.is_sol, b.is_open);
+        hipLaunchKernelGGL(search_lists_kernel, dim3(1), dim3(1024), 0, s, b.is_sol, b.is_open,
+                           r.iters, r.count, r.rc, b.sol_off, b.open_off, b.stats);
+        hipLaunchKernelGGL(search_push_kernel, dim3((unsigned)cbound), dim3(256), 0, s, r.dout, n,
+                           r.count, b.is_sol, b.is_open, b.sol_off, b.open_off, b.stack, ssize,
+                           b.sol_list);
+        hipLaunchKernelGGL(search_best_kernel, dim3(1), dim3(1024), 0, s, r.dout, n, b.sol_list,
+                           b.sol_off, r.count, b.best, b.has_best);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(b.h_stats, b.stats, 5 * sizeof(long long), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        RAC_TRY(rc_from_device((int32_t)b.h_stats[3]));
+        const long long steps = b.h_stats[0];
+        const int32_t nsol = (int32_t)b.h_stats[1], nopen = (int32_t)b.h_stats[2];
+        const int32_t C = (int32_t)b.h_stats[4];
         out->nodes += C;
         out->sweeps += steps;
         out->solutions += nsol;

@@ -116,6 +116,9 @@ struct Launch {
                               // arcs / push_ratio arcs go variable by variable (0: never)
     int32_t uniform_n;        // > 0: every problem has uniform_n variables, prob_off[p] =
                               // p * uniform_n (else 0)
+    const int32_t *nprob_dev; // non-null: the number of problems is *nprob_dev (<= nprob),
+                              // read on the device when each kernel starts, so that one
+                              // captured graph serves calls with different counts
 };
 
 // Records a message for rac_last_error() and returns `code` (rac_host.hip).
@@ -136,20 +139,21 @@ __global__ void pack_i8_kernel(const uint64_t *rel, const int32_t *arc_src, int6
 // Batched MAC search (search.hip).
 __global__ void search_branch_kernel(const uint64_t *nodes, int32_t n, int32_t *bvar,
                                      int32_t *nchild);
-__global__ void search_offsets_kernel(const int32_t *nchild, int32_t P, int32_t *coff);
+__global__ void search_offsets_kernel(const int32_t *nchild, int32_t P, int32_t *coff,
+                                      int32_t *total);
 __global__ void search_expand_kernel(const uint64_t *nodes, int32_t n, const int32_t *bvar,
                                      const int32_t *coff, uint64_t *cdom, uint8_t *cchg);
 __global__ void search_classify_kernel(const uint64_t *cres, const int32_t *status, int32_t n,
-                                       int32_t *is_sol, int32_t *is_open);
+                                       const int32_t *count, int32_t *is_sol, int32_t *is_open);
 __global__ void search_lists_kernel(const int32_t *is_sol, const int32_t *is_open,
-                                    const int32_t *iters, int32_t C, const int32_t *rc,
+                                    const int32_t *iters, const int32_t *count, const int32_t *rc,
                                     int32_t *sol_off, int32_t *open_off, long long *stats);
-__global__ void search_push_kernel(const uint64_t *cres, int32_t n, int32_t C, const int32_t *is_sol,
-                                   const int32_t *is_open, const int32_t *sol_off,
-                                   const int32_t *open_off, uint64_t *stack, int64_t base,
-                                   int32_t *sol_list);
+__global__ void search_push_kernel(const uint64_t *cres, int32_t n, const int32_t *count,
+                                   const int32_t *is_sol, const int32_t *is_open,
+                                   const int32_t *sol_off, const int32_t *open_off, uint64_t *stack,
+                                   int64_t base, int32_t *sol_list);
 __global__ void search_best_kernel(const uint64_t *cres, int32_t n, const int32_t *sol_list,
-                                   const int32_t *sol_off, int32_t C, uint64_t *best,
+                                   const int32_t *sol_off, const int32_t *count, uint64_t *best,
                                    int32_t *has_best);
 
 }  // namespace rac

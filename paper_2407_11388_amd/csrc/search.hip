@@ -70,10 +70,13 @@ __global__ __launch_bounds__(64) void search_branch_kernel(const uint64_t *nodes
     }
 }
 
-// Child offsets: coff[i] = children of nodes 0..i-1, coff[P] = all children.
+// Child offsets: coff[i] = children of nodes 0..i-1, coff[P] = all children,
+// also stored in *total (the problem count of the round's enforcement).
 __global__ __launch_bounds__(1024) void search_offsets_kernel(const int32_t *nchild, int32_t P,
-                                                              int32_t *coff) {
+                                                              int32_t *coff, int32_t *total) {
     block_scan(nchild, P, coff);
+    // thread 0 wrote coff[P] itself
+    if (threadIdx.x == 0) *total = coff[P];
 }
 
 // Children of node i (one workgroup per node): child j takes the j-th value
@@ -101,11 +104,14 @@ __global__ __launch_bounds__(256) void search_expand_kernel(const uint64_t *node
 
 // Kind of each enforced child, as 0/1 flags for the list scans that follow:
 // a solution (not wiped out, every domain a singleton) or open (not wiped
-// out, some domain larger); neither means a failure. One wave per child.
+// out, some domain larger); neither means a failure. One wave per child,
+// *count children (the grid may be larger).
 __global__ __launch_bounds__(64) void search_classify_kernel(const uint64_t *cres,
                                                              const int32_t *status, int32_t n,
+                                                             const int32_t *count,
                                                              int32_t *is_sol, int32_t *is_open) {
     const int32_t c = blockIdx.x;
+    if (c >= *count) return;
     const int lane = threadIdx.x;
     const uint64_t *dom = cres + (int64_t)c * n;
     int multi = 0;
@@ -120,14 +126,16 @@ __global__ __launch_bounds__(64) void search_classify_kernel(const uint64_t *cre
 
 // Offsets of the solution and open lists (two scans in one workgroup), and
 // the round's summary for the host in one block: stats[0] = recurrence steps
-// of all C children, stats[1] = solutions, stats[2] = open children,
-// stats[3] = the step kernels' return flags (*rc).
+// of all C = *count children, stats[1] = solutions, stats[2] = open children,
+// stats[3] = the step kernels' return flags (*rc), stats[4] = C.
 __global__ __launch_bounds__(1024) void search_lists_kernel(const int32_t *is_sol,
                                                             const int32_t *is_open,
-                                                            const int32_t *iters, int32_t C,
+                                                            const int32_t *iters,
+                                                            const int32_t *count,
                                                             const int32_t *rc, int32_t *sol_off,
                                                             int32_t *open_off, long long *stats) {
     __shared__ long long s_steps;
+    const int32_t C = *count;
     block_scan(is_sol, C, sol_off);
     // thread 0 wrote sol_off[C] itself
     if (threadIdx.x == 0) stats[1] = sol_off[C];
@@ -136,6 +144,7 @@ __global__ __launch_bounds__(1024) void search_lists_kernel(const int32_t *is_so
     if (threadIdx.x == 0) {
         stats[2] = open_off[C];
         stats[3] = *rc;
+        stats[4] = C;
         s_steps = 0;
     }
     __syncthreads();
@@ -149,14 +158,17 @@ __global__ __launch_bounds__(1024) void search_lists_kernel(const int32_t *is_so
 
 // Open children go onto the stack above `base`, the last child lowest, so
 // that the first child (the smallest value of the first node) ends on top;
-// solutions are listed in child order.
-__global__ __launch_bounds__(256) void search_push_kernel(const uint64_t *cres, int32_t n, int32_t C,
+// solutions are listed in child order. One workgroup per child, C = *count
+// children (the grid may be larger).
+__global__ __launch_bounds__(256) void search_push_kernel(const uint64_t *cres, int32_t n,
+                                                          const int32_t *count,
                                                           const int32_t *is_sol,
                                                           const int32_t *is_open,
                                                           const int32_t *sol_off,
                                                           const int32_t *open_off, uint64_t *stack,
                                                           int64_t base, int32_t *sol_list) {
     const int32_t c = blockIdx.x;
+    const int32_t C = *count;
     if (c >= C) return;
     if (is_sol[c] && threadIdx.x == 0) sol_list[sol_off[c]] = c;
     if (!is_open[c]) return;
@@ -189,15 +201,18 @@ __device__ __forceinline__ bool wave_lex_less(const uint64_t *a, const uint64_t 
 }  // namespace
 
 // The lexicographically smallest solution (value of variable 0 first, then
-// 1, ...) among `best` (if has_best) and the listed solutions. One workgroup
+// 1, ...) among `best` (if has_best) and the listed solutions of the *count
+// children. One workgroup
 // of 16 waves: each wave keeps the smallest of every 16th listed solution,
 // then wave 0 merges the wave results with `best`.
 __global__ __launch_bounds__(1024) void search_best_kernel(const uint64_t *cres, int32_t n,
                                                            const int32_t *sol_list,
-                                                           const int32_t *sol_off, int32_t C,
-                                                           uint64_t *best, int32_t *has_best) {
+                                                           const int32_t *sol_off,
+                                                           const int32_t *count, uint64_t *best,
+                                                           int32_t *has_best) {
     __shared__ int32_t s_win[16];
-    const int32_t ns = sol_off[C];
+    const int32_t ns = sol_off[*count];
+    if (ns == 0) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int32_t win = -1;   // index into sol_list
     for (int32_t k = wave; k < ns; k += 16) {

@@ -467,9 +467,14 @@ DEV bool listed_after(const Launch &L, const NetDesc &N, const Ctrl &C, int k) {
     return L.push_ratio > 0 && N.rpos && C.arcs[(k + 2) % 3] * L.push_ratio <= 4 * N.arcs;
 }
 
-DEV int prob_of_var(const Launch &L, int64_t v) {
-    if (L.uniform_n > 0) return (int)(v / L.uniform_n);
-    int lo = 0, hi = L.nprob - 1;   // largest p with prob_off[p] <= v
+// Number of problems of a launch (Launch::nprob_dev, else nprob).
+DEV int32_t problem_count(const Launch &L) { return L.nprob_dev ? *L.nprob_dev : L.nprob; }
+
+DEV int prob_of_var(const Launch &L, int32_t nprob, int64_t v) {
+    if (L.uniform_n > 0)   // 32-bit division whenever the index fits (the 64-bit one is long)
+        return v <= 0x7FFFFFFF ? (int)((uint32_t)v / (uint32_t)L.uniform_n)
+                               : (int)(v / L.uniform_n);
+    int lo = 0, hi = nprob - 1;   // largest p with prob_off[p] <= v
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (L.prob_off[mid] <= v) lo = mid; else hi = mid - 1;
@@ -481,9 +486,42 @@ DEV int prob_of_var(const Launch &L, int64_t v) {
 // item counts. One workgroup of 1024 threads; a pass gives each thread up to
 // kPlanPer consecutive problems, whose loads are all issued before any is
 // used (clamped indices), so that a pass costs about one memory latency.
-constexpr int kPlanPer = 8;
+constexpr int kPlanPer = 4;
+
+// Plan of problems pt .. pt+per-1 (per <= R) of one thread: item counts,
+// and bit i of on_m / push_m for problem pt+i.
+template <int R>
+DEV void plan_problems(const Launch &L, int k, int32_t nprob, int32_t pt, int32_t per,
+                       int64_t *items, uint32_t &on_m, uint32_t &push_m, int64_t &tot) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int32_t p = pt + i;
+        const bool valid = i < per && p < nprob;
+        const int32_t pc = valid ? p : nprob - 1;
+        const NetDesc &N = L.nets[L.prob_net[pc]];
+        const Ctrl &C = L.ws.ctrl[pc];
+        const bool on = valid && active(L, N, C, k);
+        // few arcs to re-examine: the changed variables' pieces instead of a
+        // scan of every group (step 1 of an incremental start: the pieces of
+        // the listed @changed variables bound the arcs). Step k-1 listed its
+        // changed variables only if it was itself sparse.
+        bool push = false;
+        if (L.push_ratio > 0 && N.rpos) {
+            if (k > 1)
+                push = listed_after(L, N, C, k - 1) && C.arcs[(k - 1) % 3] * L.push_ratio <= N.arcs;
+            else if (L.changed0)
+                push = (int64_t)C.nchg[0] * N.pchunks * kWave * L.push_ratio <= N.arcs;
+        }
+        push = push && on;
+        items[i] = !on ? 0 : push ? (int64_t)C.nchg[(k - 1) & 1] * N.pchunks : N.nitems;
+        on_m |= (uint32_t)on << i;
+        push_m |= (uint32_t)push << i;
+        tot += items[i];
+    }
+}
 
 __global__ __launch_bounds__(1024) void plan_kernel(Launch L, int k) {
+    const int32_t nprob = problem_count(L);
     __shared__ int64_t s_wave[16];
     __shared__ int64_t s_base_items;
     __shared__ int32_t s_wave_n[16];
@@ -494,38 +532,20 @@ __global__ __launch_bounds__(1024) void plan_kernel(Launch L, int k) {
         s_base_n = 0;
     }
     __syncthreads();
-    for (int32_t p0 = 0; p0 < L.nprob; p0 += 1024 * kPlanPer) {
-        const int32_t left = L.nprob - p0;
+    for (int32_t p0 = 0; p0 < nprob; p0 += 1024 * kPlanPer) {
+        const int32_t left = nprob - p0;
         const int32_t per = left >= 1024 * kPlanPer ? kPlanPer : (left + 1023) / 1024;
         const int32_t pt = p0 + (int32_t)threadIdx.x * per;   // this thread's first problem
-        int64_t items[kPlanPer];
+        int64_t items[kPlanPer] = {};
         uint32_t on_m = 0, push_m = 0;
         int64_t tot = 0;
-#pragma unroll
-        for (int i = 0; i < kPlanPer; ++i) {
-            const int32_t p = pt + i;
-            const bool valid = i < per && p < L.nprob;
-            const int32_t pc = valid ? p : L.nprob - 1;
-            const NetDesc &N = L.nets[L.prob_net[pc]];
-            const Ctrl &C = L.ws.ctrl[pc];
-            const bool on = valid && active(L, N, C, k);
-            // few arcs to re-examine: the changed variables' pieces instead
-            // of a scan of every group (step 1 of an incremental start: the
-            // pieces of the listed @changed variables bound the arcs). Step
-            // k-1 listed its changed variables only if it was itself sparse.
-            bool push = false;
-            if (L.push_ratio > 0 && N.rpos) {
-                if (k > 1)
-                    push = listed_after(L, N, C, k - 1) &&
-                           C.arcs[(k - 1) % 3] * L.push_ratio <= N.arcs;
-                else if (L.changed0)
-                    push = (int64_t)C.nchg[0] * N.pchunks * kWave * L.push_ratio <= N.arcs;
-            }
-            push = push && on;
-            items[i] = !on ? 0 : push ? (int64_t)C.nchg[(k - 1) & 1] * N.pchunks : N.nitems;
-            on_m |= (uint32_t)on << i;
-            push_m |= (uint32_t)push << i;
-            tot += items[i];
+        if (pt < nprob) {   // waves past the last problem issue no loads
+            if (per == 1)
+                plan_problems<1>(L, k, nprob, pt, per, items, on_m, push_m, tot);
+            else if (per == 2)
+                plan_problems<2>(L, k, nprob, pt, per, items, on_m, push_m, tot);
+            else
+                plan_problems<kPlanPer>(L, k, nprob, pt, per, items, on_m, push_m, tot);
         }
         const int32_t cnt = __popc(on_m);
         // inclusive scans of the thread totals within the wave, then across waves
@@ -697,12 +717,13 @@ struct UpdRed {
 // step re-examines (arcs into changed variables) and the support checks of
 // step k (d*d per arc it re-examined).
 __global__ __launch_bounds__(256) void update_kernel(Launch L, int k) {
+    const int32_t nprob = problem_count(L);
     __shared__ UpdRed s_red;
     const int s_now = k % 3, s_prev = (k + 2) % 3, s_next = (k + 1) % 3;
-    const int64_t nv = L.prob_off[L.nprob];
+    const int64_t nv = L.prob_off[nprob];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (blockIdx.x == 0)
-        for (int32_t p = threadIdx.x; p < L.nprob; p += blockDim.x) {
+        for (int32_t p = threadIdx.x; p < nprob; p += blockDim.x) {
             L.ws.ctrl[p].arcs[s_next] = 0;
             L.ws.ctrl[p].nchg[(k + 1) & 1] = 0;   // the list step k+1 appends to
         }
@@ -711,13 +732,13 @@ __global__ __launch_bounds__(256) void update_kernel(Launch L, int k) {
          base += (int64_t)gridDim.x * blockDim.x) {
         const int64_t v = base + threadIdx.x;
         const int64_t vlast = base + blockDim.x - 1 < nv ? base + blockDim.x - 1 : nv - 1;
-        const int pb0 = prob_of_var(L, base), pb1 = prob_of_var(L, vlast);
+        const int pb0 = prob_of_var(L, nprob, base), pb1 = prob_of_var(L, nprob, vlast);
         bool ch = false, wp = false, lst = false;
         unsigned long long dg = 0;
         int p = -1;
         int32_t x = 0;
         if (v < nv) {
-            p = pb0 == pb1 ? pb0 : prob_of_var(L, v);
+            p = pb0 == pb1 ? pb0 : prob_of_var(L, nprob, v);
             const NetDesc &N = L.nets[L.prob_net[p]];
             Ctrl &C = L.ws.ctrl[p];
             if (active(L, N, C, k)) {
@@ -789,7 +810,8 @@ __global__ __launch_bounds__(256) void update_kernel(Launch L, int k) {
 }
 
 __global__ void init_kernel(Launch L) {
-    const int64_t nv = L.prob_off[L.nprob];
+    const int32_t nprob = problem_count(L);
+    const int64_t nv = L.prob_off[nprob];
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = tid; v < nv; v += nthreads) {
@@ -798,7 +820,7 @@ __global__ void init_kernel(Launch L) {
         L.ws.chg[0][v] = c ? 1u : 0u;
         L.ws.failacc[v] = 0;
     }
-    for (int64_t p = tid; p < L.nprob; p += nthreads) {
+    for (int64_t p = tid; p < nprob; p += nthreads) {
         const NetDesc &N = L.nets[L.prob_net[p]];
         Ctrl &C = L.ws.ctrl[p];
         // arcs step 1 re-examines (arcs1 < 0: summed by list_changed0_kernel)
@@ -818,7 +840,8 @@ __global__ void init_kernel(Launch L) {
 // changed-variable list of "step 0"), after init_kernel has zeroed the counts;
 // with arcs1 < 0 also each problem's arcs into them (sum of deg).
 __global__ void list_changed0_kernel(Launch L) {
-    const int64_t nv = L.prob_off[L.nprob];
+    const int32_t nprob = problem_count(L);
+    const int64_t nv = L.prob_off[nprob];
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     const int lane = threadIdx.x & 63;
@@ -826,7 +849,7 @@ __global__ void list_changed0_kernel(Launch L) {
         const int64_t v = base + lane;
         const bool c = v < nv && L.changed0[v];
         const int64_t vl = base + 63 < nv ? base + 63 : nv - 1;
-        const int p0 = prob_of_var(L, base), p1 = prob_of_var(L, vl);
+        const int p0 = prob_of_var(L, nprob, base), p1 = prob_of_var(L, nprob, vl);
         const uint64_t m = __ballot(c);
         if (!m) continue;
         if (p0 == p1) {   // one problem: one atomic for the wave
@@ -846,7 +869,7 @@ __global__ void list_changed0_kernel(Launch L) {
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         } else if (c) {
-            const int p = prob_of_var(L, v);
+            const int p = prob_of_var(L, nprob, v);
             const int32_t r = __hip_atomic_fetch_add(&L.ws.ctrl[p].nchg[0], 1, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT);
             L.ws.clist[0][L.prob_off[p] + r] = (int32_t)(v - L.prob_off[p]);
@@ -859,7 +882,8 @@ __global__ void list_changed0_kernel(Launch L) {
 }
 
 __global__ void finish_kernel(Launch L) {
-    const int64_t nv = L.prob_off[L.nprob];
+    const int32_t nprob = problem_count(L);
+    const int64_t nv = L.prob_off[nprob];
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     auto iters_of = [&](int p, int32_t *rc) {
@@ -878,12 +902,12 @@ __global__ void finish_kernel(Launch L) {
         return maxs;
     };
     for (int64_t v = tid; v < nv; v += nthreads) {
-        const int p = prob_of_var(L, v);
+        const int p = prob_of_var(L, nprob, v);
         int32_t rc;
         const int32_t it = iters_of(p, &rc);
         L.dout[v] = L.ws.dom[it & 1][v];
     }
-    for (int64_t p = tid; p < L.nprob; p += nthreads) {
+    for (int64_t p = tid; p < nprob; p += nthreads) {
         const Ctrl &C = L.ws.ctrl[p];
         int32_t rc;
         const int32_t it = iters_of((int)p, &rc);
