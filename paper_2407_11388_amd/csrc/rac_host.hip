@@ -1044,7 +1044,7 @@ static int run_states(rac_net *net, int32_t B, int32_t path, const uint8_t *d_ch
     Runner &r = net->run;
     Launch L = base_launch(r, B, net->opt);
     L.nets = pd.d_desc;
-    L.uniform_n = net->n;   // problem s at s*n
+    L.uniform_n = net->n;   // every problem an instance of this net, at s*n
     L.stage_vars = stage_vars_for(net->n);
     L.din = r.din;
     L.dout = r.dout;
@@ -1139,7 +1139,7 @@ static int run_mfma(rac_net *net, int32_t B, const uint64_t *d_in, uint64_t *d_o
         RAC_TRY(mfma_handoff(net->mfma, k, r.din, r.changed, s));
         Launch L = base_launch(r, P, net->opt);
         L.nets = pd.d_desc;
-        L.uniform_n = net->n;   // problem s at s*n
+        L.uniform_n = net->n;   // every problem an instance of this net, at s*n
         L.stage_vars = stage_vars_for(net->n);
         L.din = r.din;
         L.dout = r.dout;
@@ -1413,7 +1413,7 @@ extern "C" int rac_enforce_batch_device(rac_net *net, int32_t B, const uint64_t 
     Runner &r = net->run;
     Launch L = base_launch(r, B, net->opt);
     L.nets = pd.d_desc;
-    L.uniform_n = net->n;   // problem s at s*n
+    L.uniform_n = net->n;   // every problem an instance of this net, at s*n
     L.stage_vars = stage_vars_for(net->n);
     L.din = d_dom_in;
     L.dout = d_dom_out;

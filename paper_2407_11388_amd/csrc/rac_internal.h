@@ -114,8 +114,8 @@ struct Launch {
     int32_t *rc_out;          // [1]: 1 if some problem reached max_sweeps unconverged
     int32_t push_ratio;       // steps k >= 2 of a bit-row problem that re-examine at most
                               // arcs / push_ratio arcs go variable by variable (0: never)
-    int32_t uniform_n;        // > 0: every problem has uniform_n variables, prob_off[p] =
-                              // p * uniform_n (else 0)
+    int32_t uniform_n;        // > 0: every problem is an instance of nets[0] with uniform_n
+                              // variables, prob_off[p] = p * uniform_n (else 0)
     const int32_t *nprob_dev; // non-null: the number of problems is *nprob_dev (<= nprob),
                               // read on the device when each kernel starts, so that one
                               // captured graph serves calls with different counts

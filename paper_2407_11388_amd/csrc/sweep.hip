@@ -467,6 +467,12 @@ DEV bool listed_after(const Launch &L, const NetDesc &N, const Ctrl &C, int k) {
     return L.push_ratio > 0 && N.rpos && C.arcs[(k + 2) % 3] * L.push_ratio <= 4 * N.arcs;
 }
 
+// Network of problem p: with uniform_n set, every problem is an instance of
+// nets[0] (no table load).
+DEV const NetDesc &net_of(const Launch &L, int32_t p) {
+    return L.uniform_n > 0 ? L.nets[0] : L.nets[L.prob_net[p]];
+}
+
 // Number of problems of a launch (Launch::nprob_dev, else nprob).
 DEV int32_t problem_count(const Launch &L) { return L.nprob_dev ? *L.nprob_dev : L.nprob; }
 
@@ -498,7 +504,7 @@ DEV void plan_problems(const Launch &L, int k, int32_t nprob, int32_t pt, int32_
         const int32_t p = pt + i;
         const bool valid = i < per && p < nprob;
         const int32_t pc = valid ? p : nprob - 1;
-        const NetDesc &N = L.nets[L.prob_net[pc]];
+        const NetDesc &N = net_of(L, pc);
         const Ctrl &C = L.ws.ctrl[pc];
         const bool on = valid && active(L, N, C, k);
         // few arcs to re-examine: the changed variables' pieces instead of a
@@ -665,7 +671,7 @@ __global__ __launch_bounds__(kWave) void revise_kernel(Launch L, int k) {
     for (int64_t c = c0; c < c1; ++c) {
         while (L.ws.act_off[a + 1] <= c) ++a;
         const int32_t p = L.ws.act[a];
-        const NetDesc &N = L.nets[L.prob_net[p]];
+        const NetDesc &N = net_of(L, p);
         const int64_t off = L.prob_off[p];
         const int32_t ci = (int32_t)(c - L.ws.act_off[a]);
         if (L.ws.act_push[a]) {
@@ -739,7 +745,7 @@ __global__ __launch_bounds__(256) void update_kernel(Launch L, int k) {
         int32_t x = 0;
         if (v < nv) {
             p = pb0 == pb1 ? pb0 : prob_of_var(L, nprob, v);
-            const NetDesc &N = L.nets[L.prob_net[p]];
+            const NetDesc &N = net_of(L, p);
             Ctrl &C = L.ws.ctrl[p];
             if (active(L, N, C, k)) {
                 const uint64_t dx = L.ws.dom[(k - 1) & 1][v];
@@ -821,7 +827,7 @@ __global__ void init_kernel(Launch L) {
         L.ws.failacc[v] = 0;
     }
     for (int64_t p = tid; p < nprob; p += nthreads) {
-        const NetDesc &N = L.nets[L.prob_net[p]];
+        const NetDesc &N = net_of(L, p);
         Ctrl &C = L.ws.ctrl[p];
         // arcs step 1 re-examines (arcs1 < 0: summed by list_changed0_kernel)
         C.arcs[0] = L.changed0 ? (L.arcs1 < 0 ? 0 : L.arcs1) : N.arcs;
@@ -861,7 +867,7 @@ __global__ void list_changed0_kernel(Launch L) {
             at = __shfl(at, leader, 64);
             if (c) L.ws.clist[0][L.prob_off[p0] + at + lane_rank(m)] = (int32_t)(v - L.prob_off[p0]);
             if (L.arcs1 < 0) {
-                const NetDesc &N = L.nets[L.prob_net[p0]];
+                const NetDesc &N = net_of(L, p0);
                 const unsigned long long dg =
                     wave_sum64(c ? (unsigned long long)N.deg[v - L.prob_off[p0]] : 0ull);
                 if (lane == leader)
@@ -875,7 +881,7 @@ __global__ void list_changed0_kernel(Launch L) {
             L.ws.clist[0][L.prob_off[p] + r] = (int32_t)(v - L.prob_off[p]);
             if (L.arcs1 < 0)
                 (void)__hip_atomic_fetch_add(&L.ws.ctrl[p].arcs[0],
-                                             (long long)L.nets[L.prob_net[p]].deg[v - L.prob_off[p]],
+                                             (long long)net_of(L, p).deg[v - L.prob_off[p]],
                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
@@ -887,7 +893,7 @@ __global__ void finish_kernel(Launch L) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     auto iters_of = [&](int p, int32_t *rc) {
-        const NetDesc &N = L.nets[L.prob_net[p]];
+        const NetDesc &N = net_of(L, p);
         const Ctrl &C = L.ws.ctrl[p];
         const int32_t maxs = max_steps(L, N);
         if (L.mode == RAC_STOP_ON_WIPEOUT && C.wipe_step != 0) {

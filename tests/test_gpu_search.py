@@ -107,3 +107,33 @@ def test_limits():
     res, _ = net.search(full_masks(8, 8), max_nodes=50, batch=4)
     assert res.nodes >= 50 and res.complete == 0
     net.close()
+
+
+def test_repeated_searches_on_one_net():
+    # Consecutive searches with one batch size launch the step kernels with
+    # the same arguments and replay the same captured step graphs; a single
+    # enforcement in between rebuilds them. Every search is checked against
+    # the oracle.
+    n = 8
+    edges, rel = queens(n)
+    net = rac.Net.from_u8(n, n, edges, rel)
+    full = full_masks(n, n)
+    roots = [full, full.copy(), full.copy(), full.copy()]
+    roots[1][0] = 0b00001111          # x0 in {0..3}
+    roots[2][3] = (1 << 2) | (1 << 5)  # x3 in {2, 5}
+    roots[3][7] = 1 << 6               # x7 = 6
+    for rep in range(2):
+        for i, root in enumerate(roots):
+            say(f"[gpu] repeated search rep={rep} root={i}")
+            exp = mac_search(n, n, edges, rel, masks_to_u8(root, n))
+            res, sol = net.search(root, batch=64)
+            assert (res.solutions, res.nodes, res.failures, res.sweeps) == \
+                (exp["solutions"], exp["nodes"], exp["failures"], exp["steps"]), (rep, i)
+            if exp["best"] is None:
+                assert sol is None
+            else:
+                assert [int(v).bit_length() - 1 for v in sol] == exp["best"].tolist()
+        say(f"[gpu] enforce between searches rep={rep}")
+        dom, iters, status = net.enforce(full)
+        assert status == 0 and (dom == full).all()
+    net.close()
