@@ -488,20 +488,23 @@ DEV int prob_of_var(const Launch &L, int32_t nprob, int64_t v) {
     return lo;
 }
 
-// The problems that execute step k, in order, with the prefix sums of their
-// item counts. One workgroup of 1024 threads; a pass gives each thread up to
-// kPlanPer consecutive problems, whose loads are all issued before any is
-// used (clamped indices), so that a pass costs about one memory latency.
+// The problems that execute step k, with the prefix sums of their item
+// counts. One workgroup of 1024 threads; a pass gives thread t up to
+// kPlanPer problems t, t + 1024, ... (a wave's loads read consecutive
+// problems), whose loads are all issued before any is used (clamped
+// indices), so that a pass costs about one memory latency. A thread's
+// active problems are listed together, so the list is not in problem order;
+// the revise kernel finds items only through the prefix sums.
 constexpr int kPlanPer = 4;
 
-// Plan of problems pt .. pt+per-1 (per <= R) of one thread: item counts,
-// and bit i of on_m / push_m for problem pt+i.
+// Plan of problems pt + i * 1024, i < per <= R, of one thread: item counts,
+// and bit i of on_m / push_m for problem pt + i * 1024.
 template <int R>
 DEV void plan_problems(const Launch &L, int k, int32_t nprob, int32_t pt, int32_t per,
                        int64_t *items, uint32_t &on_m, uint32_t &push_m, int64_t &tot) {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        const int32_t p = pt + i;
+        const int32_t p = pt + i * 1024;
         const bool valid = i < per && p < nprob;
         const int32_t pc = valid ? p : nprob - 1;
         const NetDesc &N = net_of(L, pc);
@@ -541,7 +544,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(Launch L, int k) {
     for (int32_t p0 = 0; p0 < nprob; p0 += 1024 * kPlanPer) {
         const int32_t left = nprob - p0;
         const int32_t per = left >= 1024 * kPlanPer ? kPlanPer : (left + 1023) / 1024;
-        const int32_t pt = p0 + (int32_t)threadIdx.x * per;   // this thread's first problem
+        const int32_t pt = p0 + (int32_t)threadIdx.x;   // this thread's first problem
         int64_t items[kPlanPer] = {};
         uint32_t on_m = 0, push_m = 0;
         int64_t tot = 0;
@@ -580,7 +583,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(Launch L, int k) {
 #pragma unroll
         for (int i = 0; i < kPlanPer; ++i)
             if ((on_m >> i) & 1u) {
-                L.ws.act[nbefore] = pt + i;
+                L.ws.act[nbefore] = pt + i * 1024;
                 L.ws.act_off[nbefore] = before;
                 L.ws.act_push[nbefore] = (int32_t)((push_m >> i) & 1u);
                 before += items[i];
