@@ -310,9 +310,16 @@ def cpu_baseline_single(inst, dom, budget_s):
                 host=host_cpu())
 
 
+# Open nodes per search round in the bench lines: a sweep (512 .. 8192) on
+# both search workloads gains up to 4096 (fewer rounds of the same tree) and
+# little beyond.
+SEARCH_BATCH = 4096
+
+
 def search_lines():
     """Batched MAC search (Algorithm 2) on two instances: every child of up to
-    1024 open nodes enforced together per round, against one node per round."""
+    SEARCH_BATCH open nodes enforced together per round, against one node per
+    round."""
     import numpy as np
 
     from paper_2407_11388_amd import gen, rac
@@ -326,15 +333,16 @@ def search_lines():
         net = rac.Net.from_u8(n, d, edges, rel)
         root = np.full(n, (1 << d) - 1, dtype=np.uint64)
         line = {}
-        for b in (1024, 1):
+        for b in (SEARCH_BATCH, 1):
             net.search(root, batch=b, max_nodes=2000 if b == 1 else 0)   # warm-up
-            res, _ = net.search(root, batch=b, max_nodes=0 if b == 1024 else 20000)
+            res, _ = net.search(root, batch=b, max_nodes=0 if b == SEARCH_BATCH else 20000)
             line[f"batch{b}"] = dict(nodes=int(res.nodes), solutions=int(res.solutions),
                                      failures=int(res.failures), complete=int(res.complete),
                                      rounds=int(res.rounds), ms=res.search_ms,
                                      steps_per_node=res.sweeps / res.nodes,
                                      nodes_per_s=res.nodes / (res.search_ms * 1e-3))
-        line["batched_vs_one_node"] = line["batch1024"]["nodes_per_s"] / line["batch1"]["nodes_per_s"]
+        line["batched_vs_one_node"] = (line[f"batch{SEARCH_BATCH}"]["nodes_per_s"]
+                                       / line["batch1"]["nodes_per_s"])
         out[name] = line
         net.close()
     return out
@@ -343,7 +351,7 @@ def search_lines():
 def table1_grid(oracle_nodes: int = 100, gpu_nodes: int = 20000):
     """Table 1 analogue: MAC search on model-B instances over n x density
     (d = 10, p2 = 0.3; the paper's own instances and heuristic are not
-    published). Per grid point: the GPU search (batch 1024, up to `gpu_nodes`
+    published). Per grid point: the GPU search (batch SEARCH_BATCH, up to `gpu_nodes`
     nodes): recurrence steps per enforcement and time per node; the oracle's
     search on its first `oracle_nodes` nodes (depth-first): recurrence steps
     and AC-3 revisions per enforcement."""
@@ -359,8 +367,8 @@ def table1_grid(oracle_nodes: int = 100, gpu_nodes: int = 20000):
             rel = inst.rel_u8()
             net = rac.Net.from_u8(n, d, inst.edges, rel)
             root = np.full(n, (1 << d) - 1, dtype=np.uint64)
-            net.search(root, batch=1024, max_nodes=2000)   # warm-up
-            res, _ = net.search(root, batch=1024, max_nodes=gpu_nodes)
+            net.search(root, batch=SEARCH_BATCH, max_nodes=2000)   # warm-up
+            res, _ = net.search(root, batch=SEARCH_BATCH, max_nodes=gpu_nodes)
             net.close()
             t0 = time.perf_counter()
             o = osearch.mac_search(n, d, inst.edges, rel, np.ones((n, d), np.uint8),
