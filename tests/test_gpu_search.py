@@ -137,3 +137,29 @@ def test_repeated_searches_on_one_net():
         dom, iters, status = net.enforce(full)
         assert status == 0 and (dom == full).all()
     net.close()
+
+
+@pytest.mark.parametrize("which", ["queens11", "modelB-n100"])
+def test_bench_search_workloads(which):
+    # The two search workloads of the bench at its batch (4096 open nodes per
+    # round), in full against the oracle's search (about 2 s and 30 s of CPU).
+    if which == "queens11":
+        n, d = 11, 11
+        edges, rel = queens(11)
+    else:
+        n, d = 100, 10
+        inst = gen.model_b(110, 100, 10, 0.1, 0.4)
+        edges, rel = inst.edges, inst.rel_u8()
+    say(f"[gpu] bench search workload {which}: oracle")
+    exp = mac_search(n, d, edges, rel, np.ones((n, d), np.uint8))
+    net = rac.Net.from_u8(n, d, edges, rel)
+    say(f"[gpu] bench search workload {which}: batch 4096")
+    res, sol = net.search(full_masks(n, d), batch=4096)
+    assert res.complete == 1
+    assert (res.solutions, res.nodes, res.failures, res.sweeps) == \
+        (exp["solutions"], exp["nodes"], exp["failures"], exp["steps"])
+    if exp["best"] is None:
+        assert sol is None
+    else:
+        assert [int(v).bit_length() - 1 for v in sol] == exp["best"].tolist()
+    net.close()
