@@ -192,6 +192,8 @@ def parse():
     ap.add_argument("--table1", action="store_true",
                     help="only run the Table 1-style MAC-search grid (steps and AC-3 revisions "
                          "per assignment, time per node) and print it as one JSON line")
+    ap.add_argument("--search-only", action="store_true",
+                    help="run only the two batched MAC searches (one JSON line)")
     ap.add_argument("--no-search", action="store_true",
                     help="skip the MAC-search lines in the secondary results")
     ap.add_argument("--no-uneven", action="store_true",
@@ -316,10 +318,10 @@ def cpu_baseline_single(inst, dom, budget_s):
 SEARCH_BATCH = 4096
 
 
-def search_lines():
+def search_lines(one_node: bool = True):
     """Batched MAC search (Algorithm 2) on two instances: every child of up to
     SEARCH_BATCH open nodes enforced together per round, against one node per
-    round."""
+    round (one_node)."""
     import numpy as np
 
     from paper_2407_11388_amd import gen, rac
@@ -333,7 +335,7 @@ def search_lines():
         net = rac.Net.from_u8(n, d, edges, rel)
         root = np.full(n, (1 << d) - 1, dtype=np.uint64)
         line = {}
-        for b in (SEARCH_BATCH, 1):
+        for b in (SEARCH_BATCH, 1) if one_node else (SEARCH_BATCH,):
             net.search(root, batch=b, max_nodes=2000 if b == 1 else 0)   # warm-up
             res, _ = net.search(root, batch=b, max_nodes=0 if b == SEARCH_BATCH else 20000)
             line[f"batch{b}"] = dict(nodes=int(res.nodes), solutions=int(res.solutions),
@@ -341,8 +343,9 @@ def search_lines():
                                      rounds=int(res.rounds), ms=res.search_ms,
                                      steps_per_node=res.sweeps / res.nodes,
                                      nodes_per_s=res.nodes / (res.search_ms * 1e-3))
-        line["batched_vs_one_node"] = (line[f"batch{SEARCH_BATCH}"]["nodes_per_s"]
-                                       / line["batch1"]["nodes_per_s"])
+        if one_node:
+            line["batched_vs_one_node"] = (line[f"batch{SEARCH_BATCH}"]["nodes_per_s"]
+                                           / line["batch1"]["nodes_per_s"])
         out[name] = line
         net.close()
     return out
@@ -409,6 +412,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.table1:
         print(json.dumps(dict(table1=table1_grid())), flush=True)
+        return
+    if args.search_only:
+        print(json.dumps(dict(search=search_lines(one_node=False))), flush=True)
         return
     if args.copy_calibration > 0:
         src = torch.ones(args.copy_calibration, dtype=torch.uint8, device=dev)
