@@ -398,8 +398,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the batched "
-              "states and instances shard across GPUs without communication, but this "
-              "build runs and reports a single MI355X.", file=sys.stderr)
+              "states and instances would shard across GPUs without communication, but the "
+              "benchmark runs on, and reports, a single MI355X.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
