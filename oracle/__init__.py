@@ -24,7 +24,11 @@ solution counts.
 Pins (see ``tests/test_oracle.py``): brute force on tiny instances, the closed
 forms of chains / cliques / empty and universal relations, hand-worked golden
 cases under ``tests/golden/``, and the invariants of Lemma 1, Proposition 1
-and Proposition 2. No function here is "parity unpinned".
+and Proposition 2. AC-3's revision and look-up counters are pinned by the
+hand-counted values in every golden fixture and by their closed form for
+universal relations; ``is_ac`` by the definition evaluated by brute force (a
+set is arc consistent iff it equals its own closure) and by rejecting D_ac
+plus any value it lacks. No function here is "parity unpinned".
 """
 from __future__ import annotations
 

@@ -52,16 +52,31 @@ static int arc_allows(const uint8_t *rel, int32_t d, const arc_t *r, int32_t a, 
     return r->flip ? R[(size_t)b * d + a] : R[(size_t)a * d + b];
 }
 
-/* Builds both arcs of every constraint; returns NULL on bad input. */
+static int cmp_i64(const void *p, const void *q) {
+    const int64_t a = *(const int64_t *)p, b = *(const int64_t *)q;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+/* Builds both arcs of every constraint: arc 2e is x->y and arc 2e+1 is y->x,
+ * so the reverse of arc i is arc i^1. Returns NULL on bad input: a variable
+ * out of range, a self-loop, or two constraints on one unordered pair (the
+ * CSP of Section 2 has at most one constraint c_xy per pair, and Alg. 2's
+ * Cons tensor holds one relation block per ordered pair). */
 static arc_t *build_arcs(int32_t n, int64_t m, const int32_t *edges) {
     arc_t *arcs = (arc_t *)malloc(sizeof(arc_t) * (size_t)(2 * m + 1));
-    if (!arcs) return NULL;
+    int64_t *keys = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
+    if (!arcs || !keys) { free(arcs); free(keys); return NULL; }
     for (int64_t e = 0; e < m; ++e) {
         int32_t x = edges[2 * e], y = edges[2 * e + 1];
-        if (x < 0 || y < 0 || x >= n || y >= n || x == y) { free(arcs); return NULL; }
+        if (x < 0 || y < 0 || x >= n || y >= n || x == y) { free(arcs); free(keys); return NULL; }
         arcs[2 * e] = (arc_t){x, y, e, 0};
         arcs[2 * e + 1] = (arc_t){y, x, e, 1};
+        keys[e] = (int64_t)(x < y ? x : y) * n + (x < y ? y : x);
     }
+    qsort(keys, (size_t)m, sizeof(int64_t), cmp_i64);
+    for (int64_t e = 1; e < m; ++e)
+        if (keys[e] == keys[e - 1]) { free(arcs); free(keys); return NULL; }
+    free(keys);
     return arcs;
 }
 
@@ -136,12 +151,13 @@ OR_API int oracle_ac3(int32_t n, int32_t d, int64_t m, const int32_t *edges,
             }
         }
         if (removed) {
-            /* every arc z->x may have lost a support; the arc from y itself
-             * cannot (a value of y supported only by a removed value a would
-             * need rel(a,b)=1 with b in dom(y), contradicting a's removal) */
+            /* every arc z->x may have lost a support; the reverse arc y->x of
+             * this same constraint (arc ai^1) cannot: a value b of y
+             * supported only by a removed value a would need rel(a,b)=1 with
+             * b in dom(y), contradicting a's removal */
             for (int64_t k = in_start[r->x]; k < in_start[r->x + 1]; ++k) {
                 int64_t zi = in_list[k];
-                if (arcs[zi].x == r->y || queued[zi]) continue;
+                if (zi == (ai ^ 1) || queued[zi]) continue;
                 queue[(head + count) % na] = zi;
                 queued[zi] = 1;
                 count++;

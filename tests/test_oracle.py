@@ -63,6 +63,31 @@ def test_golden_ac3(case):
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c["name"] for c in CASES])
+def test_golden_ac3_counters(case):
+    # revisions (arcs popped and revised: Table 1's #Revision) and relation
+    # look-ups, counted by hand for the FIFO order stated in each fixture
+    n, d, edges, rel, dom = golden_instance(case)
+    _, _, revisions, lookups = oracle.ac3(n, d, edges, rel, dom)
+    assert revisions == case["expect_ac3_revisions"]
+    assert lookups == case["expect_ac3_lookups"]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c["name"] for c in CASES])
+def test_golden_is_ac_rejects_each_removed_value(case):
+    # Section 3: D_ac is the largest arc-consistent subset of D, so D_ac plus
+    # any value of D it lacks is not arc consistent; D_ac itself is.
+    n, d, edges, rel, dom = golden_instance(case)
+    dac = value_lists_to_u8(case["expect_dac"], d)
+    assert oracle.is_ac(n, d, edges, rel, dac)
+    removed = np.argwhere(dom & (1 - dac))
+    for x, a in removed:
+        plus = dac.copy()
+        plus[x, a] = 1
+        assert not oracle.is_ac(n, d, edges, rel, plus), (x, a)
+    assert oracle.is_ac(n, d, edges, rel, dom) == (len(removed) == 0)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c["name"] for c in CASES])
 @pytest.mark.parametrize("incremental", [True, False])
 def test_golden_recurrence_steps(case, incremental):
     n, d, edges, rel, dom = golden_instance(case)
@@ -105,6 +130,53 @@ def test_ac3_and_recurrence_equal_brute_force(idx):
     sols = brute.solutions(n, d, edges, rel, dom)
     for s in sols:
         assert all(expect[x, s[x]] for x in range(n))
+
+
+@pytest.mark.parametrize("idx", range(0, len(TINY), 3))
+def test_is_ac_equals_definition_by_brute_force(idx):
+    # A set S is arc consistent iff it equals its own closure (the union of
+    # all arc-consistent subsets of S contains S exactly when S is one of
+    # them). Checked on D, on D_ac, on D_ac plus each value it lacks and on
+    # D_ac minus each value it holds.
+    n, d, edges, rel, dom = TINY[idx]
+    dac = brute.brute_dac(n, d, edges, rel, dom)
+    sets = [dom, dac]
+    for x, a in np.argwhere(dom):
+        s = dac.copy()
+        s[x, a] = 1 - s[x, a]
+        sets.append(s)
+    for s in sets:
+        expect = np.array_equal(brute.brute_dac(n, d, edges, rel, s), s)
+        assert oracle.is_ac(n, d, edges, rel, s) == expect
+
+
+def test_oracle_rejects_duplicate_constraints():
+    # Section 2: at most one constraint per pair of variables; (x,y) and then
+    # (y,x) is the same pair.
+    d = 3
+    rel = np.ones((2, d, d), np.uint8)
+    dom = np.ones((3, d), np.uint8)
+    for edges in (np.array([[0, 1], [0, 1]], np.int32), np.array([[0, 1], [1, 0]], np.int32),
+                  np.array([[2, 2], [0, 1]], np.int32)):
+        with pytest.raises(ValueError):
+            oracle.ac3(3, d, edges, rel, dom)
+        with pytest.raises(ValueError):
+            oracle.rac_sync(3, d, edges, rel, dom)
+        with pytest.raises(ValueError):
+            oracle.is_ac(3, d, edges, rel, dom)
+
+
+def test_ac3_counters_closed_form_universal_relations():
+    # Nothing is removed when every pair is allowed: each arc is popped once
+    # (2m revisions) and each value of x finds its support at the first value
+    # of dom(y) tried (|dom(x)| look-ups per arc x->y).
+    inst = gen.model_b(21, 25, 5, 0.6, 0.0)
+    dom = masks_to_u8(gen.preremove(22, 25, 5, 30), 5)
+    dom[dom.sum(axis=1) == 0, 2] = 1
+    _, status, revisions, lookups = oracle.ac3(25, 5, inst.edges, inst.rel_u8(), dom)
+    size = dom.sum(axis=1)
+    assert status == 0 and revisions == 2 * inst.m
+    assert lookups == int(sum(size[x] + size[y] for x, y in inst.edges))
 
 
 def test_brute_force_catches_transposed_relation():
