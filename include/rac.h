@@ -63,7 +63,9 @@ enum {
     RAC_EUNSUPPORTED = -4,    /* valid input outside what a path supports */
     RAC_ENOTCONVERGED = -5,   /* max_sweeps reached while values were still being removed */
     RAC_ENODEV = -6,          /* no usable gfx950 device */
-    RAC_ETIMEOUT = -7         /* reserved (no current code path returns it) */
+    RAC_ETIMEOUT = -7         /* the batched matrix-core path ended with a state that had
+                                 neither stopped nor been handed to the bit-row path (an
+                                 internal failure: no valid input produces it) */
 };
 
 enum { RAC_CONSISTENT = 0, RAC_WIPEOUT = 1 };
@@ -160,16 +162,19 @@ int rac_enforce_batch(rac_net *net, int32_t B, uint64_t *dom, int32_t *iters, in
  * Device-pointer form of rac_enforce_batch: d_dom_in [B][n] and d_dom_out
  * [B][n] uint64 (may be the same buffer), d_iters and d_status [B] int32, all
  * in device memory of the net's device; enqueued on `stream` (a hipStream_t,
- * NULL = the null stream). The call waits on the stream between rounds of
- * steps (to read how many states are still running) and returns once the
- * last kernels are enqueued; per-call errors detected on the device
- * (max_sweeps reached) are reported by the next call or by rac_sync_status().
+ * NULL = the null stream). The host may wait on the stream while the call
+ * runs (between rounds of steps, to read how many states are still running);
+ * the call returns once the last kernels are enqueued. Errors detected on the
+ * device (max_sweeps reached) are reported by rac_sync_status(), or by the
+ * next call on the net: every other entry point on the net first waits for a
+ * device-pointer call still in flight, since it shares the net's workspace.
  */
 int rac_enforce_batch_device(rac_net *net, int32_t B, const uint64_t *d_dom_in,
                              uint64_t *d_dom_out, int32_t *d_iters, int32_t *d_status,
                              void *stream);
 
-/* Waits for the net's last device-pointer call and returns its error code. */
+/* Waits for the net's last device-pointer call (the end of its work on the
+ * caller's stream, not the whole device) and returns its error code. */
 int rac_sync_status(rac_net *net);
 
 /*
@@ -183,10 +188,11 @@ int rac_enforce_multi(int32_t k, rac_net *const *nets, uint64_t *const *dom, int
                       int32_t *status);
 
 /*
- * A group fixes a list of nets once (device descriptor tables, work items,
- * the autotuned choice per net and a captured graph), so repeated calls
- * avoid that set-up. rac_group_enforce has the semantics of
- * rac_enforce_multi. The nets must outlive the group.
+ * A group fixes a list of nets once (device descriptor tables, its own work
+ * items, the autotuned choice per net and a captured graph), so repeated
+ * calls avoid that set-up. rac_group_enforce has the semantics of
+ * rac_enforce_multi. The nets must outlive the group; calls on the member
+ * nets themselves stay valid and do not affect the group.
  */
 int rac_group_create(int32_t k, rac_net *const *nets, const rac_options *opt, rac_group **out);
 int rac_group_enforce(rac_group *g, uint64_t *const *dom, int32_t *iters, int32_t *status);

@@ -52,7 +52,7 @@ extern "C" const char *rac_strerror(int code) {
     case RAC_EUNSUPPORTED: return "unsupported by the selected path";
     case RAC_ENOTCONVERGED: return "max_sweeps reached before the fixpoint";
     case RAC_ENODEV: return "no usable gfx950 device";
-    case RAC_ETIMEOUT: return "device scheduler wait expired";
+    case RAC_ETIMEOUT: return "a batched state did not finish on the matrix-core path";
     default: return "unknown error";
     }
 }
@@ -237,8 +237,7 @@ struct rac_net {
     int32_t mf_cap = 0;
     Runner run;
     rac_stats last{};
-    int pending_rc = RAC_OK;   // device-pointer call awaiting rac_sync_status
-    bool pending = false;
+    bool pending = false;      // a device-pointer call awaiting rac_sync_status
 };
 
 struct rac_group {
@@ -248,6 +247,8 @@ struct rac_group {
     int device = 0;
     hipStream_t stream = nullptr;
     NetDesc *d_nets = nullptr;
+    int4 *items = nullptr;       // the group's own work-item tables of every net, back to back
+    int32_t *pieces = nullptr;
     std::vector<int64_t> h_off;
     Runner run;
     rac_stats last{};
@@ -382,9 +383,16 @@ static void release_path(PathData &pd) {
     pd.nitems = 0;
 }
 
+// A device-pointer call still in flight on a net (or group) uses the net's
+// workspace on the caller's stream: every call that touches that workspace
+// waits for it first, and its device-side error code is reported then.
+static int settle(rac_net *net) { return net->pending ? rac_sync_status(net) : RAC_OK; }
+static int settle(rac_group *g) { return g->pending ? rac_group_sync_status(g) : RAC_OK; }
+
 extern "C" void rac_destroy(rac_net *net) {
     if (!net) return;
     (void)hipSetDevice(net->device);
+    (void)settle(net);
     if (net->stream) (void)hipStreamSynchronize(net->stream);
     release_runner(net->run);
     release_path(net->bits);
@@ -417,14 +425,16 @@ static int current_device(int *dev) {
     return device_info(*dev, &di);
 }
 
-// Work items over the arcs of one path: runs of whole variables up to about
-// `target` relation bytes, and variables above that split into pieces.
-static int make_items(rac_net *net, PathData &pd, int32_t target) {
+// Work items over the arcs of one path (host tables): runs of whole variables
+// up to about `target` relation bytes, and variables above that split into
+// pieces.
+static void build_items(const rac_net *net, const PathData &pd, int32_t target,
+                        std::vector<int4> &items, std::vector<int32_t> &pieces) {
     // units: 64-arc groups for bit rows, single arcs for int8 rows
     const bool groups = pd.kind != ROWI8;
     const int64_t unit_bytes = groups ? (int64_t)pd.desc.qpa * 1024 : (int64_t)net->d * pd.dp;
-    std::vector<int4> items;
-    std::vector<int32_t> pieces;
+    items.clear();
+    pieces.clear();
     const int32_t n = net->n;
     const std::vector<int32_t> &rp = groups ? net->h_gptr : net->h_row_ptr;
     const int64_t per_var = 64;   // accounts for the domain read/write of a variable
@@ -460,6 +470,15 @@ static int make_items(rac_net *net, PathData &pd, int32_t target) {
         acc += bx;
     }
     flush(n);
+}
+
+// The net's own item tables for one path (used by calls on the net itself;
+// groups build their own copies, so that a later rebuild here never leaves a
+// group with freed tables).
+static int make_items(rac_net *net, PathData &pd, int32_t target) {
+    std::vector<int4> items;
+    std::vector<int32_t> pieces;
+    build_items(net, pd, target, items, pieces);
     dfree(pd.items);
     dfree(pd.pieces);
     RAC_TRY(dalloc(&pd.items, items.size()));
@@ -1084,6 +1103,7 @@ extern "C" int rac_enforce(rac_net *net, uint64_t *dom, const int32_t *changed, 
     if (changed && n_changed < 0) return set_error(RAC_EINVAL, "n_changed < 0");
     RAC_TRY(check_domains(dom, net->n, net->d));
     HIP_TRY(hipSetDevice(net->device));
+    RAC_TRY(settle(net));
     int32_t path = net->opt.path;
     if (path == RAC_PATH_AUTO || path == RAC_PATH_MFMA) path = RAC_PATH_BITS;
     RAC_TRY(ensure_path(net, path, call_target(net, 1)));
@@ -1204,6 +1224,7 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
     if (n >= (1 << 20)) return set_error(RAC_EUNSUPPORTED, "search supports n < 2^20");
     RAC_TRY(check_domains(dom, n, d));
     HIP_TRY(hipSetDevice(net->device));
+    RAC_TRY(settle(net));
     const auto t0 = std::chrono::steady_clock::now();
     memset(out, 0, sizeof(*out));
     if (batch == 0) batch = 256;
@@ -1353,6 +1374,7 @@ extern "C" int rac_enforce_batch(rac_net *net, int32_t B, uint64_t *dom, int32_t
     if (B == 0) return RAC_OK;
     RAC_TRY(check_domains(dom, (int64_t)B * net->n, net->d));
     HIP_TRY(hipSetDevice(net->device));
+    RAC_TRY(settle(net));
     const int32_t path = pick_path(net, B, net->opt.path);
     if (path == RAC_PATH_MFMA) {
         if (B > net->mf_cap) {
@@ -1395,10 +1417,7 @@ extern "C" int rac_enforce_batch_device(rac_net *net, int32_t B, const uint64_t 
     if (B == 0) return RAC_OK;
     if (!d_dom_in || !d_dom_out) return set_error(RAC_EINVAL, "domain pointers are NULL");
     HIP_TRY(hipSetDevice(net->device));
-    if (net->pending) {
-        const int prc = rac_sync_status(net);
-        if (prc != RAC_OK) return prc;
-    }
+    RAC_TRY(settle(net));
     hipStream_t s = (hipStream_t)stream;
     const int32_t path = pick_path(net, B, net->opt.path);
     if (path == RAC_PATH_MFMA) {
@@ -1436,7 +1455,7 @@ extern "C" int rac_sync_status(rac_net *net) {
     net->pending = false;
     if (net->last.path == RAC_PATH_MFMA) return mfma_collect(net->mfma, &net->last);
     int32_t hrc = 0;
-    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipEventSynchronize(net->run.ev1));   // the end of the call on the caller's stream
     HIP_TRY(hipMemcpy(&hrc, net->run.rc, 4, hipMemcpyDeviceToHost));
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, net->run.ev0, net->run.ev1);
@@ -1458,9 +1477,12 @@ extern "C" int rac_net_stats(const rac_net *net, rac_stats *out) {
 extern "C" void rac_group_destroy(rac_group *g) {
     if (!g) return;
     (void)hipSetDevice(g->device);
+    (void)settle(g);
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     release_runner(g->run);
     dfree(g->d_nets);
+    dfree(g->items);
+    dfree(g->pieces);
     if (g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
 }
@@ -1480,6 +1502,8 @@ extern "C" int rac_group_create(int32_t k, rac_net *const *nets, const rac_optio
         if (nets[i]->device != nets[0]->device)
             return set_error(RAC_EINVAL, "nets of one group must share a device");
     }
+    HIP_TRY(hipSetDevice(nets[0]->device));
+    for (int32_t i = 0; i < k; ++i) RAC_TRY(settle(nets[i]));
     rac_group *g = new rac_group();
     g->k = k;
     g->nets.assign(nets, nets + k);
@@ -1506,19 +1530,38 @@ extern "C" int rac_group_create(int32_t k, rac_net *const *nets, const rac_optio
             total_bytes += (int64_t)(path == RAC_PATH_INT8 ? net->i8 : net->bits).rows_bytes;
         }
         if (rc) break;
-        // one item size for the whole group, from the group's total work
+        // one item size for the whole group, from the group's total work; the
+        // item tables are the group's own (the nets' tables may be rebuilt by
+        // calls on the nets themselves)
         const int32_t target = o.item_bytes > 0 ? o.item_bytes : default_item_bytes(g->device, total_bytes);
+        std::vector<int4> all_items, its;
+        std::vector<int32_t> all_pieces, pcs;
+        std::vector<size_t> item_off((size_t)k + 1, 0);
         for (int32_t i = 0; i < k; ++i) {
             rac_net *net = nets[i];
-            if ((rc = ensure_path(net, paths[(size_t)i], target))) break;
             PathData &pd = paths[(size_t)i] == RAC_PATH_INT8 ? net->i8 : net->bits;
+            build_items(net, pd, target, its, pcs);
+            all_items.insert(all_items.end(), its.begin(), its.end());
+            all_pieces.insert(all_pieces.end(), pcs.begin(), pcs.end());
+            item_off[(size_t)i + 1] = all_items.size();
             descs[(size_t)i] = pd.desc;
+            descs[(size_t)i].nitems = (int32_t)its.size();
             g->h_off[(size_t)i + 1] = g->h_off[(size_t)i] + net->n;
-            g->total_items += pd.nitems;
+            g->total_items += (int64_t)its.size();
             g->rel_bytes += (int64_t)pd.rows_bytes;
             g->max_n = std::max<int64_t>(g->max_n, net->n);
         }
-        if (rc) break;
+        if ((rc = dalloc(&g->items, all_items.size()))) break;
+        if ((rc = dalloc(&g->pieces, all_pieces.size()))) break;
+        if (hipMemcpy(g->items, all_items.data(), all_items.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(g->pieces, all_pieces.data(), all_pieces.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+            rc = set_error(RAC_EHIP, "hipMemcpy of the group's work items");
+            break;
+        }
+        for (int32_t i = 0; i < k; ++i) {
+            descs[(size_t)i].items = g->items + item_off[(size_t)i];
+            descs[(size_t)i].pieces = g->pieces + item_off[(size_t)i];
+        }
         g->total_vars = g->h_off[(size_t)k];
         if ((rc = dalloc(&g->d_nets, (size_t)k))) break;
         if (hipMemcpy(g->d_nets, descs.data(), (size_t)k * sizeof(NetDesc), hipMemcpyHostToDevice) != hipSuccess) {
@@ -1561,6 +1604,7 @@ extern "C" int rac_group_enforce(rac_group *g, uint64_t *const *dom, int32_t *it
                                  int32_t *status) {
     if (!g || !dom) return set_error(RAC_EINVAL, "group or dom is NULL");
     HIP_TRY(hipSetDevice(g->device));
+    RAC_TRY(settle(g));
     Runner &r = g->run;
     std::vector<uint64_t> h((size_t)g->total_vars);
     for (int32_t i = 0; i < g->k; ++i) {
@@ -1599,10 +1643,7 @@ extern "C" int rac_group_enforce_device(rac_group *g, uint64_t *d_dom, int32_t *
                                         int32_t *d_status, void *stream) {
     if (!g || !d_dom) return set_error(RAC_EINVAL, "group or dom is NULL");
     HIP_TRY(hipSetDevice(g->device));
-    if (g->pending) {
-        const int prc = rac_group_sync_status(g);
-        if (prc != RAC_OK) return prc;
-    }
+    RAC_TRY(settle(g));
     Launch L = group_launch(g, d_dom, d_dom, d_iters, d_status);
     RAC_TRY(launch_fixpoint(g->run, g->device, (hipStream_t)stream, L, g->total_vars,
                             g->total_items, step_cap(g->opt, g->max_nd), g->opt.use_graph != 0));
@@ -1615,7 +1656,7 @@ extern "C" int rac_group_sync_status(rac_group *g) {
     if (!g->pending) return RAC_OK;
     g->pending = false;
     HIP_TRY(hipSetDevice(g->device));
-    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipEventSynchronize(g->run.ev1));   // the end of the call on the caller's stream
     int32_t hrc = 0;
     HIP_TRY(hipMemcpy(&hrc, g->run.rc, 4, hipMemcpyDeviceToHost));
     float ms = 0.f;

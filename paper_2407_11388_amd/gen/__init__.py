@@ -130,10 +130,10 @@ class Instance:
 
 
 def rel_bits_to_u8(rel: np.ndarray, d: int) -> np.ndarray:
+    """Bit rows [m, d] uint64 (bit b of row a) -> 0/1 bytes [m, d, d]."""
     m = rel.shape[0]
-    b = np.arange(d, dtype=np.uint64)
-    out = ((rel.reshape(m, d, 1) >> b.reshape(1, 1, d)) & np.uint64(1)).astype(np.uint8)
-    return out
+    le = np.ascontiguousarray(rel, dtype="<u8").reshape(m, d).view(np.uint8).reshape(m, d, 8)
+    return np.ascontiguousarray(np.unpackbits(le, axis=2, bitorder="little")[:, :, :d])
 
 
 def rel_u8_to_bits(rel_u8: np.ndarray) -> np.ndarray:

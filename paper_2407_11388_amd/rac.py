@@ -139,6 +139,29 @@ def _ptr(a) -> Optional[int]:
     return int(a.data_ptr())  # torch tensor: device or host pointer
 
 
+def _check_device_tensors(where: str, specs):
+    """specs: (name, tensor, element bytes, exact shape tuple or minimum numel).
+    Every tensor must be a contiguous GPU tensor on the same device, with the
+    element size and the shape the entry point reads and writes."""
+    dev = None
+    for name, t, esize, shape in specs:
+        if not getattr(t, "is_cuda", False):
+            raise ValueError(f"{where}: {name} must be a tensor on the GPU")
+        if dev is None:
+            dev = t.device
+        elif t.device != dev:
+            raise ValueError(f"{where}: {name} is on {t.device}, expected {dev}")
+        if not t.is_contiguous():
+            raise ValueError(f"{where}: {name} must be contiguous")
+        if t.element_size() != esize or (esize == 4 and str(t.dtype) != "torch.int32"):
+            raise ValueError(f"{where}: {name} must have {'int32' if esize == 4 else '8-byte'} elements")
+        if isinstance(shape, tuple):
+            if tuple(t.shape) != shape:
+                raise ValueError(f"{where}: {name} has shape {tuple(t.shape)}, expected {shape}")
+        elif t.numel() < shape:
+            raise ValueError(f"{where}: {name} has {t.numel()} elements, needs {shape}")
+
+
 def options(mode: int = RAC_RUN_TO_FIXPOINT, max_sweeps: int = 0, path: int = PATH_AUTO,
             use_graph: bool = True, item_bytes: int = 0, profile: bool = False) -> rac_options:
     o = rac_options()
@@ -227,8 +250,15 @@ class Net:
         return out, it, st
 
     def enforce_batch_device(self, d_in, d_out, d_iters, d_status, stream: int = 0):
-        """Device pointers (torch tensors on the GPU): enqueue only."""
-        B = int(d_in.shape[0]) if d_in.dim() > 1 else 1
+        """Device pointers (torch tensors on the GPU): d_in and d_out [B, n] of
+        8-byte elements, d_iters and d_status [>= B] int32, all contiguous on
+        one GPU. Enqueues the call on `stream` (a hipStream_t as an int)."""
+        if getattr(d_in, "dim", None) is None or d_in.dim() != 2 or d_in.shape[1] != self.n:
+            raise ValueError(f"d_in must be a [B, {self.n}] tensor")
+        B = int(d_in.shape[0])
+        _check_device_tensors("enforce_batch_device",
+                              [("d_in", d_in, 8, (B, self.n)), ("d_out", d_out, 8, (B, self.n)),
+                               ("d_iters", d_iters, 4, B), ("d_status", d_status, 4, B)])
         _check(lib.rac_enforce_batch_device(self.handle, B, _ptr(d_in), _ptr(d_out), _ptr(d_iters),
                                             _ptr(d_status), stream or None),
                "rac_enforce_batch_device")
@@ -289,6 +319,12 @@ class Group:
         return outs, it, st
 
     def enforce_device(self, d_dom, d_iters, d_status, stream: int = 0):
+        """d_dom: [sum of n_i] 8-byte elements (the nets' states back to back, in/out);
+        d_iters, d_status: [>= k] int32; contiguous tensors on one GPU."""
+        k, total = len(self.nets), int(self.offsets[-1])
+        _check_device_tensors("Group.enforce_device",
+                              [("d_dom", d_dom, 8, (total,)), ("d_iters", d_iters, 4, k),
+                               ("d_status", d_status, 4, k)])
         _check(lib.rac_group_enforce_device(self.handle, _ptr(d_dom), _ptr(d_iters),
                                             _ptr(d_status), stream or None),
                "rac_group_enforce_device")

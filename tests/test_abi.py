@@ -81,3 +81,80 @@ def test_invalid_options():
     _expect(rac.RAC_EINVAL, lambda: rac.Net.from_bits(3, 4, E, R, mode=2))
     _expect(rac.RAC_EINVAL, lambda: rac.Net.from_bits(3, 4, E, R, path=7))
     _expect(rac.RAC_EINVAL, lambda: rac.Net.from_bits(3, 4, E, R, max_sweeps=-1))
+
+
+class FakeGpuTensor:
+    """Stands in for a torch tensor on the GPU (CPU-only test of the wrapper's
+    argument checks; nothing reaches the library)."""
+
+    def __init__(self, shape, esize=8, dtype="torch.int64", device="cuda:0", contiguous=True,
+                 is_cuda=True):
+        self.shape, self._esize, self.dtype = tuple(shape), esize, dtype
+        self.device, self._contig, self.is_cuda = device, contiguous, is_cuda
+
+    def dim(self):
+        return len(self.shape)
+
+    def numel(self):
+        return int(np.prod(self.shape))
+
+    def element_size(self):
+        return self._esize
+
+    def is_contiguous(self):
+        return self._contig
+
+    def data_ptr(self):
+        raise AssertionError("the wrapper must refuse before passing a pointer")
+
+
+def _fake_net(n):
+    net = rac.Net.__new__(rac.Net)
+    net.handle, net.n, net.d, net.m = None, n, 8, 0
+    return net
+
+
+def _i32(numel, **kw):
+    return FakeGpuTensor((numel,), esize=4, dtype="torch.int32", **kw)
+
+
+@pytest.mark.parametrize("case", [
+    "wrong_n", "one_dim", "out_shape", "on_cpu", "other_device", "not_contiguous",
+    "four_byte_domains", "short_iters", "float_status"])
+def test_device_entry_point_refuses_bad_tensors(case):
+    n, B = 10, 6
+    args = dict(d_in=FakeGpuTensor((B, n)), d_out=FakeGpuTensor((B, n)), d_iters=_i32(B),
+                d_status=_i32(B))
+    if case == "wrong_n":
+        args["d_in"] = FakeGpuTensor((B, n - 1))
+    elif case == "one_dim":
+        args["d_in"] = FakeGpuTensor((B * n,))
+    elif case == "out_shape":
+        args["d_out"] = FakeGpuTensor((B - 1, n))
+    elif case == "on_cpu":
+        args["d_out"] = FakeGpuTensor((B, n), is_cuda=False, device="cpu")
+    elif case == "other_device":
+        args["d_iters"] = _i32(B, device="cuda:1")
+    elif case == "not_contiguous":
+        args["d_out"] = FakeGpuTensor((B, n), contiguous=False)
+    elif case == "four_byte_domains":
+        args["d_out"] = FakeGpuTensor((B, n), esize=4, dtype="torch.int32")
+    elif case == "short_iters":
+        args["d_iters"] = _i32(B - 1)
+    elif case == "float_status":
+        args["d_status"] = FakeGpuTensor((B,), esize=4, dtype="torch.float32")
+    with pytest.raises(ValueError):
+        _fake_net(n).enforce_batch_device(**args)
+
+
+def test_group_device_entry_point_refuses_bad_tensors():
+    grp = rac.Group.__new__(rac.Group)
+    grp.nets = [_fake_net(4), _fake_net(7)]
+    grp.offsets = np.array([0, 4, 11], np.int64)
+    grp.handle = None
+    with pytest.raises(ValueError):
+        grp.enforce_device(FakeGpuTensor((10,)), _i32(2), _i32(2))
+    with pytest.raises(ValueError):
+        grp.enforce_device(FakeGpuTensor((11,)), _i32(1), _i32(2))
+    with pytest.raises(ValueError):
+        grp.enforce_device(FakeGpuTensor((11,), is_cuda=False), _i32(2), _i32(2))

@@ -332,3 +332,67 @@ def test_batch_device_entry_point_matches_host(path):
         assert np.array_equal(d_st.cpu().numpy(), h_st)
     assert np.array_equal(d_in.cpu().numpy().view(np.uint64), doms)   # input untouched
     net.close()
+
+
+def test_group_keeps_its_own_item_tables():
+    # A group builds its own work-item tables for its item size. Calls on a
+    # member net that rebuild the net's tables for another size (here the
+    # default size of one state, against the group's 512 bytes) must leave the
+    # group's launches reading valid tables.
+    insts, doms, nets = [], [], []
+    for i in range(6):
+        n, d = 50 + 7 * i, [5, 12, 32, 33, 64, 20][i]
+        inst = gen.model_b(300 + i, n, d, 0.5, 0.45 if d < 12 else 0.8)
+        insts.append(inst)
+        doms.append(gen.preremove(310 + i, n, d, (n * d) // 6))
+        nets.append(rac.Net.from_instance(inst))
+    say("[gpu] group item tables vs calls on member nets")
+    grp = rac.Group(nets, item_bytes=512)
+    for rep in range(3):
+        for i, net in enumerate(nets):
+            got, it, stt = net.enforce(doms[i])
+            exp, e_it, e_st, _, _ = oracle_expect(insts[i].n, insts[i].d, insts[i].edges,
+                                                  insts[i].rel_u8(), doms[i])
+            assert np.array_equal(got, exp) and it == e_it and stt == e_st
+        outs, iters, status = grp.enforce(doms)
+        for i, inst in enumerate(insts):
+            exp, e_it, e_st, _, _ = oracle_expect(inst.n, inst.d, inst.edges, inst.rel_u8(), doms[i])
+            assert np.array_equal(outs[i], exp), f"call {rep}, instance {i}"
+            assert iters[i] == e_it and status[i] == e_st
+    grp.close()
+    for net in nets:
+        net.close()
+
+
+@pytest.mark.parametrize("path", [rac.PATH_BITS, rac.PATH_MFMA])
+def test_host_call_after_device_call(path):
+    # A host-pointer call made while a device-pointer call on the same net is
+    # still in flight (no sync in between) waits for it before reusing the
+    # net's workspace; both results equal the oracle's.
+    torch = pytest.importorskip("torch")
+    n, d, B = 60, 16, 96
+    inst = gen.model_b(17, n, d, 0.7, 0.45)
+    rel = inst.rel_u8()
+    doms, _ = gen.partial_assign_states(18, n, d, B, 8)
+    dev = torch.device("cuda:0")
+    net = rac.Net.from_instance(inst, path=path)
+    d_in = torch.from_numpy(doms.view(np.int64)).to(dev)
+    d_out = torch.zeros_like(d_in)
+    d_it = torch.zeros(B, dtype=torch.int32, device=dev)
+    d_st = torch.zeros(B, dtype=torch.int32, device=dev)
+    say(f"[gpu] host call after device call path={path}")
+    for rep in range(2):
+        net.enforce_batch_device(d_in, d_out, d_it, d_st, torch.cuda.current_stream().cuda_stream)
+        got1, it1, st1 = net.enforce(doms[rep])
+        got2, it2, st2 = net.enforce_batch(doms[:5])
+        torch.cuda.synchronize()
+        res = d_out.cpu().numpy().view(np.uint64)
+        its, sts = d_it.cpu().numpy(), d_st.cpu().numpy()
+        for s in range(B):
+            exp, e_it, e_st, _, _ = oracle_expect(n, d, inst.edges, rel, doms[s])
+            assert np.array_equal(res[s], exp) and its[s] == e_it and sts[s] == e_st, f"state {s}"
+            if s == rep:
+                assert np.array_equal(got1, exp) and it1 == e_it and st1 == e_st
+            if s < 5:
+                assert np.array_equal(got2[s], exp) and it2[s] == e_it and st2[s] == e_st
+    net.close()
