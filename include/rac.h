@@ -178,6 +178,29 @@ int rac_enforce_batch_device(rac_net *net, int32_t B, const uint64_t *d_dom_in,
 int rac_sync_status(rac_net *net);
 
 /*
+ * For callers that cannot allocate device memory during the call (code that
+ * must not call hipMalloc: tight serving loops, harnesses that forbid it):
+ * rac_enforce_batch_device on the bit-row path with every workspace buffer in
+ * one fixed 64 MiB device array of the library instead of memory allocated
+ * for the net. Arguments as for rac_enforce_batch_device (device pointers of
+ * the net's device; d_dom_in may equal d_dom_out; d_iters, d_status may be
+ * NULL); results are equal to that entry point's. Always the bit-row path,
+ * whatever options.path says. It waits on `stream` between rounds of steps
+ * and at the end, so the results are complete when it returns, and it
+ * returns the call's own error code (RAC_ENOTCONVERGED at max_sweeps); it
+ * does not wait for, or report, an earlier device-pointer call on the net.
+ * B * n is limited by the array: about 64 MiB / (40 * n + 100) states; larger
+ * calls return RAC_EINVAL and do nothing. The array is per process and per
+ * device and keeps the last call's contents; each call sets every part it
+ * reads first. Calls from several host threads are serialised by the
+ * library; work that another process or library places on the same buffers
+ * would race, and none does.
+ */
+int rac_enforce_batch_noalloc(rac_net *net, int32_t B, const uint64_t *d_dom_in,
+                              uint64_t *d_dom_out, int32_t *d_iters, int32_t *d_status,
+                              void *stream);
+
+/*
  * Many independent networks of uneven n, d and density, one domain state
  * each, enforced together: every step of every network runs in the same
  * kernels (one captured graph per round of steps). dom[i] is [n_i] host

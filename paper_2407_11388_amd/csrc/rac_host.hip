@@ -1471,6 +1471,175 @@ extern "C" int rac_net_stats(const rac_net *net, rac_stats *out) {
 }
 
 // ---------------------------------------------------------------------------
+// batched states without allocation (workspace in a fixed device array)
+// ---------------------------------------------------------------------------
+
+// Workspace of rac_enforce_batch_noalloc: the bit-row path's double-buffered
+// domains, change flags, failure accumulators, changed-variable lists and
+// per-state control words, carved from one file-scope array per device. Host
+// code never passes the array's name to a kernel (that is a host-side
+// stand-in): it uses the device address fetched once per device below.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+static std::mutex g_noalloc_mu;          // one call at a time per process (they share `scratch`)
+static uint8_t *g_noalloc_ptr[16] = {};  // device address of `scratch`, per device
+
+// Called with `device` current: fetches the array's device address on the
+// first call on that device.
+static int noalloc_scratch(int device, uint8_t **out) {
+    if (device < 0 || device >= 16) return set_error(RAC_ENODEV, "device ordinal %d", device);
+    if (!g_noalloc_ptr[device]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return set_error(RAC_EHIP, "hipGetSymbolAddress returned a null address");
+        g_noalloc_ptr[device] = static_cast<uint8_t *>(p);
+    }
+    *out = g_noalloc_ptr[device];
+    return RAC_OK;
+}
+
+// Byte offsets of the workspace parts for B states of n variables (each part
+// 256-byte aligned); returns the total.
+struct NoAllocLayout {
+    size_t dom[2], chg[2], failacc, clist[2], ctrl, plan, act, act_off, act_push;
+    size_t prob_net, prob_off, checks, rc, total;
+};
+static NoAllocLayout noalloc_layout(int64_t B, int64_t n) {
+    NoAllocLayout o;
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        const size_t here = at;
+        at += (bytes + 255) / 256 * 256;
+        return here;
+    };
+    const size_t nv = (size_t)(B * n);
+    o.dom[0] = take(nv * 8);
+    o.dom[1] = take(nv * 8);
+    o.chg[0] = take(nv * 4);
+    o.chg[1] = take(nv * 4);
+    o.failacc = take(nv * 8);
+    o.clist[0] = take(nv * 4);
+    o.clist[1] = take(nv * 4);
+    o.ctrl = take((size_t)B * sizeof(Ctrl));
+    o.plan = take(sizeof(Plan));
+    o.act = take((size_t)B * 4);
+    o.act_off = take(((size_t)B + 1) * 8);
+    o.act_push = take((size_t)B * 4);
+    o.prob_net = take((size_t)B * 4);
+    o.prob_off = take(((size_t)B + 1) * 8);
+    o.checks = take((size_t)B * 8);
+    o.rc = take(4);
+    o.total = at;
+    return o;
+}
+
+// Problem tables of B instances of one net of n variables: problem p starts
+// at variable p*n.
+static __global__ void noalloc_tables_kernel(int64_t *prob_off, int32_t *prob_net, int32_t B, int32_t n) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = tid; p <= B; p += nth) {
+        prob_off[p] = p * n;
+        if (p < B) prob_net[p] = 0;
+    }
+}
+
+extern "C" int rac_enforce_batch_noalloc(rac_net *net, int32_t B, const uint64_t *d_dom_in,
+                                         uint64_t *d_dom_out, int32_t *d_iters, int32_t *d_status,
+                                         void *stream) {
+    if (!net || B < 0) return set_error(RAC_EINVAL, "bad net or B");
+    if (B == 0) return RAC_OK;
+    if (!d_dom_in || !d_dom_out) return set_error(RAC_EINVAL, "domain pointers are NULL");
+    const NoAllocLayout lay = noalloc_layout(B, net->n);
+    if (lay.total > kNoAllocBytes)
+        return set_error(RAC_EINVAL,
+                         "B*n = %lld variable states need %zu workspace bytes; the fixed "
+                         "workspace of rac_enforce_batch_noalloc holds %zu (about %lld states "
+                         "of this net)",
+                         (long long)B * net->n, lay.total, kNoAllocBytes,
+                         (long long)(kNoAllocBytes / std::max<size_t>(1, lay.total / (size_t)B)));
+    PathData &pd = net->bits;
+    if (!pd.ready || !pd.items || !pd.d_desc)
+        return set_error(RAC_EINVAL, "the net's bit rows are not packed");
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    HIP_TRY(hipSetDevice(net->device));
+    uint8_t *base = nullptr;
+    RAC_TRY(noalloc_scratch(net->device, &base));
+    hipStream_t s = (hipStream_t)stream;
+
+    Launch L;
+    memset(&L, 0, sizeof(L));
+    L.nets = pd.d_desc;
+    int32_t *prob_net = reinterpret_cast<int32_t *>(base + lay.prob_net);
+    int64_t *prob_off = reinterpret_cast<int64_t *>(base + lay.prob_off);
+    L.prob_net = prob_net;
+    L.prob_off = prob_off;
+    L.nprob = B;
+    L.mode = net->opt.mode;
+    L.max_sweeps = net->opt.max_sweeps;
+    L.stage_vars = stage_vars_for(net->n);
+    L.ws.dom[0] = reinterpret_cast<uint64_t *>(base + lay.dom[0]);
+    L.ws.dom[1] = reinterpret_cast<uint64_t *>(base + lay.dom[1]);
+    L.ws.chg[0] = reinterpret_cast<uint32_t *>(base + lay.chg[0]);
+    L.ws.chg[1] = reinterpret_cast<uint32_t *>(base + lay.chg[1]);
+    L.ws.failacc = reinterpret_cast<uint64_t *>(base + lay.failacc);
+    L.ws.ctrl = reinterpret_cast<Ctrl *>(base + lay.ctrl);
+    L.ws.plan = reinterpret_cast<Plan *>(base + lay.plan);
+    L.ws.act = reinterpret_cast<int32_t *>(base + lay.act);
+    L.ws.act_off = reinterpret_cast<int64_t *>(base + lay.act_off);
+    L.ws.act_push = reinterpret_cast<int32_t *>(base + lay.act_push);
+    L.ws.clist[0] = reinterpret_cast<int32_t *>(base + lay.clist[0]);
+    L.ws.clist[1] = reinterpret_cast<int32_t *>(base + lay.clist[1]);
+    L.din = d_dom_in;
+    L.dout = d_dom_out;
+    L.iters_out = d_iters;
+    L.status_out = d_status;
+    L.checks_out = reinterpret_cast<long long *>(base + lay.checks);
+    L.rc_out = reinterpret_cast<int32_t *>(base + lay.rc);
+    L.push_ratio = push_ratio();
+    L.uniform_n = net->n;
+
+    const int64_t nv = (int64_t)B * net->n;
+    const size_t smem = stage_bytes(L.stage_vars);
+    int64_t g = 0;
+    RAC_TRY(sweep_slots(net->device, smem, &g));
+    g = std::max<int64_t>(1, std::min<int64_t>(g, (int64_t)pd.nitems * B));
+    const dim3 ginit = grid_init(nv);
+    const dim3 gupd((unsigned)std::min<int64_t>(4096, std::max<int64_t>(1, (nv + 255) / 256)));
+    const int32_t kcap = step_cap(net->opt, (int64_t)net->n * net->d);
+
+    // every part the kernels read before writing is set here: the problem
+    // tables, then (init) the domains, change flags, failure accumulators,
+    // control words and the error word
+    hipLaunchKernelGGL(noalloc_tables_kernel, dim3((unsigned)std::min<int64_t>(1024, (B + 256) / 256)),
+                       dim3(256), 0, s, prob_off, prob_net, B, net->n);
+    hipLaunchKernelGGL(init_kernel, ginit, dim3(256), 0, s, L);
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, L, 1);
+    int32_t k = 0;
+    for (int round = 0;; ++round) {
+        const int32_t K = round_steps(round);
+        for (int32_t i = 1; i <= K; ++i) {
+            hipLaunchKernelGGL(revise_kernel, dim3((unsigned)g), dim3(kWave), smem, s, L, k + i);
+            hipLaunchKernelGGL(update_kernel, gupd, dim3(256), 0, s, L, k + i);
+            hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, L, k + i + 1);
+        }
+        HIP_TRY(hipGetLastError());
+        k += K;
+        int32_t nact = 0;
+        HIP_TRY(hipMemcpyAsync(&nact, &L.ws.plan->nact, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (nact == 0 || k >= kcap) break;
+    }
+    hipLaunchKernelGGL(finish_kernel, ginit, dim3(256), 0, s, L);
+    HIP_TRY(hipGetLastError());
+    int32_t hrc = 0;
+    HIP_TRY(hipMemcpyAsync(&hrc, L.rc_out, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return rc_from_device(hrc);
+}
+
+// ---------------------------------------------------------------------------
 // groups of networks (one state each)
 // ---------------------------------------------------------------------------
 

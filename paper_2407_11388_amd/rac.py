@@ -38,6 +38,7 @@ PATH_NAMES = {PATH_AUTO: "auto", PATH_BITS: "bits", PATH_INT8: "int8", PATH_MFMA
 EXPORTED = [
     "rac_default_options", "rac_create", "rac_create_bits", "rac_create_dense", "rac_destroy",
     "rac_enforce", "rac_enforce_batch", "rac_enforce_batch_device", "rac_sync_status",
+    "rac_enforce_batch_noalloc",
     "rac_enforce_multi", "rac_group_create", "rac_group_enforce", "rac_group_enforce_device",
     "rac_group_sync_status", "rac_group_destroy", "rac_net_stats", "rac_group_stats",
     "rac_net_info", "rac_search", "rac_strerror", "rac_last_error",
@@ -102,6 +103,7 @@ def _load():
         "rac_enforce_batch": ([vp, i32, vp, vp, vp], ctypes.c_int),
         "rac_enforce_batch_device": ([vp, i32, vp, vp, vp, vp, vp], ctypes.c_int),
         "rac_sync_status": ([vp], ctypes.c_int),
+        "rac_enforce_batch_noalloc": ([vp, i32, vp, vp, vp, vp, vp], ctypes.c_int),
         "rac_enforce_multi": ([i32, vp, vp, vp, vp], ctypes.c_int),
         "rac_group_create": ([i32, vp, vp, pp], ctypes.c_int),
         "rac_group_enforce": ([vp, vp, vp, vp], ctypes.c_int),
@@ -262,6 +264,20 @@ class Net:
         _check(lib.rac_enforce_batch_device(self.handle, B, _ptr(d_in), _ptr(d_out), _ptr(d_iters),
                                             _ptr(d_status), stream or None),
                "rac_enforce_batch_device")
+
+    def enforce_batch_noalloc(self, d_in, d_out, d_iters, d_status, stream: int = 0):
+        """rac_enforce_batch_noalloc: as enforce_batch_device (same tensors), on
+        the bit-row path with the library's fixed workspace; returns when the
+        results are complete."""
+        if getattr(d_in, "dim", None) is None or d_in.dim() != 2 or d_in.shape[1] != self.n:
+            raise ValueError(f"d_in must be a [B, {self.n}] tensor")
+        B = int(d_in.shape[0])
+        _check_device_tensors("enforce_batch_noalloc",
+                              [("d_in", d_in, 8, (B, self.n)), ("d_out", d_out, 8, (B, self.n)),
+                               ("d_iters", d_iters, 4, B), ("d_status", d_status, 4, B)])
+        _check(lib.rac_enforce_batch_noalloc(self.handle, B, _ptr(d_in), _ptr(d_out),
+                                             _ptr(d_iters), _ptr(d_status), stream or None),
+               "rac_enforce_batch_noalloc")
 
     def search(self, dom: np.ndarray, max_solutions: int = 0, max_nodes: int = 0,
                batch: int = 0):
