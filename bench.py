@@ -125,7 +125,11 @@ def profile_report(args):
     wscale = copy_kib / cw["__amd_rocclr_copyBuffer"][0]
     fv, wv = counters(fdir)[kernel], counters(wdir)[kernel]
     top = max(fv)
-    work = [i for i, v in enumerate(fv) if v > 0.01 * top]   # launches that had work
+    if args.profile_top > 0:
+        # the N launches that read the most (e.g. the step-1 launch of each of N calls)
+        work = sorted(sorted(range(len(fv)), key=lambda i: -fv[i])[:args.profile_top])
+    else:
+        work = [i for i, v in enumerate(fv) if v > 0.01 * top]   # launches that had work
     fb = sum(fv[i] for i in work) / len(work) * 1024 * fscale
     wb = sum(wv[i] for i in work) / len(work) * 1024 * wscale
     rows = stats(trace_dir)
@@ -155,7 +159,11 @@ def profile_report(args):
                 for r in csv.DictReader(f):
                     if r["Kernel_Name"].split("(")[0].endswith(kernel):
                         durs.append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
-    if durs:
+    if durs and args.profile_top > 0:
+        busy = sorted(durs)[-args.profile_top:]
+        lines.append(f"* average duration of the {len(busy)} longest launches (of {len(durs)}; "
+                     f"the launches the traffic above is taken from): {sum(busy) / len(busy) / 1e3:.1f} us")
+    elif durs:
         busy = [t for t in durs if t > 0.1 * max(durs)]
         lines.append(f"* average duration of the launches with work ({len(busy)} of {len(durs)}, "
                      f"longer than 10% of the longest): {sum(busy) / len(busy) / 1e3:.1f} us")
@@ -181,7 +189,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch-states",
-                    choices=["batch-states", "single-large", "single-mid", "single-small"])
+                    choices=["batch-states", "uneven-multi", "single-large", "single-mid", "single-small"])
     ap.add_argument("--B", type=int, default=1024)
     ap.add_argument("--plain-states", type=int, default=1024,
                     help="states timed through the plain per-state loop")
@@ -209,7 +217,20 @@ def parse():
     ap.add_argument("--profile-command", action="append", default=[],
                     help="command line recorded in the profile summary (repeatable)")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
+    ap.add_argument("--profile-top", type=int, default=0,
+                    help="with --profile-report: take traffic and duration from the N launches "
+                         "that read the most (0: every launch with work)")
     return ap.parse_args()
+
+
+def algo_row_bytes(inst, path: str = "bits") -> int:
+    """Relation bytes a full sweep of one state must read, without layout
+    padding: per arc, d rows of ceil(d/32) 32-bit words (bit rows; 8-byte rows
+    for 32 < d <= 64), or d*d bytes (int8 rows)."""
+    arcs = 2 * int(inst.m)
+    if path == "int8":
+        return arcs * inst.d * inst.d
+    return arcs * inst.d * (4 if inst.d <= 32 else 8)
 
 
 def host_cpu():
@@ -513,6 +534,58 @@ def main():
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline_batch(inst, doms, args.cpu_seconds)
         net.close()
+    elif args.workload == "uneven-multi":
+        wu = workloads.uneven_multi()
+        nets = [rac.Net.from_instance(i, profile=True) for i in wu.instances]
+        grp = rac.Group(nets, profile=True)
+        flat = np.concatenate(wu.domains).view(np.int64)
+        d_in = torch.from_numpy(flat).to(dev)
+        d_dom = torch.empty_like(d_in)
+        k = len(nets)
+        d_it = torch.empty(k, dtype=torch.int32, device=dev)
+        d_st = torch.empty(k, dtype=torch.int32, device=dev)
+        stream = torch.cuda.current_stream().cuda_stream
+
+        def step():
+            d_dom.copy_(d_in)   # the group call works in place
+            grp.enforce_device(d_dom, d_it, d_st, stream)
+            grp.sync()
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k1, kall, dms = [], 0.0, 0.0
+        for _ in range(args.steps):
+            step()
+            stg = grp.stats()
+            k1.append(stg.first_kernel_ms)
+            kall += stg.kernel_ms
+            dms += stg.device_ms
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / args.steps
+        it_u, st_u = d_it.cpu().numpy(), d_st.cpu().numpy()
+        algo = sum(algo_row_bytes(i) for i in wu.instances)
+        t1 = sum(k1) / len(k1) * 1e-3
+        gbs1 = algo / t1 / 1e9
+        out.update(value=stg.support_checks / t, ms_per_step=t * 1e3, dtype="u32/u64 bit rows",
+                   config=dict(workload=wu.name + ": model-B n~U[20,800] d~U[4,64] "
+                                                  "p1~U[0.1,1) p2~U[0.1,0.6)",
+                               instances=k, path="bits", mode="run-to-fixpoint"),
+                   fixpoints_per_s=k / t, device_ms=dms / args.steps,
+                   revise_ms_all_steps=kall / args.steps,
+                   steps_max=int(it_u.max()), steps_mean=float(it_u.mean()),
+                   wiped_instances=int(st_u.sum()),
+                   roofline=dict(kernel="revise_kernel", bound="hbm", achieved=gbs1,
+                                 peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs1 / HBM_PEAK_GBS,
+                                 traffic=recorded_traffic("revise_kernel_uneven_multi"),
+                                 algorithmic_bytes=algo, padded_bytes=int(stg.relation_bytes),
+                                 step1_ms=t1 * 1e3,
+                                 per_unit="relation rows of every arc of every instance "
+                                          "(d rows of ceil(d/32) words), step 1"))
+        grp.close()
+        for nt in nets:
+            nt.close()
     else:
         name = args.workload.replace("-", "_")
         w = getattr(workloads, name)()
@@ -520,22 +593,35 @@ def main():
         net = rac.Net.from_instance(inst, profile=True, path=rac.PATH_BITS)
         for _ in range(args.warmup):
             net.enforce(dom)
-        kms, t_host = 0.0, 0.0
+        kms, k1ms, dms, t_host = 0.0, 0.0, 0.0, 0.0
         for _ in range(args.steps):
             t0 = time.perf_counter()
             net.enforce(dom)
             t_host += time.perf_counter() - t0
-            kms += net.stats().kernel_ms
+            stk = net.stats()
+            kms += stk.kernel_ms
+            k1ms += stk.first_kernel_ms
+            dms += stk.device_ms
         st = net.stats()
-        t = kms / args.steps * 1e-3
-        gbs = st.relation_bytes / t / 1e9
-        out.update(value=st.support_checks / t, ms_per_step=t * 1e3, dtype="u32 bit rows",
+        t_call = t_host / args.steps            # one enforcement through the host call
+        t_dev = dms / args.steps * 1e-3         # its kernels on the device (all steps)
+        t_k1 = k1ms / args.steps * 1e-3         # the revise launch of step 1
+        algo = algo_row_bytes(inst)
+        gbs = algo / t_k1 / 1e9
+        out.update(value=st.support_checks / t_call, ms_per_step=t_call * 1e3,
+                   dtype="u32 bit rows",
                    config=dict(workload=w.name, path="bits"),
-                   fixpoints_per_s=1.0 / t, host_ms_per_call=t_host / args.steps * 1e3,
+                   fixpoints_per_s=1.0 / t_call, host_ms_per_call=t_call * 1e3,
+                   device_ms_per_call=t_dev * 1e3,
+                   device_support_checks_per_s=st.support_checks / t_dev,
+                   revise_kernel_support_checks_per_s=st.support_checks / (kms / args.steps * 1e-3),
                    roofline=dict(kernel="revise_kernel", bound="hbm", achieved=gbs,
                                  peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS,
                                  traffic=recorded_traffic(f"revise_kernel_{args.workload.replace('-', '_')}"),
-                                 per_unit="relation bytes of every re-examined arc"))
+                                 algorithmic_bytes=algo, padded_bytes=int(st.relation_bytes),
+                                 step1_ms=t_k1 * 1e3,
+                                 per_unit="relation rows of every arc (d rows of ceil(d/32) words), "
+                                          "step 1"))
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline_single(inst, dom, args.cpu_seconds)
         net.close()
@@ -560,7 +646,7 @@ def main():
             stt = net.stats()
             line = dict(us_per_fixpoint_host_call=t_host / reps * 1e6,
                         fixpoints_per_s=reps / t_host, kernel_ms=best,
-                        warm_relation_GBs=stt.relation_bytes / (best * 1e-3) / 1e9,
+                        warm_relation_GBs=algo_row_bytes(inst) / (best * 1e-3) / 1e9,
                         steps=int(stt.sweeps))
             if wname == "single_mid":
                 cold = 0.0
@@ -569,7 +655,7 @@ def main():
                     torch.cuda.synchronize()
                     net.enforce(dom)
                     cold += net.stats().kernel_ms
-                line["cold_relation_GBs"] = stt.relation_bytes / (cold / 5 * 1e-3) / 1e9
+                line["cold_relation_GBs"] = algo_row_bytes(inst) / (cold / 5 * 1e-3) / 1e9
             sec[ws.name] = line
             net.close()
         del flush
@@ -580,14 +666,20 @@ def main():
             net = rac.Net.from_instance(inst, path=p, profile=True)
             for _ in range(3):
                 net.enforce(dom)
-            best = 1e9
+            best, times = 1e9, []
             for _ in range(10):
                 net.enforce(dom)
-                best = min(best, net.stats().kernel_ms)
+                times.append(net.stats().kernel_ms)
+                best = min(best, times[-1])
             stt = net.stats()
-            gbs = stt.relation_bytes / (best * 1e-3) / 1e9
+            algo = algo_row_bytes(inst, pname)
+            mean = sum(times) / len(times)
             sec[f"single-large n=2000 d=32 p1=0.9 p2=0.2 [{pname}]"] = dict(
-                kernel_ms=best, relation_GBs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
+                kernel_ms=best, kernel_ms_mean=mean, algorithmic_bytes=algo,
+                padded_bytes=int(stt.relation_bytes),
+                relation_GBs=algo / (best * 1e-3) / 1e9,
+                hbm_frac=algo / (best * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                hbm_frac_mean=algo / (mean * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 support_checks_per_s=stt.support_checks / (best * 1e-3), steps=int(stt.sweeps))
             net.close()
         if not args.no_uneven:
@@ -595,16 +687,20 @@ def main():
             nets = [rac.Net.from_instance(i, profile=True) for i in wu.instances]
             grp = rac.Group(nets, profile=True)
             grp.enforce(wu.domains)
-            best, best_dev = 1e9, 1e9
+            best, best_dev, best1 = 1e9, 1e9, 1e9
             for _ in range(5):
                 _, it_u, st_u = grp.enforce(wu.domains)
                 stg = grp.stats()
                 best = min(best, stg.kernel_ms)
                 best_dev = min(best_dev, stg.device_ms)
-            gbs = stg.relation_bytes / (best * 1e-3) / 1e9
+                best1 = min(best1, stg.first_kernel_ms)
+            algo = sum(algo_row_bytes(i) for i in wu.instances)
+            gbs1 = algo / (best1 * 1e-3) / 1e9
             sec["uneven-multi 256 instances (shared step kernels)"] = dict(
                 kernel_ms=best, device_ms=best_dev, fixpoints_per_s=len(nets) / (best_dev * 1e-3),
-                relation_bytes=int(stg.relation_bytes), relation_GBs_per_first_step=gbs,
+                step1_revise_ms=best1, algorithmic_bytes=algo,
+                padded_bytes=int(stg.relation_bytes), step1_relation_GBs=gbs1,
+                step1_hbm_frac=gbs1 / HBM_PEAK_GBS,
                 support_checks_per_s=stg.support_checks / (best_dev * 1e-3),
                 steps_max=int(it_u.max()), steps_mean=float(it_u.mean()),
                 wiped_instances=int(st_u.sum()))

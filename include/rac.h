@@ -105,7 +105,9 @@ typedef struct rac_stats {
                                 2*d*d per (arc, active state, step); 0 on other paths */
     int32_t path;            /* RAC_PATH_* actually used */
     int32_t item_bytes;      /* work-item size used by the bit / int8 path */
-    int32_t reserved[2];
+    float first_kernel_ms;   /* with options.profile: duration of the dominant kernel's
+                                launch of step 1 (every arc of every state re-examined) */
+    int32_t reserved;
 } rac_stats;
 
 /* Fills *opt with the defaults. */

@@ -1149,6 +1149,7 @@ static void collect_stats(MfmaData &md, int32_t B, const std::vector<long long> 
         for (int32_t k = 1; k <= kl; ++k) {
             float t = 0.f;
             (void)hipEventElapsedTime(&t, m->kev[2 * (k - 1)], m->kev[2 * (k - 1) + 1]);
+            if (k == 1) stats->first_kernel_ms = t;
             stats->kernel_ms += t;
         }
         stats->kernel_launches = kl;

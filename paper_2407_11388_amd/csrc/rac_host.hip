@@ -943,9 +943,10 @@ static int launch_fixpoint(Runner &r, int device, hipStream_t stream, const Laun
 
 // Profile mode: summed duration of the revise launches of steps that some
 // problem executed, and their number.
-static void revise_timing(Runner &r, double *ms, int64_t *launches) {
+static void revise_timing(Runner &r, double *ms, int64_t *launches, float *first_ms) {
     *ms = 0.0;
     *launches = 0;
+    *first_ms = 0.f;
     if (!r.profiled) return;
     int32_t h[kHist] = {0};
     const int32_t n = std::min<int32_t>(r.steps_launched, kProfSteps);
@@ -955,6 +956,7 @@ static void revise_timing(Runner &r, double *ms, int64_t *launches) {
         if (h[k] <= 0) continue;
         float t = 0.f;
         if (hipEventElapsedTime(&t, r.kev[2 * (k - 1)], r.kev[2 * (k - 1) + 1]) == hipSuccess) {
+            if (k == 1) *first_ms = t;
             *ms += t;
             ++*launches;
         }
@@ -1091,7 +1093,8 @@ static int collect_bits(rac_net *net, int32_t B, int32_t path, uint64_t *dom, in
     (void)hipEventElapsedTime(&ms, r.ev0, r.ev1);
     fill_stats_bits(net->last, hc, hi, path, pd, ms);
     net->last.relation_bytes = (int64_t)pd.rows_bytes;
-    revise_timing(r, &net->last.kernel_ms, &net->last.kernel_launches);
+    revise_timing(r, &net->last.kernel_ms, &net->last.kernel_launches,
+                 &net->last.first_kernel_ms);
     if (iters) memcpy(iters, hi.data(), (size_t)B * 4);
     if (status) memcpy(status, hs.data(), (size_t)B * 4);
     return rc_from_device(hrc);
@@ -1460,7 +1463,8 @@ extern "C" int rac_sync_status(rac_net *net) {
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, net->run.ev0, net->run.ev1);
     net->last.device_ms = ms;
-    revise_timing(net->run, &net->last.kernel_ms, &net->last.kernel_launches);
+    revise_timing(net->run, &net->last.kernel_ms, &net->last.kernel_launches,
+                 &net->last.first_kernel_ms);
     return rc_from_device(hrc);
 }
 
@@ -1804,7 +1808,8 @@ extern "C" int rac_group_enforce(rac_group *g, uint64_t *const *dom, int32_t *it
     g->last.device_ms = ms;
     g->last.path = RAC_PATH_BITS;
     g->last.relation_bytes = g->rel_bytes;
-    revise_timing(r, &g->last.kernel_ms, &g->last.kernel_launches);
+    revise_timing(r, &g->last.kernel_ms, &g->last.kernel_launches,
+                 &g->last.first_kernel_ms);
     return rc_from_device(hrc);
 }
 
@@ -1815,7 +1820,8 @@ extern "C" int rac_group_enforce_device(rac_group *g, uint64_t *d_dom, int32_t *
     RAC_TRY(settle(g));
     Launch L = group_launch(g, d_dom, d_dom, d_iters, d_status);
     RAC_TRY(launch_fixpoint(g->run, g->device, (hipStream_t)stream, L, g->total_vars,
-                            g->total_items, step_cap(g->opt, g->max_nd), g->opt.use_graph != 0));
+                            g->total_items, step_cap(g->opt, g->max_nd), g->opt.use_graph != 0,
+                            g->opt.profile != 0));
     g->pending = true;
     return RAC_OK;
 }
@@ -1828,11 +1834,16 @@ extern "C" int rac_group_sync_status(rac_group *g) {
     HIP_TRY(hipEventSynchronize(g->run.ev1));   // the end of the call on the caller's stream
     int32_t hrc = 0;
     HIP_TRY(hipMemcpy(&hrc, g->run.rc, 4, hipMemcpyDeviceToHost));
+    std::vector<long long> hc((size_t)g->k);
+    HIP_TRY(hipMemcpy(hc.data(), g->run.checks, (size_t)g->k * 8, hipMemcpyDeviceToHost));
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, g->run.ev0, g->run.ev1);
+    memset(&g->last, 0, sizeof(g->last));
+    for (long long c : hc) g->last.support_checks += c;
     g->last.device_ms = ms;
     g->last.relation_bytes = g->rel_bytes;
     g->last.path = RAC_PATH_BITS;
+    revise_timing(g->run, &g->last.kernel_ms, &g->last.kernel_launches, &g->last.first_kernel_ms);
     return rc_from_device(hrc);
 }
 

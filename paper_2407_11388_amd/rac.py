@@ -63,7 +63,8 @@ class rac_stats(ctypes.Structure):
                 ("relation_bytes", ctypes.c_int64), ("device_ms", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int64),
                 ("algo_ops", ctypes.c_int64), ("path", ctypes.c_int32),
-                ("item_bytes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("item_bytes", ctypes.c_int32), ("first_kernel_ms", ctypes.c_float),
+                ("reserved", ctypes.c_int32)]
 
 
 class rac_search_result(ctypes.Structure):
