@@ -67,18 +67,16 @@ struct MState {
 
 struct MArgs {
     int32_t n, d, capB;               // capB: state slots of the domain buffers
-    const int32_t *row_ptr;           // [n+1] arcs of x, sorted by neighbour
-    const int32_t *nbr_s;             // [arcs]
     const int32_t *deg;               // [n]
-    const uint32_t *r1;               // [arcs + kMY][32] row a of each arc as bits (bit b: (a,b)
-                                      // allowed); kMY zero arcs of padding at the end
-    const uint32_t *bm4;              // [n][nw4] neighbour masks of 4 blocks of 8 neighbours per
-                                      // word: bit 8q+l of word w: x is constrained with
-                                      // y = 8(4w+q) + l
-    const int32_t *bf4;               // [n][nw4] first arc of x in block 4w
-    int32_t nw4;                      // ceil(nblk / 4)
+    const v4i *aop;                   // [operands][64 lanes] matrix-core A operands, 16 bytes
+                                      // per lane (see mfma_pack_ops_kernel)
+    const uint32_t *udesc;            // [pairs][nblk] units of pair p in neighbour block b:
+                                      // bits 3u..3u+2: block slot (y - 8b) of unit u; bits
+                                      // 24-26: chained pairs nc; 27-30: shared neighbours nb;
+                                      // bit 31: leftover kind (0: of x0, 1: of x1)
+    const uint32_t *ubase;            // [pairs][nblk] first operand (bits 0-26) and unit count
+                                      // nu (bits 27-31) of pair p in block b
     int32_t nblk;                     // ceil(n / 8)
-    int32_t narcs;                    // number of arcs
     int8_t *dom8[2];                  // [n][2][capB][16]: bytes 16h .. 16h+15 of the domain as
                                       // bytes 0 / -1 (0xFF: value present)
                                       // of (x, state slot); [0]: the current step's input,
@@ -157,55 +155,46 @@ __global__ void mfma_init_kernel(MArgs A) {
     }
 }
 
-// Direct global -> LDS copy of 16 bytes per lane: lane i writes lds + 16*i.
-__device__ __forceinline__ void dma16(const void *g, void *lds) {
-    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)g,
-                                     (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
-}
 
-// 4 bits -> 4 bytes of 0/64 (bit i of v becomes bit 6 of byte i). The shift
-// comes after the product so that the product keeps 24-bit operands (a
-// full-rate multiply); the compiler would otherwise fold it into the factor.
-__device__ __forceinline__ uint32_t spread4_64(uint32_t v) {
-    uint32_t r;
-    asm("v_lshlrev_b32 %0, 6, %1" : "=v"(r) : "v"(spread4(v)));
-    return r;
-}
-
-constexpr int kStages = 3;                          // LDS ring depth (loads run 2 blocks ahead)
+constexpr int kStages = 2;                          // LDS domain tiles (double buffer)
 constexpr int kBTile = kMY * 2 * kMS;               // v4i per domain tile (32 KiB)
-constexpr int kATile = kMX * kMY * 32 / 4;          // v4i per relation tile (16 KiB)
-constexpr int kOnes = 2 * kMS;                      // v4i of the all-present tile (4 KiB)
-constexpr size_t kMSmem = ((size_t)kStages * (kBTile + kATile) + kOnes) * 16;   // 148 KiB
-constexpr int kDmaPerBlock = kMY * 2 * kMS / 64 / kMW + kXW;        // per wave: 4 + 2
-constexpr int kChunkShift = 8;                      // lane tables cover 256 blocks (64 lanes x 4)
+constexpr int kMaxUnits = kMY;                      // operands of a pair in one block: <= 8
+constexpr size_t kMSmem = (size_t)kStages * kBTile * 16;   // 64 KiB
+constexpr int kCopyPerBlock = kMY * 2 * kMS / 64 / kMW;    // 16-byte copies per lane and block: 4
+constexpr int kTabShift = 6;                        // lane tables cover 64 blocks
 
-// Zero-count flags. Domain bytes are 0 or -1 (0xFF). A wave owns two
-// variables x0, x1 and takes their arcs of a block in pairs (the j-th arc of
-// x0 with the j-th arc of x1). For such a pair (x0 -> y0, x1 -> y1) two
-// chained products give, per (value a, state),
-//   D = kBias + R0 . Dom(y0) + 64 R1 . Dom(y1) = -2016 - c0 - 64 c1
-//     = ~((c0 + 31) + 64 (c1 + 31)),
-// where R0, R1 are the relation rows of a as 0/1 bytes and c0, c1 <= 32 the
-// support counts of (x0, a) on y0 and of (x1, a) on y1. The two 6-bit fields
-// c + 31 do not carry into each other and have bit 5 set iff c > 0, so bit 5
-// (bit 11) of D is set iff (x0, a) ((x1, a)) has no support on that arc. The
-// kernel ORs these words over all arcs: a value survives iff its flag stays
-// clear (Eq. (1): it needs a support on every constraint). A variable with
-// fewer arcs than the other in a block fills its slots with a one-value row
-// times the all-present tile (a count of 1: no flag).
+// Zero-count flags. Domain bytes are 0 or -1 (0xFF). A wave owns the pair of
+// variables x0 = 2p, x1 = 2p+1 and walks the neighbours y of either in blocks
+// of 8. For one matrix-core product D = kBias + A . Dom(y) with the operand
+//   A[a][b] = R(x0,y)[a][b] + 64 R(x1,y)[a][b]   (bytes 0, 1, 64, 65),
+// every (value a, state) gets D = -2016 - c0 - 64 c1 = ~((c0 + 31) + 64 (c1 + 31)),
+// c0 and c1 <= 32 being the support counts of (x0, a) and (x1, a) on y: the
+// two 6-bit fields c + 31 do not carry into each other and have bit 5 set iff
+// c > 0, so bit 5 (bit 11) of D is set iff (x0, a) ((x1, a)) has no support
+// on y. The kernel ORs these words over all neighbours: a value survives iff
+// its flag stays clear (Eq. (1): it needs a support on every constraint).
+//
+// A neighbour of both variables costs one product for two arcs. A neighbour
+// of only x0 (operand R(x0,y)) and one of only x1 (operand 64 R(x1,y)) of the
+// same block are chained into one accumulator, so both fields are again
+// real counts. For a neighbour left over (the block has more of one kind than
+// of the other) only the flag of its own variable is OR-ed in. The units of a
+// block are stored chains first, then shared neighbours, then leftovers, so
+// that every kind starts at a known unit index.
 constexpr int kBias = -2016;
 constexpr int kFlag0 = 1 << 5, kFlag1 = 1 << 11;
 static_assert(kXW == 2, "the zero-count flags pack exactly two variables per word");
+
+__device__ __forceinline__ v16i mfma8(const v4i a, const v4i b, const v16i c) {
+    return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+}
 
 // nseg > 1 splits the neighbour blocks of every (x-tile, state tile) over
 // nseg workgroups (for steps with few active states, so that the grid still
 // fills the chip); each ORs its flags into A.kill and mfma_split_finish_kernel
 // applies them.
 __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, int nseg) {
-    extern __shared__ v4i s_lds[];   // kStages x {domain tile [kMY][2][kMS], relation tile
-                                     // [kMX variables][kMY arcs][32 rows] uint32}, then the
-                                     // all-present tile [2][kMS]
+    extern __shared__ v4i s_lds[];   // kStages domain tiles [kMY][2][kMS]
     const int nact = A.cnt[(k - 1) & 1];
     // workgroup -> (x-tile, state tile); the state tiles of one x-tile share
     // blockIdx % 8 and so an XCD
@@ -227,96 +216,84 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
     if (st0 >= nact || xt * kMX >= A.n) return;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int nw4 = A.nw4;
     // this workgroup's neighbour blocks [blo, bhi) (all of them unless split)
     const int blo = (int)((int64_t)seg * A.nblk / nseg), bhi = (int)((int64_t)(seg + 1) * A.nblk / nseg);
-    // this wave's variables x = xt*kMX + kXW*wave + i (i < kXW)
+    // this wave's pair p and its variables x = 2p + i
+    const int pr = xt * kMW + wave;
     int xs[kXW];
     bool xvs[kXW];
 #pragma unroll
     for (int i = 0; i < kXW; ++i) {
-        xs[i] = xt * kMX + kXW * wave + i;
+        xs[i] = kXW * pr + i;
         xvs[i] = xs[i] < A.n;                       // wave-uniform
     }
+    const bool pv = xvs[0];
     const int8_t *din = A.dom8[0];
     const int half = lane >> 5, col = lane & 31;
-    v4i *ones = s_lds + kStages * (kBTile + kATile);
-    if (tid < kOnes) ones[tid] = v4i{-1, -1, -1, -1};
 
-    // Lane tables of a chunk of 256 blocks: lane l holds, per variable, the
-    // neighbour masks of blocks 4l' .. 4l'+3 (l' = 256c/4 + l) as bytes and the
-    // first arc of block 4l'. One copy follows the blocks being copied (two
-    // ahead), one the blocks being multiplied; no memory access for the tables
-    // inside a chunk.
-    uint32_t tmI[kXW], tmC[kXW];
-    int32_t tfI[kXW];
+    // Lane tables of a chunk of 64 blocks: lane l holds the unit descriptor
+    // and the first operand / unit count of block 64c + l. One copy follows
+    // the blocks whose operands are being loaded (one ahead), one the block
+    // being multiplied.
+    uint32_t tdI = 0, tbI = 0, tdC = 0, tbC = 0;
     int chunkI = -1;
     auto load_tab = [&](int c) {
-        const int w0 = (c << (kChunkShift - 2)) + lane;
-        const int w = w0 < nw4 ? w0 : nw4 - 1;
-#pragma unroll
-        for (int i = 0; i < kXW; ++i) {
-            const int64_t o = (int64_t)(xvs[i] ? xs[i] : 0) * nw4 + w;
-            const uint32_t m = A.bm4[o];
-            const int32_t f = A.bf4[o];
-            tmI[i] = (xvs[i] && w0 < nw4) ? m : 0u;
-            tfI[i] = (xvs[i] && w0 < nw4) ? f : 0;
-        }
+        const int b = (c << kTabShift) + lane;
+        const bool ok = pv && b < A.nblk;
+        const int64_t o = (int64_t)(ok ? pr : 0) * A.nblk + (ok ? b : 0);
+        const uint32_t dsc = A.udesc[o], bs = A.ubase[o];
+        tdI = ok ? dsc : 0u;
+        tbI = ok ? bs : 0u;
     };
-    auto mask_of = [&](uint32_t tm, int b) -> uint32_t {
-        const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)tm, (b >> 2) & 63);
-        return (w >> (8 * (b & 3))) & 0xFFu;
-    };
-    // the matrix-core operand of lane (col, half) for an arc: row a = col,
-    // bits 16*half .. 16*half+15 as 16 bytes of 0/1 (scale 1) or 0/64
-    auto expand1 = [&](uint32_t row) {
-        const uint32_t h = row >> (16 * half);
-        return v4i{(int)spread4(h & 0xFu), (int)spread4((h >> 4) & 0xFu),
-                   (int)spread4((h >> 8) & 0xFu), (int)spread4((h >> 12) & 0xFu)};
-    };
-    auto expand64 = [&](uint32_t row) {
-        const uint32_t h = row >> (16 * half);
-        return v4i{(int)spread4_64(h & 0xFu), (int)spread4_64((h >> 4) & 0xFu),
-                   (int)spread4_64((h >> 8) & 0xFu), (int)spread4_64((h >> 12) & 0xFu)};
+    auto lane_word = [&](uint32_t t, int b) -> uint32_t {
+        return (uint32_t)__builtin_amdgcn_readlane((int)t, b & 63);
     };
 
-    // Copies of block `blk` into ring stage `stg`, all direct to LDS (no
-    // registers): the domain tile is 16 rows (neighbour yl, half h) of 128
-    // consecutive slots, 2 KiB each in both memories; wave w copies rows 2w
-    // and 2w+1 as 1 KiB halves. A neighbour past n copies variable n-1's row
-    // (never a neighbour of anything); slots past the active ones are in the
-    // buffer and never used. The relation tile of a variable is the 8 arcs
-    // from the block's first arc (1 KiB; arcs past the block or past the last
-    // arc, where kMY zero arcs pad the array, are never used).
-    auto issue = [&](int stg, int blk) {
-        if ((blk >> kChunkShift) != chunkI) {
-            chunkI = blk >> kChunkShift;
+    // Operand table word (first operand, unit count) of block b; the copy
+    // of the lane table that follows the operand loads moves to b's chunk.
+    auto ops_word = [&](int b) -> uint32_t {
+        if ((b >> kTabShift) != chunkI) {
+            chunkI = b >> kTabShift;
             load_tab(chunkI);
         }
-        v4i *bt = s_lds + stg * (kBTile + kATile);
+        return lane_word(tbI, b);
+    };
+    // Operands u0, u0+1 of the block whose table word is w, into Aop[u0],
+    // Aop[u0+1] (16 bytes per lane each; units past the block's count load
+    // its first operand again)
+    v4i Aop[kMaxUnits];
+    auto load_two = [&](uint32_t w, int u0) {
+        const int nu = (int)(w >> 27);
+        const v4i *src = A.aop + (int64_t)(w & 0x7FFFFFFu) * 64 + lane;
+        Aop[u0] = src[(u0 < nu ? u0 : 0) * 64];
+        Aop[u0 + 1] = src[(u0 + 1 < nu ? u0 + 1 : 0) * 64];
+    };
+    // The domain tile of block `blk`: 16 rows (neighbour yl, half h) of 128
+    // consecutive slots, 2 KiB each in both memories; wave w copies rows 2w
+    // and 2w+1 as 1 KiB halves, loaded into registers (fetch) and written to
+    // an LDS stage (store). A neighbour past n copies variable n-1's row
+    // (never a neighbour of anything); slots past the active ones are in the
+    // buffer and never used. (Registers rather than direct-to-LDS copies: the
+    // compiler then waits for each operand load precisely.)
+    v4i cp[kCopyPerBlock];
+    auto fetch = [&](int blk) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < kCopyPerBlock; ++i) {
             const int row = wave * 2 + (i >> 1), part = i & 1;
             const int yl = row >> 1, h = row & 1;
             int y = blk * kMY + yl;
             y = y < A.n ? y : A.n - 1;
-            dma16(din + dom_off(A, y, h, st0 + part * 64 + lane), bt + (yl * 2 + h) * kMS + part * 64);
-        }
-#pragma unroll
-        for (int i = 0; i < kXW; ++i) {
-            const int l = (blk >> 2) & 63;
-            const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)tmI[i], l);
-            const int32_t j0 = __builtin_amdgcn_readlane(tfI[i], l) +
-                               __builtin_popcount(w & ((1u << (8 * (blk & 3))) - 1u));
-            dma16(A.r1 + ((int64_t)j0 * 32 + lane * 4),
-                  bt + kBTile + (kXW * wave + i) * (kMY * 32 / 4));
+            cp[i] = *reinterpret_cast<const v4i *>(din + dom_off(A, y, h, st0 + part * 64 + lane));
         }
     };
-    // waits until this wave's copies of the next block are in LDS (the copies
-    // of the block after it may stay in flight), and its LDS reads are done;
-    // then the workgroup barrier makes every wave's copies visible
-    auto ring_sync = [&]() {
-        asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(kDmaPerBlock) : "memory");
+    auto store = [&](int stg) {
+        v4i *bt = s_lds + stg * kBTile;
+#pragma unroll
+        for (int i = 0; i < kCopyPerBlock; ++i) {
+            const int row = wave * 2 + (i >> 1), part = i & 1;
+            const int yl = row >> 1, h = row & 1;
+            bt[(yl * 2 + h) * kMS + part * 64 + lane] = cp[i];
+        }
     };
 
     v16i rf[kMSub];
@@ -329,97 +306,89 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
     asm volatile("" : "+v"(bias));   // kept in registers, not re-created per use
     // byte offset of lane (col, half)'s 16 operand bytes within a domain row pair
     const uint32_t lane_off = (uint32_t)(half * kMS + col) * 16u;
-    const uint32_t ones_off = (uint32_t)(kStages * (kBTile + kATile)) * 16u;
+    const char *lds = reinterpret_cast<const char *>(s_lds);
+    auto ldsb = [&](uint32_t off) { return *reinterpret_cast<const v4i *>(lds + off); };
 
-    issue(0, blo);
-    issue(1, blo + 1 < bhi ? blo + 1 : bhi - 1);
-    ring_sync();
+    {
+        const uint32_t w0 = ops_word(blo);
+#pragma unroll
+        for (int q = 0; q < kMaxUnits / 2; ++q) load_two(w0, 2 * q);
+    }
+    fetch(blo);
+    store(0);
+    __syncthreads();
     for (int blk = blo; blk < bhi; ++blk) {
-        // the block two ahead (past the end: a repeat of the last block into
-        // the stage no one reads any more)
-        issue((blk - blo + 2) % kStages, blk + 2 < bhi ? blk + 2 : bhi - 1);
-        if (blk == blo || (blk & ((1 << kChunkShift) - 1)) == 0) {
-            // the copy pointer (two blocks ahead, in the same chunk) loaded it
-#pragma unroll
-            for (int i = 0; i < kXW; ++i) tmC[i] = tmI[i];
+        if (blk == blo || (blk & ((1 << kTabShift) - 1)) == 0) {
+            // the operand pointer (one block ahead, in the same chunk) loaded it
+            tdC = tdI;
+            tbC = tbI;
         }
-        const int stg = (blk - blo) % kStages;
-        const uint32_t stage_off = (uint32_t)(stg * (kBTile + kATile)) * 16u;
-        const uint32_t *at0 = reinterpret_cast<const uint32_t *>(s_lds + stg * (kBTile + kATile) + kBTile) +
-                              (kXW * wave) * (kMY * 32);
-        const uint32_t *at1 = at0 + kMY * 32;
-        const uint32_t m0 = mask_of(tmC[0], blk), m1 = mask_of(tmC[1], blk);
-        const int c0 = __builtin_popcount(m0), c1 = __builtin_popcount(m1);
-        const int cm = c0 > c1 ? c0 : c1;
-        if (cm > 0) {
-            // LDS byte offsets of the domain rows of slot j's neighbour, per
-            // variable (slots past a variable's arcs: the all-present tile)
-            uint32_t ob0[kMY], ob1[kMY];
-            {
-                uint32_t r0 = m0, r1 = m1;
+        const uint32_t desc = lane_word(tdC, blk), wb = lane_word(tbC, blk);
+        // the next block's domain tile (stored after this block's products),
+        // and its operands, loaded into the registers of each unit pair once
+        // it is done
+        const bool more = blk + 1 < bhi;
+        if (more) fetch(blk + 1);
+        const uint32_t wn = ops_word(more ? blk + 1 : blk);
+
+        const int nu = (int)(wb >> 27);
+        const int nc = (int)((desc >> 24) & 7u), nbe = 2 * nc + (int)((desc >> 27) & 15u);
+        const uint32_t stage_off = (uint32_t)(((blk - blo) & 1) * kBTile) * 16u;
+        // a leftover's word has a real flag for its own variable only
+        const int lmask = (desc >> 31) ? kFlag1 : kFlag0;
 #pragma unroll
-                for (int j = 0; j < kMY; ++j) {
-                    ob0[j] = (r0 ? stage_off + (uint32_t)__builtin_ctz(r0) * (2u * kMS * 16u) : ones_off) + lane_off;
-                    ob1[j] = (r1 ? stage_off + (uint32_t)__builtin_ctz(r1) * (2u * kMS * 16u) : ones_off) + lane_off;
-                    r0 &= r0 - 1u;
-                    r1 &= r1 - 1u;
-                }
-            }
-            const int npair = (cm + 1) >> 1;
-            const char *lds = reinterpret_cast<const char *>(s_lds);
-            // B operands of slot pair q, sub-tile t: (x0, 2q), (x1, 2q), (x0, 2q+1), (x1, 2q+1)
-            auto lds_b = [&](int q, int t, v4i (&b)[4]) {
-                b[0] = *reinterpret_cast<const v4i *>(lds + ob0[2 * q] + t * 512);
-                b[1] = *reinterpret_cast<const v4i *>(lds + ob1[2 * q] + t * 512);
-                b[2] = *reinterpret_cast<const v4i *>(lds + ob0[2 * q + 1] + t * 512);
-                b[3] = *reinterpret_cast<const v4i *>(lds + ob1[2 * q + 1] + t * 512);
-            };
-            // Units u = slot pair * kMSub + sub-tile are software-pipelined:
-            // the LDS operands of unit u+1 are read and the four products of
-            // unit u issued before the words of unit u-1 are OR-ed in.
-            v4i bn[4];
-            lds_b(0, 0, bn);
-            v16i pe = bias, po = bias;
-#pragma unroll
-            for (int q = 0; q < kMY / 2; ++q) {
-                if (q >= npair) break;
-                const int je = 2 * q, jo = 2 * q + 1;
-                const v4i a0e = expand1(je < c0 ? at0[je * 32 + col] : 1u);
-                const v4i a1e = expand64(je < c1 ? at1[je * 32 + col] : 1u);
-                const v4i a0o = expand1(jo < c0 ? at0[jo * 32 + col] : 1u);
-                const v4i a1o = expand64(jo < c1 ? at1[jo * 32 + col] : 1u);
+        for (int q = 0; q < kMaxUnits / 2; ++q) {
+            const int u0 = 2 * q, u1 = 2 * q + 1;
+            const uint32_t o0 = stage_off + ((desc >> (3 * u0)) & 7u) * (2u * kMS * 16u) + lane_off;
+            const uint32_t o1 = stage_off + ((desc >> (3 * u1)) & 7u) * (2u * kMS * 16u) + lane_off;
+            if (u0 >= nu) {
+                // no unit
+            } else if (q < nc) {
+                // chained: a neighbour of only x0, then one of only x1
 #pragma unroll
                 for (int t = 0; t < kMSub; ++t) {
-                    const int u = q * kMSub + t;
-                    v4i b[4] = {bn[0], bn[1], bn[2], bn[3]};
-                    // (past the last slot pair: slots of absent arcs, read
-                    // and never used; a constant index keeps the offsets in
-                    // registers)
-                    if (u + 1 < kMY / 2 * kMSub) lds_b((u + 1) / kMSub, (u + 1) % kMSub, bn);
-                    v16i de = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0e, b[0], bias, 0, 0, 0);
-                    v16i dd = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0o, b[2], bias, 0, 0, 0);
-                    de = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1e, b[1], de, 0, 0, 0);
-                    dd = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1o, b[3], dd, 0, 0, 0);
-                    // keep the compiler from moving the OR next to the
-                    // products it would then wait for
-                    __builtin_amdgcn_sched_barrier(0);
-                    if (u > 0) {
-                        v16i &r = rf[(u - 1) % kMSub];
+                    const v16i dd = mfma8(Aop[u1], ldsb(o1 + t * 512),
+                                          mfma8(Aop[u0], ldsb(o0 + t * 512), bias));
 #pragma unroll
-                        for (int v = 0; v < 16; ++v) r[v] = r[v] | pe[v] | po[v];
+                    for (int v = 0; v < 16; ++v) rf[t][v] |= dd[v];
+                }
+            } else if (u1 < nu) {
+                // two units: shared neighbours, or leftovers (from index nbe)
+                if (u1 < nbe) {
+#pragma unroll
+                    for (int t = 0; t < kMSub; ++t) {
+                        const v16i d0 = mfma8(Aop[u0], ldsb(o0 + t * 512), bias);
+                        const v16i d1 = mfma8(Aop[u1], ldsb(o1 + t * 512), bias);
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) rf[t][v] = rf[t][v] | d0[v] | d1[v];
                     }
-                    __builtin_amdgcn_sched_barrier(0);
-                    pe = de;
-                    po = dd;
+                } else {
+                    const int m0 = u0 < nbe ? -1 : lmask;
+#pragma unroll
+                    for (int t = 0; t < kMSub; ++t) {
+                        const v16i d0 = mfma8(Aop[u0], ldsb(o0 + t * 512), bias);
+                        const v16i d1 = mfma8(Aop[u1], ldsb(o1 + t * 512), bias);
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) rf[t][v] |= (d0[v] & m0) | (d1[v] & lmask);
+                    }
+                }
+            } else {
+                const int m0 = u0 < nbe ? -1 : lmask;
+#pragma unroll
+                for (int t = 0; t < kMSub; ++t) {
+                    const v16i d0 = mfma8(Aop[u0], ldsb(o0 + t * 512), bias);
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) rf[t][v] |= d0[v] & m0;   // one v_and_or each
                 }
             }
-            v16i &r = rf[kMSub - 1];   // a slot pair's last unit is its last sub-tile
-#pragma unroll
-            for (int v = 0; v < 16; ++v) r[v] = r[v] | pe[v] | po[v];
+            load_two(wn, u0);   // this pair's registers now take the next block's operands
         }
-        ring_sync();
+        __syncthreads();   // every wave is done with the stage the next tile goes to
+        if (more) {
+            store((blk - blo + 1) & 1);
+            __syncthreads();
+        }
     }
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // no copy may outlive the workgroup
 
     if (nseg > 1) {
         // split step: OR this workgroup's unsupported values into A.kill
@@ -712,26 +681,35 @@ __global__ void mfma_pack_kernel(MArgs A) {
     }
 }
 
-// Relation rows in the matrix-core layout: out[j][a] = row a of arc j as
-// bits (bit b: (a,b) allowed), arcs in neighbour-sorted order (src_sorted[j]
-// = 2e + flip), 32 rows per arc, zero beyond d.
-__global__ void mfma_pack_r1_kernel(const uint64_t *rel, const int32_t *src_sorted, int64_t arcs,
-                                    int32_t d, uint32_t *out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // one row per thread
-    if (i >= arcs * 32) return;
-    const int64_t j = i >> 5;
-    const int32_t a = (int32_t)(i & 31);
-    uint64_t row = 0;
-    if (a < d) {
-        const int32_t src = src_sorted[j];
-        const uint64_t *R = rel + (int64_t)(src >> 1) * d;
-        if ((src & 1) == 0) {
-            row = R[a];
-        } else {
-            for (int b = 0; b < d; ++b) row |= ((R[b] >> a) & 1ull) << b;
-        }
-    }
-    out[i] = (uint32_t)row;
+// Row a of an arc as bits (bit b: (a,b) allowed); src = 2e + flip, the arc
+// y->x of constraint e (flip = 1) holding column a of the constraint's rows.
+__device__ __forceinline__ uint32_t arc_row32(const uint64_t *rel, int32_t src, int32_t d, int32_t a) {
+    if (src < 0 || a >= d) return 0u;
+    const uint64_t *R = rel + (int64_t)(src >> 1) * d;
+    if ((src & 1) == 0) return (uint32_t)R[a];
+    uint32_t row = 0;
+    for (int b = 0; b < d; ++b) row |= (uint32_t)((R[b] >> a) & 1ull) << b;
+    return row;
+}
+
+// Matrix-core A operands: operand o is R0 + 64 R1 as int8 bytes, R0 the
+// relation of arc src[o].x (x0 -> y) and R1 that of arc src[o].y (x1 -> y),
+// an absent arc (-1) contributing zeros; lane l holds row a = l % 32, values
+// b = 16 (l / 32) .. +15, as the 32x32x32 int8 product reads its A operand.
+__global__ void mfma_pack_ops_kernel(const uint64_t *rel, const int2 *src, int64_t nops, int32_t d,
+                                     v4i *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (operand, lane)
+    if (i >= nops * 64) return;
+    const int64_t o = i >> 6;
+    const int lane = (int)(i & 63), a = lane & 31, h = lane >> 5;
+    const int2 sj = src[o];
+    const uint32_t r0 = arc_row32(rel, sj.x, d, a) >> (16 * h);
+    const uint32_t r1 = arc_row32(rel, sj.y, d, a) >> (16 * h);
+    v4i w;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        w[q] = (int)(spread4((r0 >> (4 * q)) & 0xFu) | (spread4((r1 >> (4 * q)) & 0xFu) << 6));
+    out[i] = w;
 }
 
 // ---------------------------------------------------------------------------
@@ -747,12 +725,11 @@ __global__ void mfma_pack_r1_kernel(const uint64_t *rel, const int32_t *src_sort
     } while (0)
 
 struct MfmaImpl {
-    int32_t *row_ptr = nullptr, *nbr_s = nullptr;
     const int32_t *deg = nullptr;
-    uint32_t *r1 = nullptr;
-    uint32_t *bm4 = nullptr;
-    int32_t *bf4 = nullptr;
-    int32_t nblk = 0, nw4 = 0;
+    v4i *aop = nullptr;                          // matrix-core A operands
+    uint32_t *udesc = nullptr, *ubase = nullptr; // per (pair, block) unit tables
+    int64_t nops = 0;
+    int32_t nblk = 0;
     int32_t capB = 0, words = 0;
     int8_t *dom8[2] = {nullptr, nullptr};
     uint32_t *chg = nullptr, *wipe = nullptr, *kill = nullptr;
@@ -785,11 +762,9 @@ template <typename T> static void mfree(T *&p) {
 void mfma_release(MfmaData &md) {
     MfmaImpl *m = impl(md);
     if (!m) return;
-    mfree(m->row_ptr);
-    mfree(m->nbr_s);
-    mfree(m->r1);
-    mfree(m->bm4);
-    mfree(m->bf4);
+    mfree(m->aop);
+    mfree(m->udesc);
+    mfree(m->ubase);
     mfree(m->dom8[0]);
     mfree(m->dom8[1]);
     mfree(m->chg);
@@ -838,69 +813,99 @@ int mfma_ensure(MfmaData &md, int32_t n, int32_t d, int64_t arcs, const int32_t 
     md.d = d;
     md.arcs = arcs;
     m->deg = deg;
-    // arcs of every variable sorted by neighbour
+    // neighbours of every variable, sorted, with their arcs (CSR order)
     std::vector<int32_t> h_nbr((size_t)arcs), h_src((size_t)arcs);
     if (arcs > 0) {
         HIP_OK(hipMemcpy(h_nbr.data(), nbr, (size_t)arcs * 4, hipMemcpyDeviceToHost));
         HIP_OK(hipMemcpy(h_src.data(), arc_src, (size_t)arcs * 4, hipMemcpyDeviceToHost));
     }
-    std::vector<int32_t> nbr_s((size_t)arcs), src_s((size_t)arcs), perm;
-    for (int32_t x = 0; x < n; ++x) {
-        const int32_t j0 = h_row_ptr[x], j1 = h_row_ptr[x + 1];
-        perm.resize((size_t)(j1 - j0));
-        for (int32_t j = j0; j < j1; ++j) perm[(size_t)(j - j0)] = j;
-        std::sort(perm.begin(), perm.end(),
-                  [&](int32_t p, int32_t q) { return h_nbr[(size_t)p] < h_nbr[(size_t)q]; });
-        for (int32_t j = j0; j < j1; ++j) {
-            nbr_s[(size_t)j] = h_nbr[(size_t)perm[(size_t)(j - j0)]];
-            src_s[(size_t)j] = h_src[(size_t)perm[(size_t)(j - j0)]];
-        }
-    }
-    // per (variable, 4 blocks of 8 neighbours): the blocks' neighbour masks
-    // as bytes and the first arc of the first block
+    std::vector<std::pair<int32_t, int32_t>> adj0, adj1;   // (y, arc source 2e + flip)
+    auto nbrs = [&](int32_t x, std::vector<std::pair<int32_t, int32_t>> &out) {
+        out.clear();
+        if (x >= n) return;
+        for (int32_t j = h_row_ptr[x]; j < h_row_ptr[x + 1]; ++j)
+            out.push_back({h_nbr[(size_t)j], h_src[(size_t)j]});
+        std::sort(out.begin(), out.end());
+    };
+    // per pair (x0 = 2p, x1 = 2p + 1) and block of 8 neighbours: the units
+    // (chains of a neighbour of only x0 with one of only x1, then shared
+    // neighbours, then leftovers), their operands and the unit tables
     const int32_t nblk = (n + kMY - 1) / kMY;
-    const int32_t nw4 = (nblk + 3) / 4;
-    std::vector<uint32_t> bm4((size_t)n * nw4, 0);
-    std::vector<int32_t> bf4((size_t)n * nw4, 0);
-    for (int32_t x = 0; x < n; ++x) {
-        int32_t j = h_row_ptr[x];
-        const int32_t j1 = h_row_ptr[x + 1];
-        for (int32_t w = 0; w < nw4; ++w) {
-            while (j < j1 && nbr_s[(size_t)j] < 4 * w * kMY) ++j;
-            bf4[(size_t)x * nw4 + w] = j;
-        }
-        for (int32_t jj = h_row_ptr[x]; jj < j1; ++jj) {
-            const int32_t y = nbr_s[(size_t)jj];
-            bm4[(size_t)x * nw4 + y / (4 * kMY)] |= 1u << (y % (4 * kMY));
+    const int32_t npairs = (n + 1) / 2;
+    std::vector<uint32_t> udesc((size_t)npairs * nblk, 0), ubase((size_t)npairs * nblk, 0);
+    std::vector<int2> ops;
+    for (int32_t pr = 0; pr < npairs; ++pr) {
+        nbrs(2 * pr, adj0);
+        nbrs(2 * pr + 1, adj1);
+        size_t i0 = 0, i1 = 0;
+        for (int32_t b = 0; b < nblk; ++b) {
+            const int32_t yend = (b + 1) * kMY;
+            int32_t both[kMY][3], only0[kMY][2], only1[kMY][2];
+            int nb = 0, n0 = 0, n1 = 0;
+            while ((i0 < adj0.size() && adj0[i0].first < yend) || (i1 < adj1.size() && adj1[i1].first < yend)) {
+                const int32_t y0 = i0 < adj0.size() ? adj0[i0].first : INT32_MAX;
+                const int32_t y1 = i1 < adj1.size() ? adj1[i1].first : INT32_MAX;
+                if (y0 == y1) {
+                    both[nb][0] = y0 - b * kMY;
+                    both[nb][1] = adj0[i0++].second;
+                    both[nb++][2] = adj1[i1++].second;
+                } else if (y0 < y1) {
+                    only0[n0][0] = y0 - b * kMY;
+                    only0[n0++][1] = adj0[i0++].second;
+                } else {
+                    only1[n1][0] = y1 - b * kMY;
+                    only1[n1++][1] = adj1[i1++].second;
+                }
+            }
+            const int nc = std::min(n0, n1);
+            uint32_t desc = 0;
+            int u = 0;
+            const int64_t base = (int64_t)ops.size();
+            for (int c = 0; c < nc; ++c) {
+                desc |= (uint32_t)only0[c][0] << (3 * u++);
+                ops.push_back(make_int2(only0[c][1], -1));
+                desc |= (uint32_t)only1[c][0] << (3 * u++);
+                ops.push_back(make_int2(-1, only1[c][1]));
+            }
+            for (int c = 0; c < nb; ++c) {
+                desc |= (uint32_t)both[c][0] << (3 * u++);
+                ops.push_back(make_int2(both[c][1], both[c][2]));
+            }
+            for (int c = nc; c < n0; ++c) {
+                desc |= (uint32_t)only0[c][0] << (3 * u++);
+                ops.push_back(make_int2(only0[c][1], -1));
+            }
+            for (int c = nc; c < n1; ++c) {
+                desc |= (uint32_t)only1[c][0] << (3 * u++);
+                ops.push_back(make_int2(-1, only1[c][1]));
+            }
+            desc |= (uint32_t)nc << 24 | (uint32_t)nb << 27 | (n1 > nc ? 1u << 31 : 0u);
+            if (base > 0x7FFFFFF) return set_error(RAC_EUNSUPPORTED, "matrix-core operands exceed 2^27");
+            udesc[(size_t)pr * nblk + b] = desc;
+            ubase[(size_t)pr * nblk + b] = (uint32_t)base | (uint32_t)u << 27;
         }
     }
     m->nblk = nblk;
-    m->nw4 = nw4;
-    HIP_OK(hipMalloc(&m->bm4, std::max<size_t>(1, bm4.size()) * 4));
-    HIP_OK(hipMalloc(&m->bf4, std::max<size_t>(1, bf4.size()) * 4));
-    if (!bm4.empty()) {
-        HIP_OK(hipMemcpy(m->bm4, bm4.data(), bm4.size() * 4, hipMemcpyHostToDevice));
-        HIP_OK(hipMemcpy(m->bf4, bf4.data(), bf4.size() * 4, hipMemcpyHostToDevice));
-    }
-    int32_t *d_src = nullptr;
-    HIP_OK(hipMalloc(&m->row_ptr, ((size_t)n + 1) * 4));
-    HIP_OK(hipMalloc(&m->nbr_s, std::max<size_t>(1, (size_t)arcs) * 4));
-    // kMY zero arcs of padding: the step kernel copies 8 arcs from each
-    // block's first arc
-    HIP_OK(hipMalloc(&m->r1, ((size_t)arcs + kMY) * 128));
-    HIP_OK(hipMemset(m->r1, 0, ((size_t)arcs + kMY) * 128));
-    HIP_OK(hipMalloc(&d_src, std::max<size_t>(1, (size_t)arcs) * 4));
-    HIP_OK(hipMemcpy(m->row_ptr, row_ptr, ((size_t)n + 1) * 4, hipMemcpyDeviceToDevice));
-    if (arcs > 0) {
-        HIP_OK(hipMemcpy(m->nbr_s, nbr_s.data(), (size_t)arcs * 4, hipMemcpyHostToDevice));
-        HIP_OK(hipMemcpy(d_src, src_s.data(), (size_t)arcs * 4, hipMemcpyHostToDevice));
-        const int64_t threads = arcs * 32;
-        hipLaunchKernelGGL(mfma_pack_r1_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
-                           stream, rel, d_src, arcs, d, m->r1);
+    m->nops = (int64_t)ops.size();
+    HIP_OK(hipMalloc(&m->udesc, std::max<size_t>(1, udesc.size()) * 4));
+    HIP_OK(hipMalloc(&m->ubase, std::max<size_t>(1, ubase.size()) * 4));
+    HIP_OK(hipMemcpy(m->udesc, udesc.data(), udesc.size() * 4, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(m->ubase, ubase.data(), ubase.size() * 4, hipMemcpyHostToDevice));
+    // one spare operand past the end: a block with no units still loads its
+    // (unused) first operand, which for the last blocks is operand nops
+    HIP_OK(hipMalloc(&m->aop, (ops.size() + 1) * 1024));
+    HIP_OK(hipMemset(m->aop, 0, (ops.size() + 1) * 1024));
+    if (!ops.empty()) {
+        int2 *d_ops = nullptr;
+        HIP_OK(hipMalloc(&d_ops, ops.size() * sizeof(int2)));
+        HIP_OK(hipMemcpy(d_ops, ops.data(), ops.size() * sizeof(int2), hipMemcpyHostToDevice));
+        const int64_t threads = (int64_t)ops.size() * 64;
+        hipLaunchKernelGGL(mfma_pack_ops_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
+                           stream, rel, d_ops, (int64_t)ops.size(), d, m->aop);
         HIP_OK(hipGetLastError());
         HIP_OK(hipStreamSynchronize(stream));
+        (void)hipFree(d_ops);
     }
-    (void)hipFree(d_src);
     HIP_OK(hipFuncSetAttribute((const void *)mfma_sweep_kernel,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMSmem));
     HIP_OK(hipHostMalloc((void **)&m->h_cnt, sizeof(int32_t) * 2, hipHostMallocDefault));
@@ -970,15 +975,11 @@ static MArgs make_args(MfmaData &md, int32_t B, const uint64_t *din, uint64_t *d
     A.n = md.n;
     A.d = md.d;
     A.capB = m->capB;
-    A.row_ptr = m->row_ptr;
-    A.nbr_s = m->nbr_s;
     A.deg = m->deg;
-    A.r1 = m->r1;
-    A.bm4 = m->bm4;
-    A.bf4 = m->bf4;
+    A.aop = m->aop;
+    A.udesc = m->udesc;
+    A.ubase = m->ubase;
     A.nblk = m->nblk;
-    A.nw4 = m->nw4;
-    A.narcs = (int32_t)md.arcs;
     A.dom8[0] = m->dom8[0];
     A.dom8[1] = m->dom8[1];
     A.chg = m->chg;
@@ -1138,7 +1139,7 @@ static void collect_stats(MfmaData &md, int32_t B, const std::vector<long long> 
     (void)hipEventElapsedTime(&ms, m->ev0, m->ev1);
     stats->device_ms = ms;
     stats->path = RAC_PATH_MFMA;
-    stats->relation_bytes = md.arcs * 128;
+    stats->relation_bytes = m->nops * 1024;   // the matrix-core operands, read once per state tile
     // matrix-core steps performed: state s took part in steps 1..min(iters, last_k)
     long long mfma_state_steps = 0;
     for (int32_t s = 0; s < B; ++s) mfma_state_steps += std::min(iters[(size_t)s], m->last_k);

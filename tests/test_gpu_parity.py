@@ -231,8 +231,8 @@ def test_dense_create_matches():
 
 MFMA_CASES = [(40, 32, 37, 0.6, 0.3), (45, 10, 130, 0.8, 0.5), (13, 4, 300, 1.0, 0.55),
               (70, 17, 129, 0.4, 0.7), (9, 1, 64, 0.9, 0.0), (100, 32, 257, 0.8, 0.25),
-              # more than 256 blocks of 8 neighbours: the step kernel's
-              # neighbour tables come in chunks of 256 blocks
+              # more than 64 blocks of 8 neighbours: the step kernel's
+              # lane tables of unit descriptors come in chunks of 64 blocks
               (2200, 6, 33, 0.006, 0.35), (2100, 32, 20, 0.004, 0.35)]
 
 
@@ -268,7 +268,7 @@ def test_batch_states_mfma(n, d, B, p1, p2, handoff, monkeypatch):
                                          (100, 32, 257, 0.8, 0.25)])
 def test_batch_states_mfma_split_steps(n, d, B, p1, p2, segments, monkeypatch):
     # every step's neighbour blocks split over 2-4 workgroups per tile (the
-    # segments cross the 256-block chunks of the neighbour tables for n = 2200)
+    # segments cross the 64-block chunks of the lane tables for n = 2200)
     monkeypatch.setenv("RAC_MFMA_SEGMENTS", segments)
     monkeypatch.setenv("RAC_MFMA_HANDOFF", "0")
     inst = gen.model_b(40 + n + d, n, d, p1, p2)
