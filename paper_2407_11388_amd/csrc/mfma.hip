@@ -52,6 +52,7 @@ constexpr int kMSub = 4;          // 32-state sub-tiles per wave
 constexpr int kMS = 32 * kMSub;   // states per workgroup
 constexpr int kMY = 8;            // neighbours per LDS block
 constexpr int kMThreads = 64 * kMW;
+constexpr int kMaxTrackedSteps = 256;   // steps whose re-examined arcs are counted
 
 // 4 bits -> 4 bytes holding 0/1 (bit i of v becomes byte i). The factor places
 // copies of v 7 bits apart, so no two copies overlap and no carry occurs.
@@ -90,6 +91,13 @@ struct MArgs {
     int32_t *slot_map;                // [capB] old slot -> new slot, or -1 when the state stopped
     int32_t *cnt;                     // [2] active counts
     MState *st;                       // [capB]
+    uint32_t *ych;                    // [capB/128][nw32]: bit y of tile t's words is set iff
+                                      // variable y changed in the previous step in some state
+                                      // of state tile t (Proposition 2)
+    int32_t nw32;                     // ceil(n / 32)
+    int32_t skip;                     // 1: steps k >= 2 skip neighbours no state of the tile changed
+    unsigned long long *stepops;      // [kMaxTrackedSteps + 2] arcs re-examined by the states of
+                                      // step k (sum over states of deg of the changed variables)
     int32_t mode, max_sweeps, B, xcd_map;
     long long checks1;                // support checks of step 1: 2m * d * d
     const uint64_t *din;              // [B][n]
@@ -230,12 +238,15 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
     const bool pv = xvs[0];
     const int8_t *din = A.dom8[0];
     const int half = lane >> 5, col = lane & 31;
+    const bool skip_on = A.skip && k > 1;
 
     // Lane tables of a chunk of 64 blocks: lane l holds the unit descriptor
     // and the first operand / unit count of block 64c + l. One copy follows
     // the blocks whose operands are being loaded (one ahead), one the block
     // being multiplied.
-    uint32_t tdI = 0, tbI = 0, tdC = 0, tbC = 0;
+    // A third word per lane (lanes 0..15) holds this state tile's change
+    // bits of the chunk's variables (32 per word: blocks 4l .. 4l+3).
+    uint32_t tdI = 0, tbI = 0, tdC = 0, tbC = 0, tyI = 0xFFFFFFFFu, tyC = 0xFFFFFFFFu;
     int chunkI = -1;
     auto load_tab = [&](int c) {
         const int b = (c << kTabShift) + lane;
@@ -244,6 +255,12 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
         const uint32_t dsc = A.udesc[o], bs = A.ubase[o];
         tdI = ok ? dsc : 0u;
         tbI = ok ? bs : 0u;
+        if (skip_on) {
+            const int w = (c << (kTabShift - 2)) + lane;
+            const bool okw = lane < (1 << (kTabShift - 2)) && w < A.nw32;
+            const uint32_t yw = A.ych[(int64_t)stile * A.nw32 + (okw ? w : 0)];
+            tyI = okw ? yw : 0u;
+        }
     };
     auto lane_word = [&](uint32_t t, int b) -> uint32_t {
         return (uint32_t)__builtin_amdgcn_readlane((int)t, b & 63);
@@ -322,6 +339,7 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
             // the operand pointer (one block ahead, in the same chunk) loaded it
             tdC = tdI;
             tbC = tbI;
+            tyC = tyI;
         }
         const uint32_t desc = lane_word(tdC, blk), wb = lane_word(tbC, blk);
         // the next block's domain tile (stored after this block's products),
@@ -331,8 +349,11 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
         if (more) fetch(blk + 1);
         const uint32_t wn = ops_word(more ? blk + 1 : blk);
 
-        const int nu = (int)(wb >> 27);
+        int nu = (int)(wb >> 27);
         const int nc = (int)((desc >> 24) & 7u), nbe = 2 * nc + (int)((desc >> 27) & 15u);
+        // Proposition 2: after step 1 a block none of whose neighbours changed
+        // in the previous step (in any state of this tile) is skipped
+        if (skip_on && ((lane_word(tyC, (blk & 63) >> 2) >> (8 * (blk & 3))) & 0xFFu) == 0) nu = 0;
         const uint32_t stage_off = (uint32_t)(((blk - blo) & 1) * kBTile) * 16u;
         // a leftover's word has a real flag for its own variable only
         const int lmask = (desc >> 31) ? kFlag1 : kFlag0;
@@ -555,7 +576,14 @@ __global__ __launch_bounds__(1024) void mfma_finalize_kernel(MArgs A, int k) {
     int32_t *nxt = A.act[k & 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int32_t maxs = A.max_sweeps > 0 ? A.max_sweeps : A.n * A.d + 1;
-    if (threadIdx.x == 0) s_base = 0;
+    __shared__ unsigned long long s_ops;
+    if (threadIdx.x == 0) {
+        s_base = 0;
+        s_ops = 0;
+    }
+    // the next step's tile masks start empty (mfma_tile_changed_kernel fills them)
+    for (int64_t i = threadIdx.x; i < (int64_t)A.words / 4 * A.nw32; i += blockDim.x) A.ych[i] = 0u;
+    unsigned long long ops = 0;
     __syncthreads();
     for (int c0 = 0; c0 < nact; c0 += 1024) {
         const int slot = c0 + threadIdx.x;
@@ -568,6 +596,7 @@ __global__ __launch_bounds__(1024) void mfma_finalize_kernel(MArgs A, int k) {
             const bool stop_on_wipe = (A.mode == RAC_STOP_ON_WIPEOUT) && m.wiped;
             if (changed && !stop_on_wipe && k < maxs) {
                 m.checks += (long long)m.degsum * A.d * A.d;
+                ops += m.degsum;
                 keep = true;
             } else {
                 m.iters = k;
@@ -595,7 +624,38 @@ __global__ __launch_bounds__(1024) void mfma_finalize_kernel(MArgs A, int k) {
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) A.cnt[k & 1] = s_base;
+    if (ops) atomicAdd(&s_ops, ops);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        A.cnt[k & 1] = s_base;
+        if (k + 1 <= kMaxTrackedSteps) A.stepops[k + 1] = s_ops;
+    }
+}
+
+// After the gather of step k: for each state tile of step k+1 (new slots) and
+// variable y, whether y changed in step k in some state of the tile (bit y of
+// the tile's words, cleared by the finalise kernel). A wave covers 64
+// consecutive new slots of one variable, all in one tile.
+__global__ void mfma_tile_changed_kernel(MArgs A, int k) {
+    const int nnext = A.cnt[k & 1];
+    const int64_t s64 = ((int64_t)nnext + 63) / 64 * 64;
+    const int64_t total = s64 * A.n;
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const bool in = i < total;
+        const int32_t y = in ? (int32_t)(i / s64) : 0;
+        const int32_t j = in ? (int32_t)(i - (int64_t)y * s64) : 0;
+        bool c = false;
+        if (in && j < nnext) {
+            const int32_t old = A.prev_slot[k & 1][j];
+            c = (A.chg[(int64_t)y * A.words + (old >> 5)] >> (old & 31)) & 1u;
+        }
+        const uint64_t m = __ballot(c);
+        if (lane == 0 && m)
+            atomicOr(A.ych + (int64_t)(j / kMS) * A.nw32 + (y >> 5), 1u << (y & 31));
+    }
 }
 
 // After step k: the domains of the states that go on move to their new slots
@@ -732,7 +792,8 @@ struct MfmaImpl {
     int32_t nblk = 0;
     int32_t capB = 0, words = 0;
     int8_t *dom8[2] = {nullptr, nullptr};
-    uint32_t *chg = nullptr, *wipe = nullptr, *kill = nullptr;
+    uint32_t *chg = nullptr, *wipe = nullptr, *kill = nullptr, *ych = nullptr;
+    unsigned long long *stepops = nullptr;
     int32_t *act[2] = {nullptr, nullptr};
     int32_t *prev_slot[2] = {nullptr, nullptr};
     int32_t *slot_map = nullptr;
@@ -770,6 +831,8 @@ void mfma_release(MfmaData &md) {
     mfree(m->chg);
     mfree(m->kill);
     mfree(m->wipe);
+    mfree(m->ych);
+    mfree(m->stepops);
     mfree(m->act[0]);
     mfree(m->act[1]);
     mfree(m->prev_slot[0]);
@@ -926,6 +989,8 @@ static int ensure_capacity(MfmaData &md, int32_t B) {
     mfree(m->chg);
     mfree(m->kill);
     mfree(m->wipe);
+    mfree(m->ych);
+    mfree(m->stepops);
     mfree(m->act[0]);
     mfree(m->act[1]);
     mfree(m->prev_slot[0]);
@@ -948,6 +1013,8 @@ static int ensure_capacity(MfmaData &md, int32_t B) {
     HIP_OK(hipMalloc(&m->kill, (size_t)md.n * capB * 4));
     HIP_OK(hipMemset(m->kill, 0, (size_t)md.n * capB * 4));
     HIP_OK(hipMalloc(&m->wipe, (size_t)md.n * words * 4));
+    HIP_OK(hipMalloc(&m->ych, (size_t)(capB / kMS) * ((md.n + 31) / 32) * 4));
+    HIP_OK(hipMalloc(&m->stepops, (size_t)(kMaxTrackedSteps + 2) * 8));
     HIP_OK(hipMalloc(&m->act[0], (size_t)capB * 4));
     HIP_OK(hipMalloc(&m->act[1], (size_t)capB * 4));
     HIP_OK(hipMalloc(&m->prev_slot[0], (size_t)capB * 4));
@@ -986,6 +1053,13 @@ static MArgs make_args(MfmaData &md, int32_t B, const uint64_t *din, uint64_t *d
     A.kill = m->kill;
     A.wipe = m->wipe;
     A.words = m->words;   // row stride of the mask matrices (capacity / 32)
+    A.ych = m->ych;
+    A.nw32 = (md.n + 31) / 32;
+    A.stepops = m->stepops;
+    {
+        const char *e = getenv("RAC_MFMA_SKIP");   // 0: every step re-examines every arc
+        A.skip = (e && *e) ? (atoi(e) != 0) : 1;
+    }
     A.act[0] = m->act[0];
     A.act[1] = m->act[1];
     A.prev_slot[0] = m->prev_slot[0];
@@ -1060,6 +1134,12 @@ static int run_steps(MfmaData &md, const MArgs &A, bool profile, int32_t handoff
             hipLaunchKernelGGL(mfma_reduce_kernel, dim3((A.B + 31) / 32), dim3(256), 0, stream, A, k);
             hipLaunchKernelGGL(mfma_finalize_kernel, dim3(1), dim3(1024), 0, stream, A, k);
             hipLaunchKernelGGL(mfma_gather_kernel, dim3(init_blocks), dim3(256), 0, stream, A, k);
+            if (A.skip) {
+                const int64_t thr = ((int64_t)A.B + 63) / 64 * 64 * A.n;
+                hipLaunchKernelGGL(mfma_tile_changed_kernel,
+                                   dim3((unsigned)std::min<int64_t>(4096, (thr + 255) / 256)), dim3(256),
+                                   0, stream, A, k);
+            }
         }
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpyAsync(m->h_cnt, A.cnt + (k & 1), 4, hipMemcpyDeviceToHost, stream));
@@ -1126,7 +1206,8 @@ static int rc_of(int32_t v) {
 }
 
 static void collect_stats(MfmaData &md, int32_t B, const std::vector<long long> &checks,
-                          const std::vector<int32_t> &iters, rac_stats *stats) {
+                          const std::vector<int32_t> &iters,
+                          const std::vector<unsigned long long> &stepops, rac_stats *stats) {
     MfmaImpl *m = impl(md);
     memset(stats, 0, sizeof(*stats));
     int32_t max_it = 0;
@@ -1140,10 +1221,13 @@ static void collect_stats(MfmaData &md, int32_t B, const std::vector<long long> 
     stats->device_ms = ms;
     stats->path = RAC_PATH_MFMA;
     stats->relation_bytes = m->nops * 1024;   // the matrix-core operands, read once per state tile
-    // matrix-core steps performed: state s took part in steps 1..min(iters, last_k)
-    long long mfma_state_steps = 0;
-    for (int32_t s = 0; s < B; ++s) mfma_state_steps += std::min(iters[(size_t)s], m->last_k);
-    stats->algo_ops = 2ll * md.d * md.d * md.arcs * mfma_state_steps;
+    // the matrix-core steps' work on the arcs they re-examine (Proposition 2):
+    // step 1 every arc of every state, step k >= 2 the arcs into the
+    // variables each active state changed in step k-1
+    long long arcs_examined = md.arcs * (long long)B;
+    const int32_t kt = std::min(m->last_k, kMaxTrackedSteps);
+    for (int32_t k = 2; k <= kt; ++k) arcs_examined += (long long)stepops[(size_t)k];
+    stats->algo_ops = 2ll * md.d * md.d * arcs_examined;
     if (m->profiled) {
         // the step kernels that had work: steps 1..min(max iters, last step)
         const int32_t kl = std::min(std::min(max_it, m->last_k), 64);
@@ -1171,7 +1255,9 @@ int mfma_collect(MfmaData &md, rac_stats *stats) {
         hc[(size_t)s] = hs[(size_t)s].checks;
         hi[(size_t)s] = hs[(size_t)s].iters;
     }
-    collect_stats(md, B, hc, hi, stats);
+    std::vector<unsigned long long> ops((size_t)kMaxTrackedSteps + 2, 0);
+    HIP_OK(hipMemcpy(ops.data(), m->stepops, ops.size() * 8, hipMemcpyDeviceToHost));
+    collect_stats(md, B, hc, hi, ops, stats);
     return rc_of(hrc);
 }
 

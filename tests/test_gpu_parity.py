@@ -284,6 +284,60 @@ def test_batch_states_mfma_split_steps(n, d, B, p1, p2, segments, monkeypatch):
     net.close()
 
 
+def frontier_states(inst, doms, seed):
+    """States one removal away from arc consistency: the closure of each
+    state (the oracle's), then one value of one variable with at least two
+    values removed (a search node just after its branching decision). After
+    the first step only a few variables change."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    rel = inst.rel_u8()
+    out = []
+    for s in range(doms.shape[0]):
+        dac, status, _, _ = oracle.ac3(inst.n, inst.d, inst.edges, rel, masks_to_u8(doms[s], inst.d))
+        m = u8_to_masks(dac)
+        if status == 0:
+            sizes = np.array([bin(int(v)).count("1") for v in m])
+            cand = np.flatnonzero(sizes >= 2)
+            if len(cand):
+                x = int(rng.choice(cand))
+                m[x] &= ~(np.uint64(1) << np.uint64(int(m[x]).bit_length() - 1))
+        out.append(m)
+    return np.array(out, dtype=np.uint64)
+
+
+@pytest.mark.parametrize("skip", ["0", "1"])
+@pytest.mark.parametrize("n,d,B,p1,p2", [(100, 32, 130, 0.8, 0.25), (160, 12, 130, 0.5, 0.45),
+                                         (2200, 6, 33, 0.006, 0.35)])
+def test_batch_states_mfma_prop2_frontier(n, d, B, p1, p2, skip, monkeypatch):
+    # Proposition 2 inside the matrix-core step: with skip=1 a tile of states
+    # re-examines only the neighbour blocks some of its states changed in the
+    # previous step; skip=0 re-examines every arc. Both must equal the oracle.
+    monkeypatch.setenv("RAC_MFMA_SKIP", skip)
+    monkeypatch.setenv("RAC_MFMA_HANDOFF", "0")
+    inst = gen.model_b(50 + n + d, n, d, p1, p2)
+    doms, _ = gen.partial_assign_states(51 + B, n, d, B, min(n, 12))
+    doms = frontier_states(inst, doms, 52 + n)
+    rel = inst.rel_u8()
+    say(f"[gpu] batch mfma frontier skip={skip} n={n} d={d} B={B}")
+    for mode in (0, 1):
+        net = rac.Net.from_u8(n, d, inst.edges, rel, path=rac.PATH_MFMA, mode=mode)
+        got, iters, status = net.enforce_batch(doms)
+        st = net.stats()
+        assert st.path == rac.PATH_MFMA
+        total = 0
+        for s in range(B):
+            exp, e_it, e_st, e_ch, _ = oracle_expect(n, d, inst.edges, rel, doms[s], mode)
+            assert np.array_equal(got[s], exp), f"state {s} (mode {mode})"
+            assert iters[s] == e_it and status[s] == e_st, f"state {s} (mode {mode})"
+            total += e_ch
+        assert st.support_checks == total
+        # the matrix-core work counts only re-examined arcs: step 1 every arc
+        # of every state, later steps at most every arc of the active states
+        assert 2 * d * d * inst.m * 2 * B <= st.algo_ops <= 2 * d * d * 2 * inst.m * int(iters.sum())
+        net.close()
+
+
 def test_mfma_rejects_wide_domains():
     inst = gen.model_b(3, 10, 40, 0.5, 0.3)
     net = rac.Net.from_instance(inst, path=rac.PATH_MFMA)
