@@ -200,6 +200,8 @@ def parse():
     ap.add_argument("--table1", action="store_true",
                     help="only run the Table 1-style MAC-search grid (steps and AC-3 revisions "
                          "per assignment, time per node) and print it as one JSON line")
+    ap.add_argument("--table1-out", default="", metavar="PATH",
+                    help="with --table1: also write the table as markdown to PATH")
     ap.add_argument("--search-only", action="store_true",
                     help="run only the two batched MAC searches (one JSON line)")
     ap.add_argument("--no-search", action="store_true",
@@ -372,44 +374,93 @@ def search_lines(one_node: bool = True):
     return out
 
 
-def table1_grid(oracle_nodes: int = 100, gpu_nodes: int = 20000):
-    """Table 1 analogue: MAC search on model-B instances over n x density
-    (d = 10, p2 = 0.3; the paper's own instances and heuristic are not
-    published). Per grid point: the GPU search (batch SEARCH_BATCH, up to `gpu_nodes`
-    nodes): recurrence steps per enforcement and time per node; the oracle's
-    search on its first `oracle_nodes` nodes (depth-first): recurrence steps
-    and AC-3 revisions per enforcement."""
+TABLE1_N = (100, 250, 500, 750, 1000)
+TABLE1_DENSITY = (0.1, 0.25, 0.5, 0.75, 1.0)
+TABLE1_D, TABLE1_P2 = 10, 0.3
+
+
+def table1_instance(n: int, p1: float):
+    """The model-B instance of one Table 1 grid point (d = 10, p2 = 0.3: the
+    paper gives neither its domain size nor its tightness)."""
+    from paper_2407_11388_amd import gen
+    return gen.model_b(1000 + n + int(round(100 * p1)), n, TABLE1_D, p1, TABLE1_P2)
+
+
+def table1_grid(gpu_nodes: int = 20000, oracle_cells: float = 4e8):
+    """Table 1 on the paper's grid (n in {100, 250, 500, 750, 1000} x density in
+    {0.1, 0.25, 0.5, 0.75, 1.0}; its 25 instances are not published, so
+    model-B stand-ins with d = 10, p2 = 0.3). Per grid point: the GPU MAC
+    search from full domains (batch SEARCH_BATCH, up to `gpu_nodes` nodes,
+    checked before each round): recurrence steps per enforcement (an
+    enforcement follows every assignment: the paper's #Recurrence) and time
+    per node; beside it the oracle's depth-first search on its first nodes
+    (as many as take about `oracle_cells` relation-cell visits, between 5 and
+    100), run from a pool of host threads: recurrence steps and AC-3
+    revisions per enforcement (AC-3 from scratch at every node, an upper
+    bound on the incremental AC-3 the paper times)."""
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
 
     import oracle.search as osearch
-    from paper_2407_11388_amd import gen, rac
+    from paper_2407_11388_amd import rac
+
+    cells = [(n, p1) for n in TABLE1_N for p1 in TABLE1_DENSITY]
+
+    def oracle_cell(cell):
+        n, p1 = cell
+        inst = table1_instance(n, p1)
+        rel = inst.rel_u8()
+        arcs = 2 * int(inst.edges.shape[0])
+        nodes = int(max(5, min(100, oracle_cells / max(1, arcs * TABLE1_D * TABLE1_D))))
+        t0 = time.perf_counter()
+        o = osearch.mac_search(n, TABLE1_D, inst.edges, rel, np.ones((n, TABLE1_D), np.uint8),
+                               stop_after=nodes)
+        o_s = time.perf_counter() - t0
+        return dict(kind="oracle", nodes=o["nodes"], complete=int(o["complete"]),
+                    steps_per_node=o["steps"] / o["nodes"],
+                    ac3_revisions_per_node=o["revisions"] / o["nodes"],
+                    us_per_node=o_s * 1e6 / o["nodes"])
+
+    pool = ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1))
+    futs = {c: pool.submit(oracle_cell, c) for c in cells}
     rows = []
-    for n in (100, 200, 400):
-        for p1 in (0.1, 0.3, 0.5, 1.0):
-            d, p2 = 10, 0.3
-            inst = gen.model_b(1000 + n + int(100 * p1), n, d, p1, p2)
-            rel = inst.rel_u8()
-            net = rac.Net.from_u8(n, d, inst.edges, rel)
-            root = np.full(n, (1 << d) - 1, dtype=np.uint64)
-            net.search(root, batch=SEARCH_BATCH, max_nodes=2000)   # warm-up
-            res, _ = net.search(root, batch=SEARCH_BATCH, max_nodes=gpu_nodes)
-            net.close()
-            t0 = time.perf_counter()
-            o = osearch.mac_search(n, d, inst.edges, rel, np.ones((n, d), np.uint8),
-                                   stop_after=oracle_nodes)
-            o_s = time.perf_counter() - t0
-            rows.append(dict(
-                n=n, p1=p1, d=d, p2=p2, edges=int(inst.edges.shape[0]),
-                gpu=dict(nodes=int(res.nodes), complete=int(res.complete),
-                         solutions=int(res.solutions),
-                         steps_per_node=res.sweeps / res.nodes,
-                         us_per_node=res.search_ms * 1e3 / res.nodes),
-                cpu_baseline=dict(kind="oracle", nodes=o["nodes"],
-                                  steps_per_node=o["steps"] / o["nodes"],
-                                  ac3_revisions_per_node=o["revisions"] / o["nodes"],
-                                  us_per_node=o_s * 1e6 / o["nodes"])))
-            print(f"[table1] n={n} p1={p1}: {rows[-1]}", file=sys.stderr, flush=True)
+    for (n, p1) in cells:
+        inst = table1_instance(n, p1)
+        net = rac.Net.from_bits(n, TABLE1_D, inst.edges, inst.rel)
+        root = np.full(n, (1 << TABLE1_D) - 1, dtype=np.uint64)
+        net.search(root, batch=SEARCH_BATCH, max_nodes=2000)   # warm-up
+        res, _ = net.search(root, batch=SEARCH_BATCH, max_nodes=gpu_nodes)
+        net.close()
+        rows.append(dict(
+            n=n, p1=p1, d=TABLE1_D, p2=TABLE1_P2, edges=int(inst.edges.shape[0]),
+            gpu=dict(nodes=int(res.nodes), complete=int(res.complete), solutions=int(res.solutions),
+                     steps_per_node=res.sweeps / res.nodes,
+                     us_per_node=res.search_ms * 1e3 / res.nodes)))
+        print(f"[table1] n={n} p1={p1}: gpu {rows[-1]['gpu']}", file=sys.stderr, flush=True)
+    for r in rows:
+        r["cpu_baseline"] = futs[(r["n"], r["p1"])].result()
+    pool.shutdown()
     return rows
+
+
+def table1_markdown(rows, command: str) -> str:
+    """Table 1 rows as a short markdown summary."""
+    out = ["# Table 1 on the paper's grid: MAC search on model-B stand-ins (d = 10, p2 = 0.3)", "",
+           "Command (from the repository root): `" + command + "`", "",
+           "Steps = recurrence steps per enforcement (one enforcement per assignment: the paper's "
+           "#Recurrence). GPU: batched search (4096 open nodes per round) from full domains, up to "
+           "20,000 nodes. Oracle: its depth-first search on its first nodes, AC-3 from scratch at every "
+           "node (revisions are an upper bound on an incremental AC-3's).", "",
+           "| n | density | edges | GPU nodes | GPU steps / node | µs / node (GPU) | oracle nodes | "
+           "oracle steps / node | AC-3 revisions / node | µs / node (oracle) |",
+           "|---|---|---|---|---|---|---|---|---|---|"]
+    for r in rows:
+        g, c = r["gpu"], r["cpu_baseline"]
+        out.append(f"| {r['n']} | {r['p1']} | {r['edges']} | {g['nodes']}"
+                   f"{'' if g['complete'] else ' (capped)'} | {g['steps_per_node']:.3f} | "
+                   f"{g['us_per_node']:.2f} | {c['nodes']}{'' if c['complete'] else ' (first)'} | "
+                   f"{c['steps_per_node']:.3f} | {c['ac3_revisions_per_node']:.0f} | {c['us_per_node']:.0f} |")
+    return "\n".join(out) + "\n"
 
 
 def main():
@@ -432,7 +483,12 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.table1:
-        print(json.dumps(dict(table1=table1_grid())), flush=True)
+        rows = table1_grid()
+        print(json.dumps(dict(table1=rows)), flush=True)
+        if args.table1_out:
+            with open(args.table1_out, "w") as f:
+                f.write(table1_markdown(rows, "python bench.py --table1 --table1-out "
+                                              "profiles/table1_grid_modelb_d10_p03.md"))
         return
     if args.search_only:
         print(json.dumps(dict(search=search_lines(one_node=False))), flush=True)

@@ -163,3 +163,25 @@ def test_bench_search_workloads(which):
     else:
         assert [int(v).bit_length() - 1 for v in sol] == exp["best"].tolist()
     net.close()
+
+
+@pytest.mark.parametrize("n,p1", [(100, 0.5), (100, 0.75), (100, 1.0)])
+def test_table1_cells_complete(n, p1):
+    # Cells of the Table 1 grid (model-B stand-ins, d = 10, p2 = 0.3) whose
+    # whole search tree the oracle explores in seconds: the GPU search's
+    # recurrence steps per assignment (and nodes, failures, solutions) equal
+    # the oracle's, at the batch the grid is run with.
+    import bench
+    inst = bench.table1_instance(n, p1)
+    d = bench.TABLE1_D
+    rel = inst.rel_u8()
+    say(f"[gpu] table 1 cell n={n} density={p1}: oracle")
+    exp = mac_search(n, d, inst.edges, rel, np.ones((n, d), np.uint8))
+    net = rac.Net.from_u8(n, d, inst.edges, rel)
+    say(f"[gpu] table 1 cell n={n} density={p1}: batch {bench.SEARCH_BATCH}")
+    res, _ = net.search(full_masks(n, d), batch=bench.SEARCH_BATCH)
+    net.close()
+    assert res.complete == 1 and exp["complete"]
+    assert (res.solutions, res.nodes, res.failures, res.sweeps) == \
+        (exp["solutions"], exp["nodes"], exp["failures"], exp["steps"])
+    assert res.sweeps / res.nodes == exp["steps"] / exp["nodes"]   # steps per assignment
