@@ -570,6 +570,7 @@ def main():
             config=dict(workload="batch-states: model-B n=1000 d=32 p1=0.8 p2=0.25, "
                                  f"B={B} partial-assignment states (0..20 singletons)",
                         B=B, n=n, d=d, arcs=int(2 * inst.m), path=path,
+                        tuned_from=rac.TUNE_SOURCES.get(st.tune_source, str(st.tune_source)),
                         mode="run-to-fixpoint"),
             fixpoints_per_s=fix_s,
             plain_loop=dict(fixpoints_per_s=plain_fix_s, states=P, path="bits",

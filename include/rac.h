@@ -87,7 +87,12 @@ typedef struct rac_options {
     int32_t item_bytes;   /* 0: autotuned; else target relation bytes per work item */
     int32_t profile;      /* 1: time every launch of the dominant kernel with HIP events
                              (rac_stats.kernel_ms / kernel_launches); 0 (default): off */
-    int32_t reserved[2];  /* must be zero */
+    int32_t tune;         /* with path RAC_PATH_AUTO and item_bytes 0, how the path and work-item
+                             size are chosen: 0 (default) the autotuner's table for the call's
+                             shape, measured on the call's own inputs the first time a shape is
+                             seen (the environment variable RAC_TUNE=rules or =measure overrides
+                             this default); 1: fixed rules, no measurement; 2: measure again */
+    int32_t reserved;     /* must be zero */
 } rac_options;
 
 /* Per-call counters of the last enforcement on a net or group. */
@@ -107,7 +112,9 @@ typedef struct rac_stats {
     int32_t item_bytes;      /* work-item size used by the bit / int8 path */
     float first_kernel_ms;   /* with options.profile: duration of the dominant kernel's
                                 launch of step 1 (every arc of every state re-examined) */
-    int32_t reserved;
+    int32_t tune_source;     /* where the call's path and item size came from: 0 fixed rules
+                                or the caller's options, 1 the table shipped with the library,
+                                2 the user's table file, 3 measured by this call */
 } rac_stats;
 
 /* Fills *opt with the defaults. */

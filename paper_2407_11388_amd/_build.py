@@ -12,7 +12,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(PKG, "librac.so")
 
-SOURCES = ["sweep.hip", "mfma.hip", "search.hip", "rac_host.hip"]
+SOURCES = ["sweep.hip", "mfma.hip", "search.hip", "tune.hip", "rac_host.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

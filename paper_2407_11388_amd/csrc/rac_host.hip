@@ -14,6 +14,7 @@
 #include "rac.h"
 #include "rac_internal.h"
 #include "rac_mfma.h"
+#include "rac_tune.h"
 
 using namespace rac;
 
@@ -77,8 +78,8 @@ static int check_options(const rac_options *o) {
         return set_error(RAC_EINVAL, "options.path out of range");
     if (o->item_bytes < 0) return set_error(RAC_EINVAL, "options.item_bytes must be >= 0");
     if (o->profile != 0 && o->profile != 1) return set_error(RAC_EINVAL, "options.profile must be 0 or 1");
-    for (int i = 0; i < 2; ++i)
-        if (o->reserved[i] != 0) return set_error(RAC_EINVAL, "options.reserved must be zero");
+    if (o->tune < 0 || o->tune > 2) return set_error(RAC_EINVAL, "options.tune must be 0, 1 or 2");
+    if (o->reserved != 0) return set_error(RAC_EINVAL, "options.reserved must be zero");
     return RAC_OK;
 }
 
@@ -238,6 +239,7 @@ struct rac_net {
     Runner run;
     rac_stats last{};
     bool pending = false;      // a device-pointer call awaiting rac_sync_status
+    int32_t tune_source = 0;   // of the last call (rac_stats.tune_source)
 };
 
 struct rac_group {
@@ -1048,10 +1050,6 @@ static int32_t stage_vars_for(int64_t max_n) {
     return (int32_t)std::min<int64_t>(max_n, kStageMax);
 }
 
-static int pick_path(const rac_net *net, int32_t B, int32_t requested) {
-    if (requested != RAC_PATH_AUTO) return requested;
-    return mfma_auto_choice(net->d, net->n, net->arcs, B) ? RAC_PATH_MFMA : RAC_PATH_BITS;
-}
 
 // Bit / int8 path for B states already in r.din (host waits between rounds).
 // item_bytes > 0 fixes the work-item size (else the default for B states).
@@ -1100,19 +1098,113 @@ static int collect_bits(rac_net *net, int32_t B, int32_t path, uint64_t *dom, in
     return rc_from_device(hrc);
 }
 
-extern "C" int rac_enforce(rac_net *net, uint64_t *dom, const int32_t *changed, int32_t n_changed,
-                           int32_t *iters, int32_t *status) {
-    if (!net || !dom) return set_error(RAC_EINVAL, "net or dom is NULL");
-    if (changed && n_changed < 0) return set_error(RAC_EINVAL, "n_changed < 0");
-    RAC_TRY(check_domains(dom, net->n, net->d));
-    HIP_TRY(hipSetDevice(net->device));
-    RAC_TRY(settle(net));
-    int32_t path = net->opt.path;
-    if (path == RAC_PATH_AUTO || path == RAC_PATH_MFMA) path = RAC_PATH_BITS;
-    RAC_TRY(ensure_path(net, path, call_target(net, 1)));
+// ---------------------------------------------------------------------------
+// autotuner: path and work-item size per call
+// ---------------------------------------------------------------------------
+
+struct CallChoice {
+    int32_t path = RAC_PATH_BITS;
+    int32_t item_scale_log2 = 0;   // work items of 2^s times the default size
+    int32_t handoff = -1;          // matrix-core path: -1 the default threshold
+    int32_t source = kSourceRules;
+};
+
+static int effective_tune_mode(const rac_options &o) {
+    if (o.tune == 1) return kTuneRules;
+    if (o.tune == 2) return kTuneMeasure;
+    return tune_mode();
+}
+
+// Relation bytes of one state's full sweep on a path (as ensure_path lays
+// them out), for the default item size of a call.
+static int64_t path_rows_bytes(const rac_net *net, int32_t path) {
+    if (path == RAC_PATH_INT8) return net->arcs * net->d * round_up(net->d, 16);
+    const int64_t qpa = net->d <= 32 ? round_up(net->d, 4) / 4 : round_up(net->d, 8) / 2;
+    return net->groups * qpa * 1024;
+}
+
+// The item size argument of ensure_path / run_states for B states.
+static int32_t choice_items(const rac_net *net, const CallChoice &c, int32_t B) {
+    if (net->opt.item_bytes > 0) return net->opt.item_bytes;
+    if (c.item_scale_log2 == 0) return 0;   // the default for B states
+    const int64_t t = (int64_t)default_item_bytes(net->device, path_rows_bytes(net, c.path) *
+                                                   std::max<int32_t>(1, B));
+    const int64_t sc = c.item_scale_log2 > 0 ? t << c.item_scale_log2 : t >> -c.item_scale_log2;
+    return (int32_t)std::max<int64_t>(4096, std::min<int64_t>(sc, 16 << 20));
+}
+
+// The choice for a call: the caller's options, else the tuned table, else
+// the fixed rules. *measure: the shape is not in the table and may be measured.
+static CallChoice lookup_choice(rac_net *net, int kind, int32_t B, bool *measure) {
+    CallChoice c;
+    *measure = false;
+    const int32_t req = net->opt.path;
+    if (req != RAC_PATH_AUTO || net->opt.item_bytes > 0) {
+        c.path = kind == kTuneSingle ? (req == RAC_PATH_INT8 ? RAC_PATH_INT8 : RAC_PATH_BITS)
+                                     : (req == RAC_PATH_AUTO ? RAC_PATH_BITS : req);
+        if (kind == kTuneBatch && req == RAC_PATH_AUTO)
+            c.path = mfma_auto_choice(net->d, net->n, net->arcs, B) ? RAC_PATH_MFMA : RAC_PATH_BITS;
+        return c;
+    }
+    // fixed rules: bit rows for one state; the matrix cores for many states of
+    // a dense network with d <= 32
+    c.path = kind == kTuneBatch && mfma_auto_choice(net->d, net->n, net->arcs, B) ? RAC_PATH_MFMA
+                                                                                  : RAC_PATH_BITS;
+    const int mode = effective_tune_mode(net->opt);
+    if (mode == kTuneRules) return c;
+    TuneChoice t;
+    if (mode != kTuneMeasure && tune_lookup(tune_key(kind, net->n, net->d, net->arcs, B), &t) &&
+        (t.path != RAC_PATH_MFMA || net->d <= 32) && (t.path != RAC_PATH_INT8 || net->d <= 32) &&
+        (kind == kTuneBatch || t.path != RAC_PATH_MFMA)) {
+        c.path = t.path;
+        c.item_scale_log2 = t.item_scale_log2;
+        c.handoff = t.handoff;
+        c.source = t.source;
+        return c;
+    }
+    *measure = true;
+    return c;
+}
+
+static std::vector<CallChoice> tune_candidates(const rac_net *net, int kind, int32_t B) {
+    std::vector<CallChoice> v;
+    auto add = [&](int32_t path, int32_t s, int32_t h) {
+        CallChoice c;
+        c.path = path;
+        c.item_scale_log2 = s;
+        c.handoff = h;
+        c.source = kSourceMeasured;
+        v.push_back(c);
+    };
+    add(RAC_PATH_BITS, 0, -1);
+    add(RAC_PATH_BITS, 2, -1);
+    if (kind == kTuneSingle) add(RAC_PATH_BITS, -2, -1);
+    if (net->d <= 32) add(RAC_PATH_INT8, 0, -1);
+    if (kind == kTuneBatch && net->d <= 32 && B >= 8) {
+        add(RAC_PATH_MFMA, 0, 32);
+        add(RAC_PATH_MFMA, 0, 0);
+    }
+    return v;
+}
+
+static void remember(rac_net *net, int kind, int32_t B, const CallChoice &c, double ms) {
+    TuneChoice t;
+    t.path = c.path;
+    t.item_scale_log2 = c.item_scale_log2;
+    t.handoff = c.handoff;
+    t.ms = ms;
+    tune_store(tune_key(kind, net->n, net->d, net->arcs, B), t);
+}
+
+// One state on the bit or int8 path with a given choice (host buffers).
+static int enforce_one(rac_net *net, const uint64_t *din, uint64_t *dout, const int32_t *changed,
+                       int32_t n_changed, int32_t *iters, int32_t *status, const CallChoice &c) {
+    const int32_t path = c.path == RAC_PATH_INT8 ? RAC_PATH_INT8 : RAC_PATH_BITS;
+    const int32_t items = choice_items(net, c, 1);
+    RAC_TRY(ensure_path(net, path, items > 0 ? items : call_target(net, 1)));
     RAC_TRY(prepare_net_runner(net, 1, path == RAC_PATH_INT8 ? net->i8 : net->bits));
     Runner &r = net->run;
-    memcpy(r.h_dom, dom, (size_t)net->n * 8);
+    memcpy(r.h_dom, din, (size_t)net->n * 8);
     HIP_TRY(hipMemcpyAsync(r.din, r.h_dom, (size_t)net->n * 8, hipMemcpyHostToDevice, net->stream));
     const uint8_t *d_changed = nullptr;
     long long arcs1 = 0;
@@ -1131,29 +1223,66 @@ extern "C" int rac_enforce(rac_net *net, uint64_t *dom, const int32_t *changed, 
         d_changed = r.changed;
         arcs1 = degs;
     }
-    RAC_TRY(run_states(net, 1, path, d_changed, arcs1, true, true));
-    return collect_bits(net, 1, path, dom, iters, status);
+    RAC_TRY(run_states(net, 1, path, d_changed, arcs1, true, true, items));
+    RAC_TRY(collect_bits(net, 1, path, dout, iters, status));
+    net->last.tune_source = c.source;
+    return RAC_OK;
+}
+
+extern "C" int rac_enforce(rac_net *net, uint64_t *dom, const int32_t *changed, int32_t n_changed,
+                           int32_t *iters, int32_t *status) {
+    if (!net || !dom) return set_error(RAC_EINVAL, "net or dom is NULL");
+    if (changed && n_changed < 0) return set_error(RAC_EINVAL, "n_changed < 0");
+    RAC_TRY(check_domains(dom, net->n, net->d));
+    HIP_TRY(hipSetDevice(net->device));
+    RAC_TRY(settle(net));
+    bool measure = false;
+    CallChoice c = lookup_choice(net, kTuneSingle, 1, &measure);
+    if (measure) {
+        // every candidate on this call's own state (identical results): one
+        // untimed run (packing, item tables), then the best of two timed ones
+        std::vector<uint64_t> in(dom, dom + net->n), out((size_t)net->n);
+        double best = 1e30;
+        for (const CallChoice &cand : tune_candidates(net, kTuneSingle, 1)) {
+            double t = 1e30;
+            for (int rep = 0; rep < 3; ++rep) {
+                const auto t0 = std::chrono::steady_clock::now();
+                const int rc = enforce_one(net, in.data(), out.data(), changed, n_changed, nullptr,
+                                           nullptr, cand);
+                if (rc != RAC_OK && rc != RAC_ENOTCONVERGED) return rc;
+                if (rep > 0)
+                    t = std::min(t, std::chrono::duration<double, std::milli>(
+                                        std::chrono::steady_clock::now() - t0).count());
+            }
+            if (t < best) {
+                best = t;
+                c = cand;
+            }
+        }
+        remember(net, kTuneSingle, 1, c, best);
+    }
+    return enforce_one(net, dom, dom, changed, n_changed, iters, status, c);
 }
 
 // States still active when at most this many remain leave the matrix-core
 // path and finish on the bit-row path, whose incremental steps
 // touch only arcs into changed variables.
-static int32_t mfma_handoff_threshold() {
+static int32_t mfma_handoff_threshold(int32_t tuned) {
     const char *e = getenv("RAC_MFMA_HANDOFF");
     if (e) return std::max(0, atoi(e));
-    return 32;
+    return tuned >= 0 ? tuned : 32;
 }
 
 // The batched matrix-core path: matrix-core steps while many states are
 // active, then the stragglers on the bit-row path (continuing from D^(k)
 // with @changed = the variables step k changed, Proposition 2).
 static int run_mfma(rac_net *net, int32_t B, const uint64_t *d_in, uint64_t *d_out,
-                    int32_t *d_it, int32_t *d_st, hipStream_t s) {
+                    int32_t *d_it, int32_t *d_st, hipStream_t s, int32_t handoff) {
     RAC_TRY(mfma_ensure(net->mfma, net->n, net->d, net->arcs, net->row_ptr, net->nbr, net->deg,
                         net->rel, net->arc_src, net->h_row_ptr, net->stream));
     int32_t k = 0, P = 0;
     RAC_TRY(mfma_start(net->mfma, B, d_in, d_out, net->opt.mode, net->opt.max_sweeps,
-                       net->opt.profile, mfma_handoff_threshold(), s, &k, &P));
+                       net->opt.profile, handoff, s, &k, &P));
     if (P > 0) {
         RAC_TRY(ensure_path(net, RAC_PATH_BITS, call_target(net, P)));
         PathData &pd = net->bits;
@@ -1370,6 +1499,81 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
     return finish();
 }
 
+// Enqueues B states of one net (device buffers) on stream s with a choice of
+// path; the call is then pending on the net (rac_sync_status waits for it).
+static int enqueue_batch(rac_net *net, int32_t B, const uint64_t *d_in, uint64_t *d_out,
+                         int32_t *d_it, int32_t *d_st, hipStream_t s, const CallChoice &c) {
+    net->tune_source = c.source;
+    if (c.path == RAC_PATH_MFMA) {
+        RAC_TRY(run_mfma(net, B, d_in, d_out, d_it, d_st, s, mfma_handoff_threshold(c.handoff)));
+        net->pending = true;
+        net->last.path = RAC_PATH_MFMA;
+        return RAC_OK;
+    }
+    const int32_t items = choice_items(net, c, B);
+    RAC_TRY(ensure_path(net, c.path, items > 0 ? items : call_target(net, B)));
+    PathData &pd = c.path == RAC_PATH_INT8 ? net->i8 : net->bits;
+    RAC_TRY(prepare_net_runner(net, B, pd));
+    Runner &r = net->run;
+    Launch L = base_launch(r, B, net->opt);
+    L.nets = pd.d_desc;
+    L.uniform_n = net->n;   // every problem an instance of this net, at s*n
+    L.stage_vars = stage_vars_for(net->n);
+    L.din = d_in;
+    L.dout = d_out;
+    L.iters_out = d_it;
+    L.status_out = d_st;
+    RAC_TRY(launch_fixpoint(r, net->device, s, L, (int64_t)B * net->n, (int64_t)pd.nitems * B,
+                            step_cap(net->opt, (int64_t)net->n * net->d), net->opt.use_graph != 0,
+                            net->opt.profile != 0));
+    net->pending = true;
+    net->last.path = c.path;
+    net->last.item_bytes = pd.item_bytes;
+    net->last.relation_bytes = (int64_t)pd.rows_bytes;
+    return RAC_OK;
+}
+
+// Measures every candidate choice on B states already on the device (the
+// results of all candidates are identical and land in d_out, d_it, d_st):
+// one untimed run, then the best of two timed ones; returns the fastest.
+static int measure_batch(rac_net *net, int32_t B, const uint64_t *d_in, uint64_t *d_out,
+                         int32_t *d_it, int32_t *d_st, hipStream_t s, CallChoice *best_c) {
+    double best = 1e30;
+    for (const CallChoice &cand : tune_candidates(net, kTuneBatch, B)) {
+        double t = 1e30;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIP_TRY(hipStreamSynchronize(s));
+            const auto t0 = std::chrono::steady_clock::now();
+            RAC_TRY(enqueue_batch(net, B, d_in, d_out, d_it, d_st, s, cand));
+            const int rc = rac_sync_status(net);
+            if (rc != RAC_OK && rc != RAC_ENOTCONVERGED) return rc;
+            if (rep > 0)
+                t = std::min(t, std::chrono::duration<double, std::milli>(
+                                    std::chrono::steady_clock::now() - t0).count());
+        }
+        if (t < best) {
+            best = t;
+            *best_c = cand;
+        }
+    }
+    remember(net, kTuneBatch, B, *best_c, best);
+    return RAC_OK;
+}
+
+static int ensure_mf_staging(rac_net *net, int32_t B) {
+    if (B <= net->mf_cap) return RAC_OK;
+    dfree(net->mf_in);
+    dfree(net->mf_out);
+    dfree(net->mf_it);
+    dfree(net->mf_st);
+    RAC_TRY(dalloc(&net->mf_in, (size_t)B * net->n));
+    RAC_TRY(dalloc(&net->mf_out, (size_t)B * net->n));
+    RAC_TRY(dalloc(&net->mf_it, (size_t)B));
+    RAC_TRY(dalloc(&net->mf_st, (size_t)B));
+    net->mf_cap = B;
+    return RAC_OK;
+}
+
 extern "C" int rac_enforce_batch(rac_net *net, int32_t B, uint64_t *dom, int32_t *iters,
                                  int32_t *status) {
     if (!net || (!dom && B > 0)) return set_error(RAC_EINVAL, "net or dom is NULL");
@@ -1378,22 +1582,20 @@ extern "C" int rac_enforce_batch(rac_net *net, int32_t B, uint64_t *dom, int32_t
     RAC_TRY(check_domains(dom, (int64_t)B * net->n, net->d));
     HIP_TRY(hipSetDevice(net->device));
     RAC_TRY(settle(net));
-    const int32_t path = pick_path(net, B, net->opt.path);
-    if (path == RAC_PATH_MFMA) {
-        if (B > net->mf_cap) {
-            dfree(net->mf_in);
-            dfree(net->mf_out);
-            dfree(net->mf_it);
-            dfree(net->mf_st);
-            RAC_TRY(dalloc(&net->mf_in, (size_t)B * net->n));
-            RAC_TRY(dalloc(&net->mf_out, (size_t)B * net->n));
-            RAC_TRY(dalloc(&net->mf_it, (size_t)B));
-            RAC_TRY(dalloc(&net->mf_st, (size_t)B));
-            net->mf_cap = B;
-        }
+    bool measure = false;
+    CallChoice c = lookup_choice(net, kTuneBatch, B, &measure);
+    if (measure) {
+        RAC_TRY(ensure_mf_staging(net, B));
         HIP_TRY(hipMemcpyAsync(net->mf_in, dom, (size_t)B * net->n * 8, hipMemcpyHostToDevice,
                                net->stream));
-        RAC_TRY(run_mfma(net, B, net->mf_in, net->mf_out, net->mf_it, net->mf_st, net->stream));
+        RAC_TRY(measure_batch(net, B, net->mf_in, net->mf_out, net->mf_it, net->mf_st, net->stream, &c));
+    }
+    if (c.path == RAC_PATH_MFMA) {
+        RAC_TRY(ensure_mf_staging(net, B));
+        HIP_TRY(hipMemcpyAsync(net->mf_in, dom, (size_t)B * net->n * 8, hipMemcpyHostToDevice,
+                               net->stream));
+        RAC_TRY(run_mfma(net, B, net->mf_in, net->mf_out, net->mf_it, net->mf_st, net->stream,
+                         mfma_handoff_threshold(c.handoff)));
         HIP_TRY(hipMemcpyAsync(dom, net->mf_out, (size_t)B * net->n * 8, hipMemcpyDeviceToHost,
                                net->stream));
         if (iters)
@@ -1402,15 +1604,20 @@ extern "C" int rac_enforce_batch(rac_net *net, int32_t B, uint64_t *dom, int32_t
             HIP_TRY(hipMemcpyAsync(status, net->mf_st, (size_t)B * 4, hipMemcpyDeviceToHost,
                                    net->stream));
         HIP_TRY(hipStreamSynchronize(net->stream));
-        return mfma_collect(net->mfma, &net->last);
+        const int rc = mfma_collect(net->mfma, &net->last);
+        net->last.tune_source = c.source;
+        return rc;
     }
-    RAC_TRY(ensure_path(net, path, call_target(net, B)));
-    RAC_TRY(prepare_net_runner(net, B, path == RAC_PATH_INT8 ? net->i8 : net->bits));
+    const int32_t items = choice_items(net, c, B);
+    RAC_TRY(ensure_path(net, c.path, items > 0 ? items : call_target(net, B)));
+    RAC_TRY(prepare_net_runner(net, B, c.path == RAC_PATH_INT8 ? net->i8 : net->bits));
     memcpy(net->run.h_dom, dom, (size_t)B * net->n * 8);
     HIP_TRY(hipMemcpyAsync(net->run.din, net->run.h_dom, (size_t)B * net->n * 8,
                            hipMemcpyHostToDevice, net->stream));
-    RAC_TRY(run_states(net, B, path, nullptr, 0, true, true));
-    return collect_bits(net, B, path, dom, iters, status);
+    RAC_TRY(run_states(net, B, c.path, nullptr, 0, true, true, items));
+    const int rc = collect_bits(net, B, c.path, dom, iters, status);
+    net->last.tune_source = c.source;
+    return rc;
 }
 
 extern "C" int rac_enforce_batch_device(rac_net *net, int32_t B, const uint64_t *d_dom_in,
@@ -1422,32 +1629,25 @@ extern "C" int rac_enforce_batch_device(rac_net *net, int32_t B, const uint64_t 
     HIP_TRY(hipSetDevice(net->device));
     RAC_TRY(settle(net));
     hipStream_t s = (hipStream_t)stream;
-    const int32_t path = pick_path(net, B, net->opt.path);
-    if (path == RAC_PATH_MFMA) {
-        RAC_TRY(run_mfma(net, B, d_dom_in, d_dom_out, d_iters, d_status, s));
-        net->pending = true;
-        net->last.path = RAC_PATH_MFMA;
-        return RAC_OK;
+    bool measure = false;
+    CallChoice c = lookup_choice(net, kTuneBatch, B, &measure);
+    if (measure) {
+        if (d_dom_in == d_dom_out) {
+            // the candidates must all start from the caller's input
+            RAC_TRY(ensure_mf_staging(net, B));
+            HIP_TRY(hipMemcpyAsync(net->mf_in, d_dom_in, (size_t)B * net->n * 8,
+                                   hipMemcpyDeviceToDevice, s));
+            RAC_TRY(measure_batch(net, B, net->mf_in, d_dom_out, d_iters, d_status, s, &c));
+        } else {
+            RAC_TRY(measure_batch(net, B, d_dom_in, d_dom_out, d_iters, d_status, s, &c));
+        }
+        // the call itself then runs the chosen path (from the caller's input,
+        // restored if it was overwritten), so that the net's counters describe it
+        if (d_dom_in == d_dom_out)
+            HIP_TRY(hipMemcpyAsync(d_dom_out, net->mf_in, (size_t)B * net->n * 8,
+                                   hipMemcpyDeviceToDevice, s));
     }
-    RAC_TRY(ensure_path(net, path, call_target(net, B)));
-    RAC_TRY(prepare_net_runner(net, B, path == RAC_PATH_INT8 ? net->i8 : net->bits));
-    PathData &pd = path == RAC_PATH_INT8 ? net->i8 : net->bits;
-    Runner &r = net->run;
-    Launch L = base_launch(r, B, net->opt);
-    L.nets = pd.d_desc;
-    L.uniform_n = net->n;   // every problem an instance of this net, at s*n
-    L.stage_vars = stage_vars_for(net->n);
-    L.din = d_dom_in;
-    L.dout = d_dom_out;
-    L.iters_out = d_iters;
-    L.status_out = d_status;
-    RAC_TRY(launch_fixpoint(r, net->device, s, L, (int64_t)B * net->n, (int64_t)pd.nitems * B,
-                            step_cap(net->opt, (int64_t)net->n * net->d), net->opt.use_graph != 0,
-                            net->opt.profile != 0));
-    net->pending = true;
-    net->last.path = path;
-    net->last.item_bytes = pd.item_bytes;
-    net->last.relation_bytes = (int64_t)pd.rows_bytes;
+    RAC_TRY(enqueue_batch(net, B, d_dom_in, d_dom_out, d_iters, d_status, s, c));
     return RAC_OK;
 }
 
@@ -1456,7 +1656,12 @@ extern "C" int rac_sync_status(rac_net *net) {
     if (!net->pending) return RAC_OK;
     HIP_TRY(hipSetDevice(net->device));
     net->pending = false;
-    if (net->last.path == RAC_PATH_MFMA) return mfma_collect(net->mfma, &net->last);
+    if (net->last.path == RAC_PATH_MFMA) {
+        const int rc = mfma_collect(net->mfma, &net->last);
+        net->last.tune_source = net->tune_source;
+        return rc;
+    }
+    net->last.tune_source = net->tune_source;
     int32_t hrc = 0;
     HIP_TRY(hipEventSynchronize(net->run.ev1));   // the end of the call on the caller's stream
     HIP_TRY(hipMemcpy(&hrc, net->run.rc, 4, hipMemcpyDeviceToHost));
@@ -1660,6 +1865,30 @@ extern "C" void rac_group_destroy(rac_group *g) {
     delete g;
 }
 
+// The tuned path of one state of a net (bit or int8 rows), measuring the
+// shape with the net's full domains if it is not in the table yet.
+static int instance_path(rac_net *net, int32_t tune, int32_t *path) {
+    const rac_options saved = net->opt;
+    net->opt.path = RAC_PATH_AUTO;
+    net->opt.item_bytes = 0;
+    net->opt.tune = tune;
+    net->opt.mode = RAC_RUN_TO_FIXPOINT;
+    bool measure = false;
+    CallChoice c = lookup_choice(net, kTuneSingle, 1, &measure);
+    int rc = RAC_OK;
+    if (measure) {
+        std::vector<uint64_t> dom((size_t)net->n, net->d >= 64 ? ~0ull : (1ull << net->d) - 1ull);
+        rc = rac_enforce(net, dom.data(), nullptr, 0, nullptr, nullptr);   // measures and stores
+        if (rc == RAC_ENOTCONVERGED) rc = RAC_OK;
+        TuneChoice t;
+        if (rc == RAC_OK && tune_lookup(tune_key(kTuneSingle, net->n, net->d, net->arcs, 1), &t))
+            c.path = t.path;
+    }
+    net->opt = saved;
+    *path = c.path == RAC_PATH_INT8 ? RAC_PATH_INT8 : RAC_PATH_BITS;
+    return rc;
+}
+
 extern "C" int rac_group_create(int32_t k, rac_net *const *nets, const rac_options *opt,
                                 rac_group **out) {
     if (!out) return set_error(RAC_EINVAL, "out is NULL");
@@ -1695,9 +1924,13 @@ extern "C" int rac_group_create(int32_t k, rac_net *const *nets, const rac_optio
         int64_t total_bytes = 0;
         for (int32_t i = 0; i < k && rc == RAC_OK; ++i) {
             rac_net *net = nets[i];
-            // per-net path: the int8 rows only where they are asked for and fit
+            // per-net path: the int8 rows where they are asked for and fit; with
+            // the automatic path, each instance's tuned single-state choice
+            // (measured now for shapes not in the table)
             int32_t path = RAC_PATH_BITS;
             if (o.path == RAC_PATH_INT8 && net->d <= 32) path = RAC_PATH_INT8;
+            if (o.path == RAC_PATH_AUTO && o.item_bytes == 0 && o.tune != 1)
+                if ((rc = instance_path(net, o.tune, &path))) break;
             paths[(size_t)i] = path;
             if ((rc = ensure_path(net, path, -1))) break;
             total_bytes += (int64_t)(path == RAC_PATH_INT8 ? net->i8 : net->bits).rows_bytes;

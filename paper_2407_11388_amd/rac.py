@@ -55,7 +55,7 @@ class rac_options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("path", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("item_bytes", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("tune", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class rac_stats(ctypes.Structure):
@@ -64,7 +64,7 @@ class rac_stats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int64),
                 ("algo_ops", ctypes.c_int64), ("path", ctypes.c_int32),
                 ("item_bytes", ctypes.c_int32), ("first_kernel_ms", ctypes.c_float),
-                ("reserved", ctypes.c_int32)]
+                ("tune_source", ctypes.c_int32)]
 
 
 class rac_search_result(ctypes.Structure):
@@ -165,13 +165,19 @@ def _check_device_tensors(where: str, specs):
             raise ValueError(f"{where}: {name} has {t.numel()} elements, needs {shape}")
 
 
+TUNE_AUTO, TUNE_RULES, TUNE_MEASURE = 0, 1, 2
+TUNE_SOURCES = {0: "rules", 1: "shipped table", 2: "user table", 3: "measured"}
+
+
 def options(mode: int = RAC_RUN_TO_FIXPOINT, max_sweeps: int = 0, path: int = PATH_AUTO,
-            use_graph: bool = True, item_bytes: int = 0, profile: bool = False) -> rac_options:
+            use_graph: bool = True, item_bytes: int = 0, profile: bool = False,
+            tune: int = TUNE_AUTO) -> rac_options:
     o = rac_options()
     lib.rac_default_options(ctypes.byref(o))
     o.mode, o.max_sweeps, o.path = mode, max_sweeps, path
     o.use_graph, o.item_bytes = 1 if use_graph else 0, item_bytes
     o.profile = 1 if profile else 0
+    o.tune = tune
     return o
 
 

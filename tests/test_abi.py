@@ -158,3 +158,28 @@ def test_group_device_entry_point_refuses_bad_tensors():
         grp.enforce_device(FakeGpuTensor((11,)), _i32(1), _i32(2))
     with pytest.raises(ValueError):
         grp.enforce_device(FakeGpuTensor((11,), is_cuda=False), _i32(2), _i32(2))
+
+
+def test_shipped_tuner_table_format():
+    # every entry of the autotuner table shipped beside librac.so parses the
+    # way the library reads it, once per key, with valid choices
+    import re
+    path = os.path.join(ROOT, "paper_2407_11388_amd", "rac_tune_gfx950.txt")
+    keys = set()
+    pat = re.compile(r"^gfx950/(single|batch)/d(\d+)/n(\d+)/dens(0\.05|0\.1|0\.25|0\.5|0\.75|1)/B(\d+) "
+                     r"path=([123]) items=(-?\d) handoff=(-?\d+) ms=(\d+\.\d+)$")
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#"):
+                continue
+            m = pat.match(line.rstrip("\n"))
+            assert m, line
+            kind, d, n, _, B, p, items, handoff, _ = m.groups()
+            for v in (int(d), int(n), int(B)):
+                assert v & (v - 1) == 0           # powers of 2
+            assert not (kind == "single" and (p == "3" or B != "1"))
+            assert -4 <= int(items) <= 4 and int(handoff) >= -1
+            key = line.split()[0]
+            assert key not in keys
+            keys.add(key)
+    assert any(k.startswith("gfx950/batch/d32/n1024/dens1/B1024") for k in keys)
