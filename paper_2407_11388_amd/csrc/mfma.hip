@@ -53,6 +53,7 @@ constexpr int kMS = 32 * kMSub;   // states per workgroup
 constexpr int kMY = 8;            // neighbours per LDS block
 constexpr int kMThreads = 64 * kMW;
 constexpr int kMaxTrackedSteps = 256;   // steps whose re-examined arcs are counted
+constexpr int kNsegMax = 4;             // workgroups per tile of a split step, at most
 
 // 4 bits -> 4 bytes holding 0/1 (bit i of v becomes byte i). The factor places
 // copies of v 7 bits apart, so no two copies overlap and no carry occurs.
@@ -98,6 +99,11 @@ struct MArgs {
     int32_t skip;                     // 1: steps k >= 2 skip neighbours no state of the tile changed
     unsigned long long *stepops;      // [kMaxTrackedSteps + 2] arcs re-examined by the states of
                                       // step k (sum over states of deg of the changed variables)
+    int32_t *ctl;                     // [4] device control of the step loop: [0] 1 once the
+                                      // matrix-core steps are over, [1] the last step they ran,
+                                      // [2 + (k & 1)] workgroups per tile of step k (split)
+    int32_t handoff;                  // stop when at most this many states remain (0: never)
+    int32_t cus, force_seg, ntiles_x; // compute units; forced split (0: none); x-tiles
     int32_t mode, max_sweeps, B, xcd_map;
     long long checks1;                // support checks of step 1: 2m * d * d
     const uint64_t *din;              // [B][n]
@@ -109,6 +115,27 @@ struct MArgs {
 // Byte offset of the 16 domain bytes (x, half h, slot) in a domain buffer.
 __device__ __forceinline__ int64_t dom_off(const MArgs &A, int32_t x, int h, int32_t slot) {
     return (((int64_t)x * 2 + h) * A.capB + slot) * 16;
+}
+
+// The step loop runs on the device: every kernel of step k returns at once
+// when the matrix-core steps ended before step k (the host enqueues whole
+// rounds of steps and reads the control words once per round).
+__device__ __forceinline__ bool step_off(const MArgs &A, int k) {
+    return A.ctl[0] != 0 && k > A.ctl[1];
+}
+
+// Workgroups per tile for a step with `active` states: enough tiles to fill
+// the compute units, at most 4 (or the forced count).
+__device__ __forceinline__ int split_for(const MArgs &A, int active) {
+    const int sact = (active + kMS - 1) / kMS;
+    const int tiles = A.ntiles_x * sact;
+    const int cap = A.nblk < kNsegMax ? A.nblk : kNsegMax;
+    if (A.force_seg > 0) return A.force_seg < cap ? A.force_seg : cap;
+    int sg = tiles > 0 ? A.cus / tiles : 1;
+    // workgroups the grid holds for each active tile: those of the idle tiles
+    const int avail = sact > 0 ? (A.words / 4) / sact : 1;
+    sg = sg < avail ? sg : avail;
+    return sg < 1 ? 1 : (sg > cap ? cap : sg);
 }
 
 // 32 domain bytes (two 16-byte halves, 0 or 0xFF) -> bit mask, and back.
@@ -159,6 +186,9 @@ __global__ void mfma_init_kernel(MArgs A) {
     if (tid == 0) {
         A.cnt[0] = A.B;
         A.cnt[1] = 0;
+        A.ctl[0] = 0;
+        A.ctl[1] = 0;
+        A.ctl[2 + 1] = split_for(A, A.B);   // step 1
         if (A.rc_out) *A.rc_out = 0;
     }
 }
@@ -201,27 +231,35 @@ __device__ __forceinline__ v16i mfma8(const v4i a, const v4i b, const v16i c) {
 // nseg workgroups (for steps with few active states, so that the grid still
 // fills the chip); each ORs its flags into A.kill and mfma_split_finish_kernel
 // applies them.
-__global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, int nseg) {
+__global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, int fgrid) {
     extern __shared__ v4i s_lds[];   // kStages domain tiles [kMY][2][kMS]
+    if (step_off(A, k)) return;
     const int nact = A.cnt[(k - 1) & 1];
-    // workgroup -> (x-tile, state tile); the state tiles of one x-tile share
-    // blockIdx % 8 and so an XCD
-    const int ntiles_s = (A.words * 32 + kMS - 1) / kMS;
-    int xt, stile, seg;
+    const int nseg = A.ctl[2 + (k & 1)];   // workgroups per tile this step
+    // The grid holds fgrid workgroups per (x-tile, state tile) of the whole
+    // batch; a step uses the first nseg x (tiles of its active states) of
+    // them, so that a step with few states splits each tile's neighbour
+    // blocks over workgroups the idle state tiles leave. Workgroup ->
+    // (x-tile, state tile, segment): the state tiles of one x-tile share
+    // blockIdx % 8 and so an XCD.
+    const int sact = (nact + kMS - 1) / kMS;   // active state tiles
+    int xt, stile, seg, i;
     if (A.xcd_map) {
-        const int b = blockIdx.x;
-        const int xcd = b & 7, r = (b >> 3) / nseg;
-        seg = (b >> 3) % nseg;
-        stile = r % ntiles_s;
-        xt = (r / ntiles_s) * 8 + xcd;
+        i = blockIdx.x >> 3;
+        const int t = i / nseg;
+        seg = i - t * nseg;
+        stile = t % sact;
+        xt = (t / sact) * 8 + (blockIdx.x & 7);
     } else {
-        seg = blockIdx.x % nseg;
-        const int r = blockIdx.x / nseg;
-        stile = r % ntiles_s;
-        xt = r / ntiles_s;
+        i = blockIdx.x;
+        const int t = i / nseg;
+        seg = i - t * nseg;
+        stile = t % sact;
+        xt = t / sact;
     }
+    (void)fgrid;
     const int st0 = stile * kMS;
-    if (st0 >= nact || xt * kMX >= A.n) return;
+    if (sact == 0 || xt * kMX >= A.n) return;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     // this workgroup's neighbour blocks [blo, bhi) (all of them unless split)
@@ -486,6 +524,7 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
 // the unsplit kernel's epilogue writes them. Threads cover 64 slots of one
 // variable per wave.
 __global__ void mfma_split_finish_kernel(MArgs A, int k) {
+    if (step_off(A, k) || A.ctl[2 + (k & 1)] <= 1) return;   // not a split step
     const int nact = A.cnt[(k - 1) & 1];
     const int64_t s64 = ((int64_t)nact + 63) / 64 * 64;
     const int64_t total = s64 * A.n;
@@ -531,6 +570,7 @@ __global__ void mfma_split_finish_kernel(MArgs A, int k) {
 __global__ void mfma_reduce_kernel(MArgs A, int k) {
     __shared__ uint32_t s_or, s_wp;
     __shared__ unsigned long long s_deg[32];
+    if (step_off(A, k)) return;
     const int nact = A.cnt[(k - 1) & 1];
     const int w = blockIdx.x;
     if (w * 32 >= nact) return;
@@ -571,6 +611,7 @@ __global__ void mfma_reduce_kernel(MArgs A, int k) {
 __global__ __launch_bounds__(1024) void mfma_finalize_kernel(MArgs A, int k) {
     __shared__ int32_t s_wave_tot[16];
     __shared__ int32_t s_base;
+    if (step_off(A, k)) return;
     const int nact = A.cnt[(k - 1) & 1];
     const int32_t *act = A.act[(k - 1) & 1];
     int32_t *nxt = A.act[k & 1];
@@ -629,6 +670,14 @@ __global__ __launch_bounds__(1024) void mfma_finalize_kernel(MArgs A, int k) {
     if (threadIdx.x == 0) {
         A.cnt[k & 1] = s_base;
         if (k + 1 <= kMaxTrackedSteps) A.stepops[k + 1] = s_ops;
+        // Algorithm 1's loop, on the device: the matrix-core steps end when no
+        // state goes on, or when the rest is few enough for the bit rows
+        if (s_base == 0 || (A.handoff > 0 && s_base <= A.handoff)) {
+            A.ctl[1] = k;
+            A.ctl[0] = 1;
+        } else {
+            A.ctl[2 + ((k + 1) & 1)] = split_for(A, s_base);
+        }
     }
 }
 
@@ -637,6 +686,7 @@ __global__ __launch_bounds__(1024) void mfma_finalize_kernel(MArgs A, int k) {
 // the tile's words, cleared by the finalise kernel). A wave covers 64
 // consecutive new slots of one variable, all in one tile.
 __global__ void mfma_tile_changed_kernel(MArgs A, int k) {
+    if (step_off(A, k)) return;
     const int nnext = A.cnt[k & 1];
     const int64_t s64 = ((int64_t)nnext + 63) / 64 * 64;
     const int64_t total = s64 * A.n;
@@ -661,6 +711,7 @@ __global__ void mfma_tile_changed_kernel(MArgs A, int k) {
 // After step k: the domains of the states that go on move to their new slots
 // in the input buffer; the states that stopped write their final domains.
 __global__ void mfma_gather_kernel(MArgs A, int k) {
+    if (step_off(A, k)) return;
     const int nact = A.cnt[(k - 1) & 1];
     const int32_t *act = A.act[(k - 1) & 1];
     const int64_t total = (int64_t)nact * A.n;
@@ -803,7 +854,16 @@ struct MfmaImpl {
     uint64_t *hin = nullptr, *hout = nullptr;   // device staging for host calls
     int32_t *d_iters = nullptr, *d_status = nullptr, *d_rc = nullptr;
     long long *d_checks = nullptr;
-    int32_t *h_cnt = nullptr;                    // pinned host copy of the active count
+    int32_t *h_cnt = nullptr;                    // pinned host copy of the control words and
+                                                 // active counts, read once per round
+    int32_t *ctl = nullptr;                      // device control words of the step loop
+    struct Round {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<Round> rounds;                   // captured rounds of steps, valid for graph_args
+    MArgs graph_args{};
+    bool graph_valid = false, graph_profiled = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_cnt = nullptr;
     hipEvent_t kev[2 * 64] = {};                 // step kernel timing (profiling)
     bool profiled = false;
@@ -840,6 +900,7 @@ void mfma_release(MfmaData &md) {
     mfree(m->slot_map);
     mfree(m->ids);
     mfree(m->cnt);
+    mfree(m->ctl);
     mfree(m->st);
     mfree(m->hin);
     mfree(m->hout);
@@ -848,6 +909,11 @@ void mfma_release(MfmaData &md) {
     mfree(m->d_rc);
     mfree(m->d_checks);
     if (m->h_cnt) (void)hipHostFree(m->h_cnt);
+    for (auto &r : m->rounds) {
+        if (r.exec) (void)hipGraphExecDestroy(r.exec);
+        if (r.graph) (void)hipGraphDestroy(r.graph);
+    }
+    m->rounds.clear();
     if (m->ev0) (void)hipEventDestroy(m->ev0);
     if (m->ev1) (void)hipEventDestroy(m->ev1);
     if (m->ev_cnt) (void)hipEventDestroy(m->ev_cnt);
@@ -971,7 +1037,8 @@ int mfma_ensure(MfmaData &md, int32_t n, int32_t d, int64_t arcs, const int32_t 
     }
     HIP_OK(hipFuncSetAttribute((const void *)mfma_sweep_kernel,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMSmem));
-    HIP_OK(hipHostMalloc((void **)&m->h_cnt, sizeof(int32_t) * 2, hipHostMallocDefault));
+    HIP_OK(hipHostMalloc((void **)&m->h_cnt, sizeof(int32_t) * 8, hipHostMallocDefault));
+    HIP_OK(hipMalloc(&m->ctl, sizeof(int32_t) * 4));
     HIP_OK(hipEventCreate(&m->ev0));
     HIP_OK(hipEventCreate(&m->ev1));
     HIP_OK(hipEventCreateWithFlags(&m->ev_cnt, hipEventDisableTiming));
@@ -1056,6 +1123,19 @@ static MArgs make_args(MfmaData &md, int32_t B, const uint64_t *din, uint64_t *d
     A.ych = m->ych;
     A.nw32 = (md.n + 31) / 32;
     A.stepops = m->stepops;
+    A.ctl = m->ctl;
+    A.ntiles_x = (md.n + kMX - 1) / kMX;
+    {
+        // RAC_MFMA_SEGMENTS forces the split of every step (tests)
+        const char *e = getenv("RAC_MFMA_SEGMENTS");
+        A.force_seg = e && *e ? std::max(0, std::min(atoi(e), kNsegMax)) : 0;
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+            A.cus = cus;
+        else
+            A.cus = 256;
+    }
     {
         const char *e = getenv("RAC_MFMA_SKIP");   // 0: every step re-examines every arc
         A.skip = (e && *e) ? (atoi(e) != 0) : 1;
@@ -1081,76 +1161,144 @@ static MArgs make_args(MfmaData &md, int32_t B, const uint64_t *din, uint64_t *d
     return A;
 }
 
-// Enqueues init and matrix-core steps. After step 2 and every later step the
-// host reads the active-state count (one small device-to-host copy); it stops
-// when no state is active, or hands the rest over when at most `handoff`
-// states remain (0: never), or at the step cap.
-static int run_steps(MfmaData &md, const MArgs &A, bool profile, int32_t handoff,
-                     hipStream_t stream, int32_t *k_out, int32_t *p_out) {
+#define RC_OK(expr)                    \
+    do {                               \
+        const int rc_ = (expr);        \
+        if (rc_ != RAC_OK) return rc_; \
+    } while (0)
+
+// Kernel node of a round graph, chained after *prev.
+static int round_node(hipGraph_t g, hipGraphNode_t *prev, const void *func, dim3 grid, dim3 block,
+                      size_t smem, void **params) {
+    hipKernelNodeParams kp;
+    memset(&kp, 0, sizeof(kp));
+    kp.func = const_cast<void *>(func);
+    kp.gridDim = grid;
+    kp.blockDim = block;
+    kp.sharedMemBytes = (unsigned)smem;
+    kp.kernelParams = params;
+    hipGraphNode_t node;
+    HIP_OK(hipGraphAddKernelNode(&node, g, *prev ? prev : nullptr, *prev ? 1 : 0, &kp));
+    *prev = node;
+    return RAC_OK;
+}
+
+// Event record node of a round graph (per-launch timing), chained after *prev.
+static int round_event(hipGraph_t g, hipGraphNode_t *prev, hipEvent_t ev) {
+    hipGraphNode_t node;
+    HIP_OK(hipGraphAddEventRecordNode(&node, g, *prev ? prev : nullptr, *prev ? 1 : 0, ev));
+    *prev = node;
+    return RAC_OK;
+}
+
+// Steps per round: 4, 4, 8, 16, 32, then 64.
+static int mfma_round_steps(int r) { return r < 2 ? 4 : (r >= 5 ? 64 : 4 << (r - 1)); }
+
+// Enqueues init and rounds of matrix-core steps. Whether the steps go on,
+// how many workgroups a step splits into, and when the few states left move
+// to the bit rows are decided on the device (finalise kernel); the host reads
+// the control words once per round, and replays a captured graph per round
+// when the arguments are those of the last call.
+static int run_steps(MfmaData &md, const MArgs &A, bool profile, hipStream_t stream,
+                     int32_t *k_out, int32_t *p_out) {
     MfmaImpl *m = impl(md);
     m->profiled = profile;
     m->args = A;
     const int ntiles_s = (A.words * 32 + kMS - 1) / kMS;
-    const int ntiles_x = (A.n + kMX - 1) / kMX;
-    const int sweep_blocks = ((ntiles_x + 7) / 8) * 8 * ntiles_s;
+    // one workgroup per (x-tile, state tile) of the whole batch, times a
+    // forced split count (tests); a split step uses the idle tiles' workgroups
+    const int fgrid = A.force_seg > 0 ? A.force_seg : 1;
+    const int sweep_blocks = ((A.ntiles_x + 7) / 8) * 8 * ntiles_s * fgrid;
     const int init_blocks = (int)std::min<int64_t>(4096, ((int64_t)A.B * A.n + 255) / 256);
+    const int64_t thr64 = ((int64_t)A.B + 63) / 64 * 64 * A.n;
+    const unsigned small_blocks = (unsigned)std::min<int64_t>(4096, (thr64 + 255) / 256);
     const int32_t maxs = A.max_sweeps > 0 ? A.max_sweeps : A.n * A.d + 1;
-    int dev = 0, cus = 0;
-    HIP_OK(hipGetDevice(&dev));
-    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    // one workgroup per CU (the LDS ring): a step whose active states fill
-    // fewer tiles than CUs splits its neighbour blocks over up to 4
-    // workgroups per tile
-    // RAC_MFMA_SEGMENTS forces the split of every step (tests)
-    const char *env_seg = getenv("RAC_MFMA_SEGMENTS");
-    const int force_seg = env_seg && *env_seg ? atoi(env_seg) : 0;
-    auto segments = [&](int64_t active) {
-        const int64_t tiles = (int64_t)ntiles_x * ((active + kMS - 1) / kMS);
-        int64_t sg = force_seg > 0 ? force_seg : (tiles > 0 ? cus / tiles : 1);
-        sg = std::max<int64_t>(1, std::min<int64_t>({sg, 4, (int64_t)A.nblk}));
-        return (int)sg;
-    };
+    // rounds are replayed graphs, also when profiling: the timing events are
+    // nodes of the graphs (RAC_MFMA_GRAPHS=0: direct launches)
+    const char *eg = getenv("RAC_MFMA_GRAPHS");
+    const bool graphs = !(eg && *eg && atoi(eg) == 0);
+    if (graphs && !(m->graph_valid && m->graph_profiled == profile &&
+                    memcmp(&m->graph_args, &A, sizeof(MArgs)) == 0)) {
+        for (auto &r : m->rounds) {
+            if (r.exec) (void)hipGraphExecDestroy(r.exec);
+            if (r.graph) (void)hipGraphDestroy(r.graph);
+        }
+        m->rounds.clear();
+        m->graph_args = A;
+        m->graph_valid = true;
+        m->graph_profiled = profile;
+    }
     HIP_OK(hipEventRecord(m->ev0, stream));
     hipLaunchKernelGGL(mfma_init_kernel, dim3(init_blocks), dim3(256), 0, stream, A);
     int k = 0;
-    int32_t left = A.B;
-    while (k < maxs) {
-        const int steps = k == 0 ? 2 : 1;
-        for (int i = 0; i < steps && k < maxs; ++i) {
-            ++k;
-            const bool timed = profile && k <= 64;
-            // step 2 runs before its active count is read: no split
-            const int nseg = k == 2 && force_seg <= 0 ? 1 : segments(left);
-            if (timed) HIP_OK(hipEventRecord(m->kev[2 * (k - 1)], stream));
-            hipLaunchKernelGGL(mfma_sweep_kernel, dim3(sweep_blocks * nseg), dim3(kMThreads), kMSmem,
-                               stream, A, k, nseg);
-            if (nseg > 1) {
-                const int64_t thr = ((int64_t)left + 63) / 64 * 64 * A.n;
-                hipLaunchKernelGGL(mfma_split_finish_kernel,
-                                   dim3((unsigned)std::min<int64_t>(4096, (thr + 255) / 256)), dim3(256),
-                                   0, stream, A, k);
+    for (int r = 0; k < maxs; ++r) {
+        const int K = std::min(mfma_round_steps(r), maxs - k);
+        if (graphs) {
+            if ((int)m->rounds.size() <= r) m->rounds.resize((size_t)r + 1);
+            MfmaImpl::Round &rd = m->rounds[(size_t)r];
+            if (!rd.exec) {
+                HIP_OK(hipGraphCreate(&rd.graph, 0));
+                MArgs args = A;
+                int nsm = fgrid;
+                std::vector<int> ks((size_t)K);
+                hipGraphNode_t prev = nullptr;
+                for (int i = 0; i < K; ++i) {
+                    ks[(size_t)i] = k + 1 + i;
+                    void *p2[2] = {&args, &ks[(size_t)i]};
+                    void *p3[3] = {&args, &ks[(size_t)i], &nsm};
+                    const int kk = ks[(size_t)i];
+                    const bool timed = profile && kk <= 64;
+                    if (timed) RC_OK(round_event(rd.graph, &prev, m->kev[2 * (kk - 1)]));
+                    RC_OK(round_node(rd.graph, &prev, (const void *)mfma_sweep_kernel, dim3(sweep_blocks),
+                                       dim3(kMThreads), kMSmem, p3));
+                    RC_OK(round_node(rd.graph, &prev, (const void *)mfma_split_finish_kernel,
+                                       dim3(small_blocks), dim3(256), 0, p2));
+                    if (timed) RC_OK(round_event(rd.graph, &prev, m->kev[2 * (kk - 1) + 1]));
+                    RC_OK(round_node(rd.graph, &prev, (const void *)mfma_reduce_kernel,
+                                       dim3((A.B + 31) / 32), dim3(256), 0, p2));
+                    RC_OK(round_node(rd.graph, &prev, (const void *)mfma_finalize_kernel, dim3(1),
+                                       dim3(1024), 0, p2));
+                    RC_OK(round_node(rd.graph, &prev, (const void *)mfma_gather_kernel, dim3(init_blocks),
+                                       dim3(256), 0, p2));
+                    if (A.skip)
+                        RC_OK(round_node(rd.graph, &prev, (const void *)mfma_tile_changed_kernel,
+                                           dim3(small_blocks), dim3(256), 0, p2));
+                }
+                HIP_OK(hipGraphInstantiate(&rd.exec, rd.graph, nullptr, nullptr, 0));
             }
-            if (timed) HIP_OK(hipEventRecord(m->kev[2 * (k - 1) + 1], stream));
-            hipLaunchKernelGGL(mfma_reduce_kernel, dim3((A.B + 31) / 32), dim3(256), 0, stream, A, k);
-            hipLaunchKernelGGL(mfma_finalize_kernel, dim3(1), dim3(1024), 0, stream, A, k);
-            hipLaunchKernelGGL(mfma_gather_kernel, dim3(init_blocks), dim3(256), 0, stream, A, k);
-            if (A.skip) {
-                const int64_t thr = ((int64_t)A.B + 63) / 64 * 64 * A.n;
-                hipLaunchKernelGGL(mfma_tile_changed_kernel,
-                                   dim3((unsigned)std::min<int64_t>(4096, (thr + 255) / 256)), dim3(256),
-                                   0, stream, A, k);
+            HIP_OK(hipGraphLaunch(rd.exec, stream));
+            k += K;
+        } else {
+            for (int i = 0; i < K; ++i) {
+                ++k;
+                const bool timed = profile && k <= 64;
+                if (timed) HIP_OK(hipEventRecord(m->kev[2 * (k - 1)], stream));
+                hipLaunchKernelGGL(mfma_sweep_kernel, dim3(sweep_blocks), dim3(kMThreads), kMSmem, stream,
+                                   A, k, fgrid);
+                hipLaunchKernelGGL(mfma_split_finish_kernel, dim3(small_blocks), dim3(256), 0, stream, A, k);
+                if (timed) HIP_OK(hipEventRecord(m->kev[2 * (k - 1) + 1], stream));
+                hipLaunchKernelGGL(mfma_reduce_kernel, dim3((A.B + 31) / 32), dim3(256), 0, stream, A, k);
+                hipLaunchKernelGGL(mfma_finalize_kernel, dim3(1), dim3(1024), 0, stream, A, k);
+                hipLaunchKernelGGL(mfma_gather_kernel, dim3(init_blocks), dim3(256), 0, stream, A, k);
+                if (A.skip)
+                    hipLaunchKernelGGL(mfma_tile_changed_kernel, dim3(small_blocks), dim3(256), 0, stream,
+                                       A, k);
             }
         }
         HIP_OK(hipGetLastError());
-        HIP_OK(hipMemcpyAsync(m->h_cnt, A.cnt + (k & 1), 4, hipMemcpyDeviceToHost, stream));
+        HIP_OK(hipMemcpyAsync(m->h_cnt, A.ctl, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        HIP_OK(hipMemcpyAsync(m->h_cnt + 4, A.cnt, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
         HIP_OK(hipEventRecord(m->ev_cnt, stream));
         HIP_OK(hipEventSynchronize(m->ev_cnt));
-        left = *m->h_cnt;
-        if (left == 0 || left <= handoff) break;
+        if (m->h_cnt[0]) break;
     }
-    m->last_k = k;
-    *k_out = k;
-    *p_out = k < maxs ? left : 0;   // at the cap every state has stopped
+    // the steps ended at step kd: no state went on (left = 0), or `left`
+    // states remain for the bit rows; at the step cap every state stopped
+    const int32_t kd = m->h_cnt[0] ? m->h_cnt[1] : k;
+    const int32_t left = m->h_cnt[0] ? m->h_cnt[4 + (kd & 1)] : 0;
+    m->last_k = kd;
+    *k_out = kd;
+    *p_out = left;
     return RAC_OK;
 }
 
@@ -1162,7 +1310,8 @@ int mfma_start(MfmaData &md, int32_t B, const uint64_t *d_in, uint64_t *d_out, i
     MfmaImpl *m = impl(md);
     MArgs A = make_args(md, B, d_in, d_out, nullptr, nullptr, mode, max_sweeps);
     m->last_B = B;
-    return run_steps(md, A, profile != 0, handoff, stream, k_out, p_out);
+    A.handoff = handoff;
+    return run_steps(md, A, profile != 0, stream, k_out, p_out);
 }
 
 int mfma_handoff(MfmaData &md, int32_t k, uint64_t *d_bits, uint8_t *d_changed, hipStream_t stream) {
