@@ -159,6 +159,25 @@ def profile_report(args):
                 for r in csv.DictReader(f):
                     if r["Kernel_Name"].split("(")[0].endswith(kernel):
                         durs.append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    if args.profile_sq:
+        # instruction and cycle counters of the same launches (one --pmc run)
+        sq = defaultdict(list)
+        for fn in os.listdir(args.profile_sq):
+            if fn.endswith("counter_collection.csv"):
+                with open(os.path.join(args.profile_sq, fn)) as f:
+                    for r in csv.DictReader(f):
+                        if r["Kernel_Name"].split("(")[0].endswith(kernel):
+                            sq[r["Counter_Name"]].append(float(r["Counter_Value"]))
+        if sq:
+            lines += ["", f"Instruction counters of {kernel} (--pmc, per launch, median over "
+                          f"{len(next(iter(sq.values())))} launches; SQ_INSTS_VALU also counts the "
+                          "matrix-core instructions, in more than one unit each):", ""]
+            med = {c: sorted(v)[len(v) // 2] for c, v in sq.items()}
+            for c in sorted(med):
+                lines.append(f"* {c}: {med[c]:.4g}")
+            if med.get("SQ_INSTS_MFMA") and med.get("SQ_INSTS_LDS"):
+                lines.append(f"* LDS instructions per matrix-core instruction: "
+                             f"{med['SQ_INSTS_LDS'] / med['SQ_INSTS_MFMA']:.2f}")
     if durs and args.profile_top > 0:
         busy = sorted(durs)[-args.profile_top:]
         lines.append(f"* average duration of the {len(busy)} longest launches (of {len(durs)}; "
@@ -219,6 +238,8 @@ def parse():
     ap.add_argument("--profile-command", action="append", default=[],
                     help="command line recorded in the profile summary (repeatable)")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
+    ap.add_argument("--profile-sq", default="", metavar="DIR",
+                    help="with --profile-report: a --pmc run of SQ instruction/cycle counters")
     ap.add_argument("--profile-top", type=int, default=0,
                     help="with --profile-report: take traffic and duration from the N launches "
                          "that read the most (0: every launch with work)")

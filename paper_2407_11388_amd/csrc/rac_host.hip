@@ -1865,30 +1865,6 @@ extern "C" void rac_group_destroy(rac_group *g) {
     delete g;
 }
 
-// The tuned path of one state of a net (bit or int8 rows), measuring the
-// shape with the net's full domains if it is not in the table yet.
-static int instance_path(rac_net *net, int32_t tune, int32_t *path) {
-    const rac_options saved = net->opt;
-    net->opt.path = RAC_PATH_AUTO;
-    net->opt.item_bytes = 0;
-    net->opt.tune = tune;
-    net->opt.mode = RAC_RUN_TO_FIXPOINT;
-    bool measure = false;
-    CallChoice c = lookup_choice(net, kTuneSingle, 1, &measure);
-    int rc = RAC_OK;
-    if (measure) {
-        std::vector<uint64_t> dom((size_t)net->n, net->d >= 64 ? ~0ull : (1ull << net->d) - 1ull);
-        rc = rac_enforce(net, dom.data(), nullptr, 0, nullptr, nullptr);   // measures and stores
-        if (rc == RAC_ENOTCONVERGED) rc = RAC_OK;
-        TuneChoice t;
-        if (rc == RAC_OK && tune_lookup(tune_key(kTuneSingle, net->n, net->d, net->arcs, 1), &t))
-            c.path = t.path;
-    }
-    net->opt = saved;
-    *path = c.path == RAC_PATH_INT8 ? RAC_PATH_INT8 : RAC_PATH_BITS;
-    return rc;
-}
-
 extern "C" int rac_group_create(int32_t k, rac_net *const *nets, const rac_options *opt,
                                 rac_group **out) {
     if (!out) return set_error(RAC_EINVAL, "out is NULL");
@@ -1924,13 +1900,12 @@ extern "C" int rac_group_create(int32_t k, rac_net *const *nets, const rac_optio
         int64_t total_bytes = 0;
         for (int32_t i = 0; i < k && rc == RAC_OK; ++i) {
             rac_net *net = nets[i];
-            // per-net path: the int8 rows where they are asked for and fit; with
-            // the automatic path, each instance's tuned single-state choice
-            // (measured now for shapes not in the table)
+            // per-net path: the int8 rows where they are asked for and fit, else
+            // bit rows (a group's step streams every instance's rows at once, so
+            // the fewest bytes win: single-instance measurements, latency-bound,
+            // do not carry over)
             int32_t path = RAC_PATH_BITS;
             if (o.path == RAC_PATH_INT8 && net->d <= 32) path = RAC_PATH_INT8;
-            if (o.path == RAC_PATH_AUTO && o.item_bytes == 0 && o.tune != 1)
-                if ((rc = instance_path(net, o.tune, &path))) break;
             paths[(size_t)i] = path;
             if ((rc = ensure_path(net, path, -1))) break;
             total_bytes += (int64_t)(path == RAC_PATH_INT8 ? net->i8 : net->bits).rows_bytes;

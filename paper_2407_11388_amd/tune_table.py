@@ -44,12 +44,11 @@ def main(out: str) -> None:
         print(f"[tune] {w.name}: path {net.stats().path}", flush=True)
         net.close()
     w = workloads.uneven_multi()
-    nets = [rac.Net.from_instance(i) for i in w.instances]
-    grp = rac.Group(nets, **measure)   # each instance's single-state shape
-    grp.close()
-    for nt in nets:
-        nt.close()
-    print(f"[tune] {w.name}: {len(nets)} instances", flush=True)
+    for inst, dom in zip(w.instances, w.domains):   # each instance's single-state shape
+        net = rac.Net.from_instance(inst, **measure)
+        net.enforce(dom)
+        net.close()
+    print(f"[tune] {w.name}: {len(w.instances)} instances", flush=True)
     w = workloads.batch_states()
     net = rac.Net.from_instance(w.instances[0], **measure)
     net.enforce_batch(w.domains[0])
