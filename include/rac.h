@@ -76,7 +76,9 @@ enum {
     RAC_PATH_AUTO = 0,   /* the autotuner chooses per call */
     RAC_PATH_BITS = 1,   /* relation rows as bit masks; support = (row & dom(y)) != 0 */
     RAC_PATH_INT8 = 2,   /* relation as 0/1 int8 blocks; support count = int32 dot product */
-    RAC_PATH_MFMA = 3    /* batched states: int8 x int8 -> int32 matrix-core products */
+    RAC_PATH_MFMA = 3,   /* batched states: int8 x int8 -> int32 matrix-core products */
+    RAC_PATH_FUSED = 4   /* bit rows; one workgroup per state runs every step in one launch,
+                            domains in LDS (n <= 2048; else RAC_EUNSUPPORTED at the call) */
 };
 
 typedef struct rac_options {

@@ -74,7 +74,7 @@ static int check_options(const rac_options *o) {
     if (o->mode != RAC_RUN_TO_FIXPOINT && o->mode != RAC_STOP_ON_WIPEOUT)
         return set_error(RAC_EINVAL, "options.mode must be 0 or 1");
     if (o->max_sweeps < 0) return set_error(RAC_EINVAL, "options.max_sweeps must be >= 0");
-    if (o->path < RAC_PATH_AUTO || o->path > RAC_PATH_MFMA)
+    if (o->path < RAC_PATH_AUTO || o->path > RAC_PATH_FUSED)
         return set_error(RAC_EINVAL, "options.path out of range");
     if (o->item_bytes < 0) return set_error(RAC_EINVAL, "options.item_bytes must be >= 0");
     if (o->profile != 0 && o->profile != 1) return set_error(RAC_EINVAL, "options.profile must be 0 or 1");
@@ -209,6 +209,7 @@ struct Runner {
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_round = nullptr;
     hipEvent_t kev[2 * kProfSteps] = {};
     bool profiled = false;
+    bool fused = false;             // the last launch was small_fixpoint_kernel
     int32_t steps_launched = 0;
     // captured rounds, valid for graph_args / graph_grid
     std::vector<RoundGraph> rounds;
@@ -254,7 +255,7 @@ struct rac_group {
     std::vector<int64_t> h_off;
     Runner run;
     rac_stats last{};
-    int64_t total_vars = 0, total_items = 0, rel_bytes = 0, max_n = 0, max_nd = 0;
+    int64_t total_vars = 0, total_items = 0, rel_bytes = 0, max_n = 0, max_nd = 0, max_groups = 0;
     bool pending = false;
 };
 
@@ -872,6 +873,7 @@ static int launch_fixpoint(Runner &r, int device, hipStream_t stream, const Laun
         fprintf(stderr, "[rac] revise grid=%lld items=%lld lds=%zu stage_vars=%d nprob=%d\n",
                 (long long)g, (long long)total_items, sg.smem, L.stage_vars, L.nprob);
     r.profiled = profile;
+    r.fused = false;
     const bool graphs = use_graph && !profile;
     if (graphs) {
         const bool same = r.graph_grid[0] == sg.init.x && r.graph_grid[1] == sg.revise.x &&
@@ -943,6 +945,42 @@ static int launch_fixpoint(Runner &r, int device, hipStream_t stream, const Laun
     return RAC_OK;
 }
 
+// Every step of every problem in one launch (RAC_PATH_FUSED): one workgroup
+// of small_fixpoint_kernel per problem with its domains in LDS; max_n and
+// max_groups are the largest problem's variables and 64-arc groups. Waves
+// per workgroup: up to 16 for one problem, fewer for many (measured: 8 for
+// batches of states whose steps re-examine many arcs, 4 for search rounds
+// whose children change few variables per step, where barriers dominate).
+// Outputs and read-back as launch_fixpoint.
+enum { kFusedWavesOne = 16, kFusedWavesBatch = 8, kFusedWavesSearch = 4 };
+static int launch_fused(Runner &r, hipStream_t stream, const Launch &L, int32_t max_n,
+                        int64_t max_groups, int max_waves, bool profile, int64_t rb_vars = -1) {
+    if (max_n > kSmallMaxN)
+        return set_error(RAC_EUNSUPPORTED, "the fused path holds at most %d variables per state",
+                         kSmallMaxN);
+    HIP_TRY(hipEventRecord(r.ev0, stream));
+    hipLaunchKernelGGL(clear_word_kernel, dim3(1), dim3(64), 0, stream, L.rc_out);
+    if (profile) HIP_TRY(hipEventRecord(r.kev[0], stream));
+    if (L.nprob > 0)
+        hipLaunchKernelGGL(small_fixpoint_kernel, dim3((unsigned)L.nprob), dim3(small_threads(max_groups, max_waves)),
+                           small_lds_bytes(max_n), stream, L);
+    if (profile) HIP_TRY(hipEventRecord(r.kev[1], stream));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(r.ev1, stream));
+    r.profiled = profile;
+    r.fused = true;
+    r.steps_launched = 0;
+    r.prefetched_vars = -1;
+    if (rb_vars >= 0) {
+        if (rb_vars > 0)
+            HIP_TRY(hipMemcpyAsync(r.h_dom, L.dout, (size_t)rb_vars * 8, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(r.h_res, r.res, res_bytes(r.cap_probs), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        r.prefetched_vars = rb_vars;
+    }
+    return RAC_OK;
+}
+
 // Profile mode: summed duration of the revise launches of steps that some
 // problem executed, and their number.
 static void revise_timing(Runner &r, double *ms, int64_t *launches, float *first_ms) {
@@ -950,6 +988,15 @@ static void revise_timing(Runner &r, double *ms, int64_t *launches, float *first
     *launches = 0;
     *first_ms = 0.f;
     if (!r.profiled) return;
+    if (r.fused) {   // one launch ran every step
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.kev[0], r.kev[1]) == hipSuccess) {
+            *ms = t;
+            *launches = 1;
+            *first_ms = t;
+        }
+        return;
+    }
     int32_t h[kHist] = {0};
     const int32_t n = std::min<int32_t>(r.steps_launched, kProfSteps);
     if (hipMemcpy(h, r.hist, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return;
@@ -1054,10 +1101,13 @@ static int32_t stage_vars_for(int64_t max_n) {
 // Bit / int8 path for B states already in r.din (host waits between rounds).
 // item_bytes > 0 fixes the work-item size (else the default for B states).
 // d_count non-null: the first *d_count of the B states run (a device count,
-// see Launch::nprob_dev).
+// see Launch::nprob_dev), which is at most count_bound (> 0) if given.
 static int run_states(rac_net *net, int32_t B, int32_t path, const uint8_t *d_changed,
                       long long arcs1, bool allow_graph = true, bool readback = false,
-                      int32_t item_bytes = 0, const int32_t *d_count = nullptr) {
+                      int32_t item_bytes = 0, const int32_t *d_count = nullptr,
+                      int32_t count_bound = 0) {
+    const bool fused = path == RAC_PATH_FUSED;
+    if (fused) path = RAC_PATH_BITS;
     PathData &pd = path == RAC_PATH_INT8 ? net->i8 : net->bits;
     RAC_TRY(ensure_path(net, path, item_bytes > 0 ? item_bytes : call_target(net, B)));
     Runner &r = net->run;
@@ -1072,6 +1122,14 @@ static int run_states(rac_net *net, int32_t B, int32_t path, const uint8_t *d_ch
     L.changed0 = d_changed;
     L.arcs1 = arcs1;
     L.nprob_dev = d_count;
+    if (fused) {
+        // no captured graph here: the grid needs only the states that can run
+        if (d_count && count_bound > 0 && count_bound < L.nprob) L.nprob = count_bound;
+        return launch_fused(r, net->stream, L, net->n, net->groups,
+                            d_count ? kFusedWavesSearch : B == 1 ? kFusedWavesOne : kFusedWavesBatch,
+                            net->opt.profile != 0,
+                            readback ? (int64_t)B * net->n : -1);
+    }
     RAC_TRY(launch_fixpoint(r, net->device, net->stream, L, (int64_t)B * net->n,
                             (int64_t)pd.nitems * B, step_cap(net->opt, (int64_t)net->n * net->d),
                             allow_graph && net->opt.use_graph != 0, net->opt.profile != 0,
@@ -1082,6 +1140,8 @@ static int run_states(rac_net *net, int32_t B, int32_t path, const uint8_t *d_ch
 static int collect_bits(rac_net *net, int32_t B, int32_t path, uint64_t *dom, int32_t *iters,
                         int32_t *status) {
     Runner &r = net->run;
+    const int32_t used = path;
+    if (path == RAC_PATH_FUSED) path = RAC_PATH_BITS;
     PathData &pd = path == RAC_PATH_INT8 ? net->i8 : net->bits;
     std::vector<int32_t> hi, hs;
     std::vector<long long> hc;
@@ -1089,7 +1149,7 @@ static int collect_bits(rac_net *net, int32_t B, int32_t path, uint64_t *dom, in
     RAC_TRY(read_results(r, net->stream, B, (int64_t)B * net->n, dom, hc, hi, hs, &hrc));
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, r.ev0, r.ev1);
-    fill_stats_bits(net->last, hc, hi, path, pd, ms);
+    fill_stats_bits(net->last, hc, hi, used, pd, ms);
     net->last.relation_bytes = (int64_t)pd.rows_bytes;
     revise_timing(r, &net->last.kernel_ms, &net->last.kernel_launches,
                  &net->last.first_kernel_ms);
@@ -1123,6 +1183,18 @@ static int64_t path_rows_bytes(const rac_net *net, int32_t path) {
     return net->groups * qpa * 1024;
 }
 
+// Fixed rule for the fused path (one workgroup per state, every step in one
+// launch): networks whose bit rows fit the L2 caches many times over, where
+// one workgroup's latency-bound sweep beats three launches per step. Bounds
+// on the bit rows of one state, measured on MI355X: 512 KiB for a single
+// state, 2 MiB for batches of states, 1 MiB for search rounds (whose
+// children re-examine few arcs per step).
+enum { kFusedRuleOne = 512 << 10, kFusedRuleBatch = 2 << 20, kFusedRuleSearch = 1 << 20 };
+static bool fused_rule(const rac_net *net, int64_t max_rows_bytes) {
+    if (net->n > kSmallMaxN) return false;
+    return path_rows_bytes(net, RAC_PATH_BITS) <= max_rows_bytes;
+}
+
 // The item size argument of ensure_path / run_states for B states.
 static int32_t choice_items(const rac_net *net, const CallChoice &c, int32_t B) {
     if (net->opt.item_bytes > 0) return net->opt.item_bytes;
@@ -1140,21 +1212,25 @@ static CallChoice lookup_choice(rac_net *net, int kind, int32_t B, bool *measure
     *measure = false;
     const int32_t req = net->opt.path;
     if (req != RAC_PATH_AUTO || net->opt.item_bytes > 0) {
-        c.path = kind == kTuneSingle ? (req == RAC_PATH_INT8 ? RAC_PATH_INT8 : RAC_PATH_BITS)
-                                     : (req == RAC_PATH_AUTO ? RAC_PATH_BITS : req);
+        c.path = kind == kTuneSingle
+                     ? (req == RAC_PATH_INT8 || req == RAC_PATH_FUSED ? req : RAC_PATH_BITS)
+                     : (req == RAC_PATH_AUTO ? RAC_PATH_BITS : req);
         if (kind == kTuneBatch && req == RAC_PATH_AUTO)
             c.path = mfma_auto_choice(net->d, net->n, net->arcs, B) ? RAC_PATH_MFMA : RAC_PATH_BITS;
         return c;
     }
-    // fixed rules: bit rows for one state; the matrix cores for many states of
-    // a dense network with d <= 32
+    // fixed rules: the fused path for small networks; else bit rows for one
+    // state, the matrix cores for many states of a dense network with d <= 32
     c.path = kind == kTuneBatch && mfma_auto_choice(net->d, net->n, net->arcs, B) ? RAC_PATH_MFMA
                                                                                   : RAC_PATH_BITS;
+    if (fused_rule(net, kind == kTuneBatch ? kFusedRuleBatch : kFusedRuleOne))
+        c.path = RAC_PATH_FUSED;
     const int mode = effective_tune_mode(net->opt);
     if (mode == kTuneRules) return c;
     TuneChoice t;
     if (mode != kTuneMeasure && tune_lookup(tune_key(kind, net->n, net->d, net->arcs, B), &t) &&
         (t.path != RAC_PATH_MFMA || net->d <= 32) && (t.path != RAC_PATH_INT8 || net->d <= 32) &&
+        (t.path != RAC_PATH_FUSED || net->n <= kSmallMaxN) &&
         (kind == kTuneBatch || t.path != RAC_PATH_MFMA)) {
         c.path = t.path;
         c.item_scale_log2 = t.item_scale_log2;
@@ -1180,6 +1256,7 @@ static std::vector<CallChoice> tune_candidates(const rac_net *net, int kind, int
     add(RAC_PATH_BITS, 2, -1);
     if (kind == kTuneSingle) add(RAC_PATH_BITS, -2, -1);
     if (net->d <= 32) add(RAC_PATH_INT8, 0, -1);
+    if (net->n <= kSmallMaxN) add(RAC_PATH_FUSED, 0, -1);
     if (kind == kTuneBatch && net->d <= 32 && B >= 8) {
         add(RAC_PATH_MFMA, 0, 32);
         add(RAC_PATH_MFMA, 0, 0);
@@ -1199,7 +1276,8 @@ static void remember(rac_net *net, int kind, int32_t B, const CallChoice &c, dou
 // One state on the bit or int8 path with a given choice (host buffers).
 static int enforce_one(rac_net *net, const uint64_t *din, uint64_t *dout, const int32_t *changed,
                        int32_t n_changed, int32_t *iters, int32_t *status, const CallChoice &c) {
-    const int32_t path = c.path == RAC_PATH_INT8 ? RAC_PATH_INT8 : RAC_PATH_BITS;
+    const int32_t path = c.path == RAC_PATH_INT8 ? RAC_PATH_INT8 : RAC_PATH_BITS;   // rows used
+    const int32_t run_path = c.path == RAC_PATH_FUSED ? RAC_PATH_FUSED : path;
     const int32_t items = choice_items(net, c, 1);
     RAC_TRY(ensure_path(net, path, items > 0 ? items : call_target(net, 1)));
     RAC_TRY(prepare_net_runner(net, 1, path == RAC_PATH_INT8 ? net->i8 : net->bits));
@@ -1223,8 +1301,8 @@ static int enforce_one(rac_net *net, const uint64_t *din, uint64_t *dout, const 
         d_changed = r.changed;
         arcs1 = degs;
     }
-    RAC_TRY(run_states(net, 1, path, d_changed, arcs1, true, true, items));
-    RAC_TRY(collect_bits(net, 1, path, dout, iters, status));
+    RAC_TRY(run_states(net, 1, run_path, d_changed, arcs1, true, true, items));
+    RAC_TRY(collect_bits(net, 1, run_path, dout, iters, status));
     net->last.tune_source = c.source;
     return RAC_OK;
 }
@@ -1363,6 +1441,12 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
     batch = std::min<int32_t>(batch, 1 << 16);
     const int32_t path = net->opt.path == RAC_PATH_INT8 ? RAC_PATH_INT8 : RAC_PATH_BITS;
     PathData &pd = path == RAC_PATH_INT8 ? net->i8 : net->bits;
+    // the enforcements themselves: one fused launch per round when asked for,
+    // or by the fixed rule on small networks
+    const bool fused = net->opt.path == RAC_PATH_FUSED ||
+                       (net->opt.path == RAC_PATH_AUTO && net->opt.item_bytes == 0 &&
+                        fused_rule(net, kFusedRuleSearch));
+    const int32_t run_path = fused ? RAC_PATH_FUSED : path;
     // a wipe-out anywhere ends a node: stop on the first one (same status as
     // running to the fixpoint, fewer steps)
     struct ModeGuard {
@@ -1378,7 +1462,7 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
     RAC_TRY(ensure_path(net, path, call_target(net, 1)));
     RAC_TRY(prepare_net_runner(net, 1, pd));
     HIP_TRY(hipMemcpyAsync(r.din, dom, (size_t)n * 8, hipMemcpyHostToDevice, s));
-    RAC_TRY(run_states(net, 1, path, nullptr, 0, false));
+    RAC_TRY(run_states(net, 1, run_path, nullptr, 0, false));
     std::vector<uint64_t> root((size_t)n);
     int32_t root_status = 0, hrc = 0, root_iters = 0;
     HIP_TRY(hipMemcpyAsync(root.data(), r.dout, (size_t)n * 8, hipMemcpyDeviceToHost, s));
@@ -1467,7 +1551,8 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
         ssize = base;
         // launched for cmax states with the count on the device: the same
         // arguments every round, so the captured step graphs are reused
-        RAC_TRY(run_states(net, cmax, path, r.changed, -1, true, false, item_bytes, r.count));
+        RAC_TRY(run_states(net, cmax, run_path, r.changed, -1, true, false, item_bytes, r.count,
+                           cbound));
         hipLaunchKernelGGL(search_classify_kernel, dim3((unsigned)cbound), dim3(64), 0, s, r.dout,
                            r.status, n, r.count, b.is_sol, b.is_open);
         hipLaunchKernelGGL(search_lists_kernel, dim3(1), dim3(1024), 0, s, b.is_sol, b.is_open,
@@ -1511,8 +1596,9 @@ static int enqueue_batch(rac_net *net, int32_t B, const uint64_t *d_in, uint64_t
         return RAC_OK;
     }
     const int32_t items = choice_items(net, c, B);
-    RAC_TRY(ensure_path(net, c.path, items > 0 ? items : call_target(net, B)));
-    PathData &pd = c.path == RAC_PATH_INT8 ? net->i8 : net->bits;
+    const int32_t rows = c.path == RAC_PATH_INT8 ? RAC_PATH_INT8 : RAC_PATH_BITS;
+    RAC_TRY(ensure_path(net, rows, items > 0 ? items : call_target(net, B)));
+    PathData &pd = rows == RAC_PATH_INT8 ? net->i8 : net->bits;
     RAC_TRY(prepare_net_runner(net, B, pd));
     Runner &r = net->run;
     Launch L = base_launch(r, B, net->opt);
@@ -1523,9 +1609,13 @@ static int enqueue_batch(rac_net *net, int32_t B, const uint64_t *d_in, uint64_t
     L.dout = d_out;
     L.iters_out = d_it;
     L.status_out = d_st;
-    RAC_TRY(launch_fixpoint(r, net->device, s, L, (int64_t)B * net->n, (int64_t)pd.nitems * B,
-                            step_cap(net->opt, (int64_t)net->n * net->d), net->opt.use_graph != 0,
-                            net->opt.profile != 0));
+    if (c.path == RAC_PATH_FUSED)
+        RAC_TRY(launch_fused(r, s, L, net->n, net->groups,
+                             B == 1 ? kFusedWavesOne : kFusedWavesBatch, net->opt.profile != 0));
+    else
+        RAC_TRY(launch_fixpoint(r, net->device, s, L, (int64_t)B * net->n, (int64_t)pd.nitems * B,
+                                step_cap(net->opt, (int64_t)net->n * net->d),
+                                net->opt.use_graph != 0, net->opt.profile != 0));
     net->pending = true;
     net->last.path = c.path;
     net->last.item_bytes = pd.item_bytes;
@@ -1609,7 +1699,8 @@ extern "C" int rac_enforce_batch(rac_net *net, int32_t B, uint64_t *dom, int32_t
         return rc;
     }
     const int32_t items = choice_items(net, c, B);
-    RAC_TRY(ensure_path(net, c.path, items > 0 ? items : call_target(net, B)));
+    RAC_TRY(ensure_path(net, c.path == RAC_PATH_INT8 ? RAC_PATH_INT8 : RAC_PATH_BITS,
+                        items > 0 ? items : call_target(net, B)));
     RAC_TRY(prepare_net_runner(net, B, c.path == RAC_PATH_INT8 ? net->i8 : net->bits));
     memcpy(net->run.h_dom, dom, (size_t)B * net->n * 8);
     HIP_TRY(hipMemcpyAsync(net->run.din, net->run.h_dom, (size_t)B * net->n * 8,
@@ -1931,6 +2022,7 @@ extern "C" int rac_group_create(int32_t k, rac_net *const *nets, const rac_optio
             g->total_items += (int64_t)its.size();
             g->rel_bytes += (int64_t)pd.rows_bytes;
             g->max_n = std::max<int64_t>(g->max_n, net->n);
+            g->max_groups = std::max<int64_t>(g->max_groups, net->groups);
         }
         if ((rc = dalloc(&g->items, all_items.size()))) break;
         if ((rc = dalloc(&g->pieces, all_pieces.size()))) break;
@@ -1954,6 +2046,11 @@ extern "C" int rac_group_create(int32_t k, rac_net *const *nets, const rac_optio
         for (int32_t i = 0; i < k; ++i) {
             pn[(size_t)i] = i;
             g->max_nd = std::max<int64_t>(g->max_nd, (int64_t)nets[i]->n * nets[i]->d);
+        }
+        if (o.path == RAC_PATH_FUSED && g->max_n > kSmallMaxN) {
+            rc = set_error(RAC_EUNSUPPORTED, "the fused path holds at most %d variables per net",
+                           kSmallMaxN);
+            break;
         }
         if (hipMemcpy(g->run.prob_net, pn.data(), (size_t)k * 4, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(g->run.prob_off, g->h_off.data(), ((size_t)k + 1) * 8, hipMemcpyHostToDevice) != hipSuccess) {
@@ -1995,9 +2092,14 @@ extern "C" int rac_group_enforce(rac_group *g, uint64_t *const *dom, int32_t *it
     }
     HIP_TRY(hipMemcpyAsync(r.din, r.h_dom, h.size() * 8, hipMemcpyHostToDevice, g->stream));
     Launch L = group_launch(g, r.din, r.dout, r.iters, r.status);
-    RAC_TRY(launch_fixpoint(r, g->device, g->stream, L, g->total_vars, g->total_items,
-                            step_cap(g->opt, g->max_nd), g->opt.use_graph != 0,
-                            g->opt.profile != 0, g->total_vars));
+    if (g->opt.path == RAC_PATH_FUSED)
+        RAC_TRY(launch_fused(r, g->stream, L, (int32_t)g->max_n, g->max_groups,
+                             g->k == 1 ? kFusedWavesOne : kFusedWavesBatch, g->opt.profile != 0,
+                             g->total_vars));
+    else
+        RAC_TRY(launch_fixpoint(r, g->device, g->stream, L, g->total_vars, g->total_items,
+                                step_cap(g->opt, g->max_nd), g->opt.use_graph != 0,
+                                g->opt.profile != 0, g->total_vars));
     std::vector<int32_t> hi, hs;
     std::vector<long long> hc;
     int32_t hrc = 0;
@@ -2014,7 +2116,7 @@ extern "C" int rac_group_enforce(rac_group *g, uint64_t *const *dom, int32_t *it
         g->last.sweeps += hi[(size_t)i];
     }
     g->last.device_ms = ms;
-    g->last.path = RAC_PATH_BITS;
+    g->last.path = g->opt.path == RAC_PATH_FUSED ? RAC_PATH_FUSED : RAC_PATH_BITS;
     g->last.relation_bytes = g->rel_bytes;
     revise_timing(r, &g->last.kernel_ms, &g->last.kernel_launches,
                  &g->last.first_kernel_ms);
@@ -2027,9 +2129,13 @@ extern "C" int rac_group_enforce_device(rac_group *g, uint64_t *d_dom, int32_t *
     HIP_TRY(hipSetDevice(g->device));
     RAC_TRY(settle(g));
     Launch L = group_launch(g, d_dom, d_dom, d_iters, d_status);
-    RAC_TRY(launch_fixpoint(g->run, g->device, (hipStream_t)stream, L, g->total_vars,
-                            g->total_items, step_cap(g->opt, g->max_nd), g->opt.use_graph != 0,
-                            g->opt.profile != 0));
+    if (g->opt.path == RAC_PATH_FUSED)
+        RAC_TRY(launch_fused(g->run, (hipStream_t)stream, L, (int32_t)g->max_n, g->max_groups,
+                             g->k == 1 ? kFusedWavesOne : kFusedWavesBatch, g->opt.profile != 0));
+    else
+        RAC_TRY(launch_fixpoint(g->run, g->device, (hipStream_t)stream, L, g->total_vars,
+                                g->total_items, step_cap(g->opt, g->max_nd),
+                                g->opt.use_graph != 0, g->opt.profile != 0));
     g->pending = true;
     return RAC_OK;
 }
@@ -2050,7 +2156,7 @@ extern "C" int rac_group_sync_status(rac_group *g) {
     for (long long c : hc) g->last.support_checks += c;
     g->last.device_ms = ms;
     g->last.relation_bytes = g->rel_bytes;
-    g->last.path = RAC_PATH_BITS;
+    g->last.path = g->opt.path == RAC_PATH_FUSED ? RAC_PATH_FUSED : RAC_PATH_BITS;
     revise_timing(g->run, &g->last.kernel_ms, &g->last.kernel_launches, &g->last.first_kernel_ms);
     return rc_from_device(hrc);
 }

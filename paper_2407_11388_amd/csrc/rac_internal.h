@@ -37,6 +37,20 @@ constexpr int kSparseGroups = 16;
 // active arcs of a sparse batch (kSparseGroups * 64 16-bit codes).
 constexpr int kScratchWords = kItemVars + kSparseGroups * kGroup / 4;
 
+// Small problems in one launch (small_fixpoint_kernel): at most kSmallMaxN
+// variables, one workgroup of up to kSmallMaxThreads per problem; LDS of
+// 3 * 8 + 2 bytes per variable.
+constexpr int kSmallMaxN = 2048;
+constexpr int kSmallMaxThreads = 1024;
+inline size_t small_lds_bytes(int32_t n) { return (size_t)n * 26 + 16; }
+// Threads of the workgroup for networks of at most `groups` 64-arc groups:
+// about 4 groups per wave and step, 1 to max_waves (<= 16) waves.
+inline int small_threads(int64_t groups, int max_waves) {
+    int w = 1;
+    while (w < max_waves && w < 16 && (int64_t)w * 4 < groups) w <<= 1;
+    return w * 64;
+}
+
 // One network as seen by the sweep kernel (device memory, read-only).
 // Arcs leaving x: row_ptr[x] .. row_ptr[x+1]-1 (to nbr[j]); in the padded
 // group layout, groups gptr[x] .. gptr[x+1]-1 with nbrp[g*64 + l] the
@@ -131,6 +145,8 @@ __global__ void plan_kernel(Launch L, int k);
 __global__ void revise_kernel(Launch L, int k);
 __global__ void update_kernel(Launch L, int k);
 __global__ void finish_kernel(Launch L);
+__global__ void small_fixpoint_kernel(Launch L);
+__global__ void clear_word_kernel(int32_t *w);
 __global__ void pack_bits_kernel(const uint64_t *rel, const int32_t *src_p, int64_t groups,
                                  int32_t d, int32_t qpa, int32_t kind, uint4 *out);
 __global__ void pack_i8_kernel(const uint64_t *rel, const int32_t *arc_src, int64_t arcs,

@@ -818,6 +818,157 @@ __global__ __launch_bounds__(256) void update_kernel(Launch L, int k) {
     }
 }
 
+// Small problems in one launch: one workgroup per problem runs every step of
+// Eq. (1) with the problem's domains in LDS (double-buffered), so a step
+// costs two workgroup barriers instead of three dependent kernel launches.
+// Bit rows only (ROW32 / ROW64), n <= kSmallMaxN. Wave w takes the groups
+// w, w + waves, ... of the network (lane = arc of a group; a group's arcs all
+// leave one variable), tests the rows of each arc into a variable changed in
+// the previous step against that variable's domain, and ORs the failures per
+// variable in LDS; then every thread updates its variables. Outputs as the
+// finish kernel writes them: domains, step count, status, support checks, and
+// rc_out = 1 when a problem stopped at the step cap unconverged.
+//
+// One wave's groups follow each other, so the loop hides latency itself: the
+// next group's neighbour indices are loaded while the current group's rows
+// are tested, and a group's row quads are loaded up to 8 at a time.
+template <bool WIDE>
+DEV void small_revise(const NetDesc &N, const uint64_t *__restrict__ dom, const uint8_t *__restrict__ chg,
+                      unsigned long long *failx, int wave, int nwaves, int lane, unsigned long long *arcs_seen) {
+    constexpr int RPQ = WIDE ? 2 : 4;   // rows per quad
+    const GLOBAL u32x4 *rows = as_global(reinterpret_cast<const u32x4 *>(N.rows));
+    const GLOBAL int32_t *nbrp = as_global(N.nbrp);
+    const GLOBAL int32_t *gown = as_global(N.gown);
+    const int64_t ngroups = N.gptr[N.n];
+    const int qpa = N.qpa;
+    const uint64_t dmask = dmask_of(N.d);
+    unsigned long long seen = 0;
+    int64_t g = wave;
+    int32_t y_next = -1, x_next = 0;
+    if (g < ngroups) {
+        y_next = nbrp[g * kGroup + lane];
+        x_next = gown[g];
+    }
+    for (; g < ngroups; g += nwaves) {
+        const int32_t y = y_next, x = x_next;
+        const int64_t gn = g + nwaves;
+        if (gn < ngroups) {
+            y_next = nbrp[gn * kGroup + lane];
+            x_next = gown[gn];
+        }
+        const int32_t yc = y >= 0 ? y : 0;   // padding arcs read variable 0, unused
+        const bool on = y >= 0 && chg[yc];
+        const uint64_t act = __ballot(on);
+        if (!act) continue;
+        seen += __popcll(act);
+        const uint64_t dy = on ? dom[yc] : ~0ull;   // lanes off: every row has support
+        const GLOBAL u32x4 *q = rows + g * qpa * kGroup + lane;
+        uint64_t f = 0;
+        for (int c0 = 0; c0 < qpa; c0 += 8) {
+            u32x4 v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (c0 + i < qpa) v[i] = q[(int64_t)(c0 + i) * kGroup];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (c0 + i < qpa) f |= (uint64_t)quad_fail<WIDE>(v[i], dy) << ((c0 + i) * RPQ);
+        }
+        if (!on) f = 0;
+        f = wave_or64(f) & dom[x] & dmask;
+        if (lane == 0 && f)
+            (void)__hip_atomic_fetch_or(failx + x, (unsigned long long)f, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    if (lane == 0) *arcs_seen += seen;
+}
+
+__global__ __launch_bounds__(kSmallMaxThreads) void small_fixpoint_kernel(Launch L) {
+    extern __shared__ uint64_t s_lds[];   // dom[2][n], fail[n], then chg[2][n] bytes
+    __shared__ int32_t s_any, s_wipe;
+    __shared__ unsigned long long s_arcs;
+    const int32_t p = blockIdx.x;
+    if (p >= problem_count(L)) return;
+    const NetDesc &N = net_of(L, p);
+    const int32_t n = N.n;
+    const int64_t off = L.uniform_n > 0 ? (int64_t)p * L.uniform_n : L.prob_off[p];
+    uint64_t *dom0 = s_lds, *dom1 = s_lds + n;
+    unsigned long long *failx = reinterpret_cast<unsigned long long *>(s_lds + 2 * n);
+    uint8_t *chg0 = reinterpret_cast<uint8_t *>(s_lds + 3 * n), *chg1 = chg0 + n;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+    for (int32_t x = tid; x < n; x += blockDim.x) {
+        dom0[x] = L.din[off + x];
+        chg0[x] = L.changed0 ? (L.changed0[off + x] ? 1 : 0) : 1;
+        failx[x] = 0;
+    }
+    if (tid == 0) {
+        s_arcs = 0;
+        s_wipe = 0;
+    }
+    const int32_t maxs = max_steps(L, N);
+    unsigned long long arcs_total = 0;   // re-examined arcs over all steps (thread 0)
+    int32_t k = 0, last_change = 0, wipe_step = 0;
+    uint64_t *cur = dom0, *nxt = dom1;
+    uint8_t *cin = chg0, *cout = chg1;
+    while (k < maxs) {
+        ++k;
+        __syncthreads();   // domains, change flags and cleared failures of step k-1 visible
+        unsigned long long seen = 0;
+        if (N.kind == ROW64)
+            small_revise<true>(N, cur, cin, failx, wave, nwaves, lane, &seen);
+        else
+            small_revise<false>(N, cur, cin, failx, wave, nwaves, lane, &seen);
+        if (lane == 0 && seen)
+            (void)__hip_atomic_fetch_add(&s_arcs, seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (tid == 0) s_any = 0;
+        __syncthreads();   // every failure of step k recorded
+        int any = 0, wiped = 0;
+        for (int32_t x = tid; x < n; x += blockDim.x) {
+            const uint64_t o = cur[x], nd = o & ~failx[x] & dmask_of(N.d);
+            nxt[x] = nd;
+            cout[x] = nd != o ? 1 : 0;
+            failx[x] = 0;
+            any |= nd != o;
+            wiped |= nd == 0;
+        }
+        if (__ballot(any) && lane == 0) atomicOr(&s_any, 1);
+        if (__ballot(wiped) && lane == 0) atomicOr(&s_wipe, 1);
+        __syncthreads();   // the step's change and wipe-out words
+        if (tid == 0) arcs_total = s_arcs;
+        const bool changed = s_any != 0;
+        if (changed) last_change = k;
+        if (s_wipe && wipe_step == 0) wipe_step = k;
+        uint64_t *t64 = cur;
+        cur = nxt;
+        nxt = t64;
+        uint8_t *t8 = cin;
+        cin = cout;
+        cout = t8;
+        if (!changed) break;
+        if (L.mode == RAC_STOP_ON_WIPEOUT && wipe_step != 0) break;
+    }
+    int32_t iters, rc = 0;
+    if (L.mode == RAC_STOP_ON_WIPEOUT && wipe_step != 0) {
+        iters = wipe_step;
+    } else if (last_change < maxs) {
+        iters = last_change + 1;
+    } else {
+        iters = maxs;
+        rc = 1;
+    }
+    for (int32_t x = tid; x < n; x += blockDim.x) L.dout[off + x] = cur[x];
+    if (tid == 0) {
+        if (L.iters_out) L.iters_out[p] = iters;
+        if (L.status_out) L.status_out[p] = wipe_step != 0 ? RAC_WIPEOUT : RAC_CONSISTENT;
+        if (L.checks_out) L.checks_out[p] = (long long)arcs_total * N.d * N.d;
+        if (rc && L.rc_out) atomicOr(L.rc_out, 1);
+    }
+}
+
+// Clears one word (the non-convergence flag before a fused launch).
+__global__ void clear_word_kernel(int32_t *w) {
+    if (threadIdx.x == 0) *w = 0;
+}
+
 __global__ void init_kernel(Launch L) {
     const int32_t nprob = problem_count(L);
     const int64_t nv = L.prob_off[nprob];

@@ -47,7 +47,7 @@ bool parse_line(const char *line, std::string *key, TuneChoice *c) {
     int p = 0, s = 0, h = 0;
     double ms = 0.0;
     if (sscanf(line, "%127s path=%d items=%d handoff=%d ms=%lf", k, &p, &s, &h, &ms) != 5) return false;
-    if (p < 1 || p > 3 || s < -4 || s > 4 || h < -1) return false;
+    if (p < 1 || p > 4 || s < -4 || s > 4 || h < -1) return false;
     *key = k;
     c->path = p;
     c->item_scale_log2 = s;

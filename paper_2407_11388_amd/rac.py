@@ -32,8 +32,10 @@ RAC_CONSISTENT = 0
 RAC_WIPEOUT = 1
 RAC_RUN_TO_FIXPOINT = 0
 RAC_STOP_ON_WIPEOUT = 1
-PATH_AUTO, PATH_BITS, PATH_INT8, PATH_MFMA = 0, 1, 2, 3
-PATH_NAMES = {PATH_AUTO: "auto", PATH_BITS: "bits", PATH_INT8: "int8", PATH_MFMA: "mfma"}
+PATH_AUTO, PATH_BITS, PATH_INT8, PATH_MFMA, PATH_FUSED = 0, 1, 2, 3, 4
+PATH_NAMES = {PATH_AUTO: "auto", PATH_BITS: "bits", PATH_INT8: "int8", PATH_MFMA: "mfma",
+              PATH_FUSED: "fused"}
+SMALL_MAX_N = 2048   # largest network the fused path (one workgroup per state) holds
 
 EXPORTED = [
     "rac_default_options", "rac_create", "rac_create_bits", "rac_create_dense", "rac_destroy",

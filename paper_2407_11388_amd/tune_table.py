@@ -37,6 +37,16 @@ def main(out: str) -> None:
                     net.enforce_batch(doms)
                     print(f"[tune] batch d={d} n={n} p1={p1} B={B}: path {net.stats().path}", flush=True)
                     net.close()
+    # single states over a grid of shapes
+    for d in (8, 16, 32, 64):
+        for n in (64, 256, 1024):
+            for p1 in (0.1, 0.5, 1.0):
+                inst = gen.model_b(7500 + n + d + int(10 * p1), n, d, p1, 0.25)
+                dom = gen.preremove(7501 + n, n, d, (n * d) // 10)
+                net = rac.Net.from_instance(inst, **measure)
+                net.enforce(dom)
+                print(f"[tune] single d={d} n={n} p1={p1}: path {net.stats().path}", flush=True)
+                net.close()
     for name in ("single_small", "single_mid", "single_large"):
         w = getattr(workloads, name)()
         net = rac.Net.from_instance(w.instances[0], **measure)
@@ -61,7 +71,8 @@ def main(out: str) -> None:
             "#   python -m paper_2407_11388_amd.tune_table rac_tune_gfx950.txt",
             "# key: gfx950/<single|batch>/d<domain size, power of 2>/n<variables, power of 2>/",
             "#      dens<constraint density bucket>/B<states per call, power of 2>",
-            "# path: 1 bit rows, 2 int8 rows, 3 matrix cores; items: work items of 2^items times the",
+            "# path: 1 bit rows, 2 int8 rows, 3 matrix cores, 4 fused (one workgroup per state, every",
+            "# step in one launch); items: work items of 2^items times the",
             "# default size; handoff: matrix-core states left when the rest moves to the bit rows",
             "# (-1: the default); ms: the measured time per call"]
     with open(out, "w") as f:

@@ -167,7 +167,7 @@ def test_shipped_tuner_table_format():
     path = os.path.join(ROOT, "paper_2407_11388_amd", "rac_tune_gfx950.txt")
     keys = set()
     pat = re.compile(r"^gfx950/(single|batch)/d(\d+)/n(\d+)/dens(0\.05|0\.1|0\.25|0\.5|0\.75|1)/B(\d+) "
-                     r"path=([123]) items=(-?\d) handoff=(-?\d+) ms=(\d+\.\d+)$")
+                     r"path=([1234]) items=(-?\d) handoff=(-?\d+) ms=(\d+\.\d+)$")
     with open(path) as f:
         for line in f:
             if line.startswith("#"):

@@ -1,8 +1,9 @@
 """GPU parity: every result of the HIP paths equals the CPU oracle bit for bit
 (domains, step count, wipe-out status and support-check count), on the tiny,
-golden and medium instances, for the bit-row and int8-row paths, both stop
-modes, forced item splitting, graph and direct launches, incremental starts,
-the step cap, batched states and groups of networks."""
+golden and medium instances, for the bit-row, int8-row and fused (one
+workgroup per state, every step in one launch) paths, both stop modes, forced
+item splitting, graph and direct launches, incremental starts, the step cap,
+batched states and groups of networks."""
 import sys
 
 import numpy as np
@@ -40,7 +41,7 @@ def gpu_vs_oracle(name, n, d, edges, rel_u8, dom_masks, path, mode=0, item_bytes
     net.close()
 
 
-PATHS = [rac.PATH_BITS, rac.PATH_INT8]
+PATHS = [rac.PATH_BITS, rac.PATH_INT8, rac.PATH_FUSED]
 CASES = golden_cases()
 
 
@@ -85,6 +86,17 @@ def test_medium_bits(d, item_bytes):
                       item_bytes=item_bytes, use_graph=(d % 2 == 0))
 
 
+@pytest.mark.parametrize("d", MEDIUM_D)
+def test_medium_fused(d):
+    n = 60
+    p2 = 0.5 if d <= 4 else (0.62 if d <= 12 else 0.8)
+    inst = gen.model_b(900 + d, n, d, 0.35, p2)
+    dom = gen.preremove(901 + d, n, d, (n * d) // 6)
+    for mode in (0, 1):
+        gpu_vs_oracle(f"medium-fused-d{d}", n, d, inst.edges, inst.rel_u8(), dom, rac.PATH_FUSED,
+                      mode)
+
+
 @pytest.mark.parametrize("d", [d for d in MEDIUM_D if d <= 32])
 def test_medium_int8(d):
     n = 50
@@ -97,7 +109,8 @@ def test_medium_int8(d):
                           rac.PATH_INT8, mode, item_bytes=ib)
 
 
-def test_incremental_start():
+@pytest.mark.parametrize("path", [rac.PATH_BITS, rac.PATH_FUSED])
+def test_incremental_start(path):
     n, d = 80, 8
     inst = gen.model_b(31, n, d, 0.2, 0.45)
     rel = inst.rel_u8()
@@ -109,10 +122,11 @@ def test_incremental_start():
         st[x] = 0
         st[x, vals[0]] = 1
         gpu_vs_oracle(f"incremental-x{x}", n, d, inst.edges, rel, u8_to_masks(st),
-                      rac.PATH_BITS, 0, changed=[x])
+                      path, 0, changed=[x])
 
 
-def test_step_cap_reports_not_converged():
+@pytest.mark.parametrize("path", [rac.PATH_BITS, rac.PATH_FUSED])
+def test_step_cap_reports_not_converged(path):
     L, d = 9, 12
     allowed = [(a, b) for a in range(d) for b in range(d) if a < b]
     edges = np.array([[i, i + 1] for i in range(L)], np.int32)
@@ -120,14 +134,14 @@ def test_step_cap_reports_not_converged():
     for a, b in allowed:
         rel[:, a, b] = 1
     dom = np.full(L + 1, (1 << d) - 1, np.uint64)
-    say("[gpu] step cap")
-    net = rac.Net.from_u8(L + 1, d, edges, rel, max_sweeps=4)
+    say(f"[gpu] step cap path={path}")
+    net = rac.Net.from_u8(L + 1, d, edges, rel, max_sweeps=4, path=path)
     with pytest.raises(rac.RacError) as ei:
         net.enforce(dom)
     assert ei.value.code == rac.RAC_ENOTCONVERGED
     net.close()
     # resume: the full run equals a capped run then a second run
-    net = rac.Net.from_u8(L + 1, d, edges, rel)
+    net = rac.Net.from_u8(L + 1, d, edges, rel, path=path)
     full, it_full, _ = net.enforce(dom)
     exp = oracle.rac_sync(L + 1, d, edges, rel, masks_to_u8(dom, d), trace=True)
     mid = u8_to_masks(exp["trace"][3])
@@ -136,14 +150,15 @@ def test_step_cap_reports_not_converged():
     net.close()
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_batch_states_bits(use_graph):
+@pytest.mark.parametrize("path,use_graph", [(rac.PATH_BITS, True), (rac.PATH_BITS, False),
+                                            (rac.PATH_FUSED, True)])
+def test_batch_states_bits(use_graph, path):
     n, d, B = 40, 6, 37
     inst = gen.model_b(12, n, d, 0.5, 0.4)
     doms, _ = gen.partial_assign_states(13, n, d, B, 8)
     rel = inst.rel_u8()
-    say(f"[gpu] batch bits B={B} graph={use_graph}")
-    net = rac.Net.from_u8(n, d, inst.edges, rel, path=rac.PATH_BITS, use_graph=use_graph)
+    say(f"[gpu] batch path={path} B={B} graph={use_graph}")
+    net = rac.Net.from_u8(n, d, inst.edges, rel, path=path, use_graph=use_graph)
     for rep in range(2):
         got, iters, status = net.enforce_batch(doms)
         total_checks = 0
@@ -156,8 +171,9 @@ def test_batch_states_bits(use_graph):
     net.close()
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_group_of_networks(use_graph):
+@pytest.mark.parametrize("path,use_graph", [(rac.PATH_AUTO, True), (rac.PATH_AUTO, False),
+                                            (rac.PATH_FUSED, True)])
+def test_group_of_networks(use_graph, path):
     rng = np.random.default_rng(5)
     nets, doms, insts = [], [], []
     for i in range(23):
@@ -167,8 +183,8 @@ def test_group_of_networks(use_graph):
         insts.append(inst)
         nets.append(rac.Net.from_instance(inst))
         doms.append(gen.preremove(200 + i, n, d, (n * d) // 7))
-    say(f"[gpu] group k={len(nets)} graph={use_graph}")
-    grp = rac.Group(nets, use_graph=use_graph)
+    say(f"[gpu] group k={len(nets)} path={path} graph={use_graph}")
+    grp = rac.Group(nets, use_graph=use_graph, path=path)
     for rep in range(2):
         outs, iters, status = grp.enforce(doms)
         for i, inst in enumerate(insts):
@@ -197,21 +213,22 @@ def test_scan_and_changed_variable_steps(ratio, monkeypatch):
                           rac.PATH_BITS, mode)
     for d in (3, 32, 33, 64):
         test_medium_bits(d, 0)
-    test_incremental_start()
-    test_batch_states_bits(True)
-    test_group_of_networks(True)
+    test_incremental_start(rac.PATH_BITS)
+    test_batch_states_bits(True, rac.PATH_BITS)
+    test_group_of_networks(True, rac.PATH_AUTO)
 
 
-def test_empty_domains_and_isolated_variables():
+@pytest.mark.parametrize("path", [rac.PATH_BITS, rac.PATH_FUSED])
+def test_empty_domains_and_isolated_variables(path):
     n, d = 7, 5
     edges = np.array([[0, 1], [1, 2], [4, 5]], np.int32)
     rel = np.ones((3, d, d), np.uint8)
     dom = np.array([31, 31, 31, 0, 31, 0, 31], np.uint64)   # x3 isolated & empty, x5 empty
     for mode in (0, 1):
-        gpu_vs_oracle("empty-isolated", n, d, edges, rel, dom, rac.PATH_BITS, mode)
+        gpu_vs_oracle("empty-isolated", n, d, edges, rel, dom, path, mode)
     # no constraints at all
     gpu_vs_oracle("no-edges", n, d, np.zeros((0, 2), np.int32), np.zeros((0, d, d), np.uint8),
-                  dom, rac.PATH_BITS, 0)
+                  dom, path, 0)
 
 
 def test_dense_create_matches():
@@ -362,7 +379,7 @@ def test_mfma_step_cap():
     net.close()
 
 
-@pytest.mark.parametrize("path", [rac.PATH_BITS, rac.PATH_MFMA])
+@pytest.mark.parametrize("path", [rac.PATH_BITS, rac.PATH_MFMA, rac.PATH_FUSED])
 def test_batch_device_entry_point_matches_host(path):
     torch = pytest.importorskip("torch")
     n, d, B = 60, 32, 200
@@ -418,7 +435,7 @@ def test_group_keeps_its_own_item_tables():
         net.close()
 
 
-@pytest.mark.parametrize("path", [rac.PATH_BITS, rac.PATH_MFMA])
+@pytest.mark.parametrize("path", [rac.PATH_BITS, rac.PATH_MFMA, rac.PATH_FUSED])
 def test_host_call_after_device_call(path):
     # A host-pointer call made while a device-pointer call on the same net is
     # still in flight (no sync in between) waits for it before reusing the
@@ -450,3 +467,35 @@ def test_host_call_after_device_call(path):
             if s < 5:
                 assert np.array_equal(got2[s], exp) and it2[s] == e_it and st2[s] == e_st
     net.close()
+
+
+@pytest.mark.parametrize("n", [rac.SMALL_MAX_N, rac.SMALL_MAX_N + 1])
+def test_fused_size_limit(n):
+    # The fused path holds a state of at most SMALL_MAX_N variables in LDS:
+    # at the limit it equals the oracle (a sparse network with a few
+    # hundred groups), one variable more is refused with RAC_EUNSUPPORTED.
+    d = 6
+    inst = gen.model_b(41, n, d, 3.0 / n, 0.5)
+    dom = gen.preremove(42, n, d, n // 2)
+    if n > rac.SMALL_MAX_N:
+        say(f"[gpu] fused refuses n={n}")
+        net = rac.Net.from_instance(inst, path=rac.PATH_FUSED)
+        with pytest.raises(rac.RacError) as ei:
+            net.enforce(dom)
+        assert ei.value.code == rac.RAC_EUNSUPPORTED
+        net.close()
+        return
+    for mode in (0, 1):
+        gpu_vs_oracle(f"fused-n{n}", n, d, inst.edges, inst.rel_u8(), dom, rac.PATH_FUSED, mode)
+
+
+def test_fused_dense_multi_group_variables():
+    # Variables with several 64-arc groups (degree up to 119) and uint64 rows:
+    # every wave of the workgroup takes groups of one variable, their failures
+    # meet in the LDS word of the variable.
+    for n, d, p2 in ((120, 10, 0.55), (120, 40, 0.85), (90, 64, 0.9)):
+        inst = gen.model_b(50 + d, n, d, 1.0, p2)
+        dom = gen.preremove(51 + d, n, d, (n * d) // 8)
+        for mode in (0, 1):
+            gpu_vs_oracle(f"fused-dense-d{d}", n, d, inst.edges, inst.rel_u8(), dom,
+                          rac.PATH_FUSED, mode)

@@ -82,6 +82,21 @@ def test_int8_path():
     check("queens6-int8", 6, 6, edges, rel, full_masks(6, 6), batches=(4,), path=rac.PATH_INT8)
 
 
+@pytest.mark.parametrize("which", ["queens7", "random-n25", "random-n16-d33"])
+def test_fused_path(which):
+    # Every search round's enforcements in one fused launch (one workgroup
+    # per child, @changed = its assigned variable, stop on the first wipe-out).
+    if which == "queens7":
+        edges, rel = queens(7)
+        check("queens7-fused", 7, 7, edges, rel, full_masks(7, 7), batches=(1, 5, 256),
+              path=rac.PATH_FUSED)
+        return
+    n, d, p1, p2, seed = (25, 8, 0.3, 0.45, 1) if which == "random-n25" else (16, 33, 0.6, 0.6, 2)
+    inst = gen.model_b(800 + seed + 10 * n, n, d, p1, p2)
+    check(f"{which}-fused", n, d, inst.edges, inst.rel_u8(), full_masks(n, d), batches=(3, 64),
+          path=rac.PATH_FUSED)
+
+
 def test_root_cases():
     # root wiped out
     edges, rel = instance_from_pairs(2, 2, [(0, 1, [(0, 1)])])

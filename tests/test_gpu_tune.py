@@ -46,7 +46,8 @@ def test_batch_tuner_measures_then_reuses(n, d, p1, p2, B):
     net = rac.Net.from_instance(inst, tune=rac.TUNE_MEASURE)
     got, iters, status = net.enforce_batch(doms)
     st = net.stats()
-    assert st.tune_source == 3 and st.path in (rac.PATH_BITS, rac.PATH_INT8, rac.PATH_MFMA)
+    assert st.tune_source == 3 and st.path in (rac.PATH_BITS, rac.PATH_INT8, rac.PATH_MFMA,
+                                               rac.PATH_FUSED)
     check_states(inst, doms, got, iters, status)
     lines = table_lines("batch")
     assert len(lines) == before + 1 and lines[-1][1] == f"path={st.path}"
@@ -77,14 +78,18 @@ def test_single_tuner_measures_then_reuses():
     net2.close()
 
 
-def test_rules_mode_does_not_measure():
-    inst = gen.model_b(320, 64, 16, 0.7, 0.3)
-    doms, _ = gen.partial_assign_states(321, 64, 16, 70, 8)
+@pytest.mark.parametrize("n,expect", [(64, rac.PATH_FUSED), (200, rac.PATH_MFMA)])
+def test_rules_mode_does_not_measure(n, expect):
+    # The fixed rules: many states of a network with at most 2 MiB of bit
+    # rows (n=64: 64 groups of 4 KiB) take the fused path; of a larger dense
+    # one with d <= 32 (n=200: 600 groups, 2.4 MiB), the matrix cores.
+    inst = gen.model_b(320, n, 16, 0.7, 0.3)
+    doms, _ = gen.partial_assign_states(321, n, 16, 70, 8)
     before = len(table_lines("batch"))
     net = rac.Net.from_instance(inst, tune=rac.TUNE_RULES)
     got, iters, status = net.enforce_batch(doms)
     st = net.stats()
-    assert st.tune_source == 0 and st.path == rac.PATH_MFMA   # the fixed rule: dense, d <= 32
+    assert st.tune_source == 0 and st.path == expect
     assert len(table_lines("batch")) == before
     check_states(inst, doms, got, iters, status)
     net.close()
@@ -92,11 +97,11 @@ def test_rules_mode_does_not_measure():
 
 # every candidate the tuner can pick, forced: bit rows and int8 rows with
 # small, default and large work items, the matrix cores with hand-off at 32
-# states and never
+# states and never, the fused path
 @pytest.mark.parametrize("path,item_bytes,handoff", [
     (rac.PATH_BITS, 4096, None), (rac.PATH_BITS, 0, None), (rac.PATH_BITS, 1 << 20, None),
     (rac.PATH_INT8, 0, None), (rac.PATH_INT8, 1 << 20, None),
-    (rac.PATH_MFMA, 0, "32"), (rac.PATH_MFMA, 0, "0")])
+    (rac.PATH_MFMA, 0, "32"), (rac.PATH_MFMA, 0, "0"), (rac.PATH_FUSED, 0, None)])
 def test_tuner_candidates_forced(path, item_bytes, handoff, monkeypatch):
     if handoff is not None:
         monkeypatch.setenv("RAC_MFMA_HANDOFF", handoff)
