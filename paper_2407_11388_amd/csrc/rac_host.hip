@@ -1187,9 +1187,10 @@ static int64_t path_rows_bytes(const rac_net *net, int32_t path) {
 // launch): networks whose bit rows fit the L2 caches many times over, where
 // one workgroup's latency-bound sweep beats three launches per step. Bounds
 // on the bit rows of one state, measured on MI355X: 512 KiB for a single
-// state, 2 MiB for batches of states, 1 MiB for search rounds (whose
-// children re-examine few arcs per step).
-enum { kFusedRuleOne = 512 << 10, kFusedRuleBatch = 2 << 20, kFusedRuleSearch = 1 << 20 };
+// state, 2 MiB for batches of states and for search rounds (whose children
+// re-examine few arcs per step: model-B n = 500, 1.5 MiB of rows, searches
+// 1.8x faster fused; n = 1000, 6 MiB, 2x slower).
+enum { kFusedRuleOne = 512 << 10, kFusedRuleBatch = 2 << 20, kFusedRuleSearch = 2 << 20 };
 static bool fused_rule(const rac_net *net, int64_t max_rows_bytes) {
     if (net->n > kSmallMaxN) return false;
     return path_rows_bytes(net, RAC_PATH_BITS) <= max_rows_bytes;
@@ -1442,10 +1443,10 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
     const int32_t path = net->opt.path == RAC_PATH_INT8 ? RAC_PATH_INT8 : RAC_PATH_BITS;
     PathData &pd = path == RAC_PATH_INT8 ? net->i8 : net->bits;
     // the enforcements themselves: one fused launch per round when asked for,
-    // or by the fixed rule on small networks
-    const bool fused = net->opt.path == RAC_PATH_FUSED ||
-                       (net->opt.path == RAC_PATH_AUTO && net->opt.item_bytes == 0 &&
-                        fused_rule(net, kFusedRuleSearch));
+    // or by the fixed rules on small networks (the root: one state's rule)
+    const bool rules = net->opt.path == RAC_PATH_AUTO && net->opt.item_bytes == 0;
+    const bool fused = net->opt.path == RAC_PATH_FUSED || (rules && fused_rule(net, kFusedRuleSearch));
+    const bool fused_root = net->opt.path == RAC_PATH_FUSED || (rules && fused_rule(net, kFusedRuleOne));
     const int32_t run_path = fused ? RAC_PATH_FUSED : path;
     // a wipe-out anywhere ends a node: stop on the first one (same status as
     // running to the fixpoint, fewer steps)
@@ -1462,7 +1463,7 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
     RAC_TRY(ensure_path(net, path, call_target(net, 1)));
     RAC_TRY(prepare_net_runner(net, 1, pd));
     HIP_TRY(hipMemcpyAsync(r.din, dom, (size_t)n * 8, hipMemcpyHostToDevice, s));
-    RAC_TRY(run_states(net, 1, run_path, nullptr, 0, false));
+    RAC_TRY(run_states(net, 1, fused_root ? RAC_PATH_FUSED : path, nullptr, 0, false));
     std::vector<uint64_t> root((size_t)n);
     int32_t root_status = 0, hrc = 0, root_iters = 0;
     HIP_TRY(hipMemcpyAsync(root.data(), r.dout, (size_t)n * 8, hipMemcpyDeviceToHost, s));

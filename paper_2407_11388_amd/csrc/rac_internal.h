@@ -39,10 +39,11 @@ constexpr int kScratchWords = kItemVars + kSparseGroups * kGroup / 4;
 
 // Small problems in one launch (small_fixpoint_kernel): at most kSmallMaxN
 // variables, one workgroup of up to kSmallMaxThreads per problem; LDS of
-// 3 * 8 + 2 bytes per variable.
+// 3 * 8 + 2 * 4 + 2 * 2 + 2 bytes per variable.
 constexpr int kSmallMaxN = 2048;
 constexpr int kSmallMaxThreads = 1024;
-inline size_t small_lds_bytes(int32_t n) { return (size_t)n * 26 + 16; }
+constexpr int kSmallWalkRatio = 4;   // walk the changed variables' arcs when at most 1/4 of all
+inline size_t small_lds_bytes(int32_t n) { return (size_t)n * 38 + 16; }
 // Threads of the workgroup for networks of at most `groups` 64-arc groups:
 // about 4 groups per wave and step, 1 to max_waves (<= 16) waves.
 inline int small_threads(int64_t groups, int max_waves) {

@@ -821,20 +821,28 @@ __global__ __launch_bounds__(256) void update_kernel(Launch L, int k) {
 // Small problems in one launch: one workgroup per problem runs every step of
 // Eq. (1) with the problem's domains in LDS (double-buffered), so a step
 // costs two workgroup barriers instead of three dependent kernel launches.
-// Bit rows only (ROW32 / ROW64), n <= kSmallMaxN. Wave w takes the groups
-// w, w + waves, ... of the network (lane = arc of a group; a group's arcs all
-// leave one variable), tests the rows of each arc into a variable changed in
-// the previous step against that variable's domain, and ORs the failures per
-// variable in LDS; then every thread updates its variables. Outputs as the
-// finish kernel writes them: domains, step count, status, support checks, and
+// Bit rows only (ROW32 / ROW64), n <= kSmallMaxN. Outputs as the finish
+// kernel writes them: domains, step count, status, support checks, and
 // rc_out = 1 when a problem stopped at the step cap unconverged.
 //
-// One wave's groups follow each other, so the loop hides latency itself: the
-// next group's neighbour indices are loaded while the current group's rows
-// are tested, and a group's row quads are loaded up to 8 at a time.
+// A step re-examines the arcs x -> y into the variables y changed in the
+// previous step (Prop. 2) in one of two ways, chosen per step by their number:
+// * scan: wave w takes the 64-arc groups w, w + waves, ... (lane = arc; a
+//   group's arcs all leave one variable x), tests the rows of each arc into a
+//   changed variable against that variable's domain and ORs the failures of x
+//   into its LDS word. The next group's neighbour indices are loaded while
+//   the current one is tested, a group's row quads up to 8 at a time.
+// * walk: the changed variables' own arcs y -> x, numbered consecutively
+//   over the step's list of changed variables, 64 per wave at a time; a lane
+//   finds its variable y by a binary search over the list's arc offsets,
+//   reads the rows of the reverse arc x -> y (through NetDesc::rpos) and ORs
+//   the values of x without support in dom(y) into x's LDS word.
+// The update phase removes the failures, and lists the changed variables
+// with their arc offsets (one 64-bit LDS atomic per variable: list length in
+// the high word, arcs in the low word, so offsets grow with the list index).
 template <bool WIDE>
-DEV void small_revise(const NetDesc &N, const uint64_t *__restrict__ dom, const uint8_t *__restrict__ chg,
-                      unsigned long long *failx, int wave, int nwaves, int lane, unsigned long long *arcs_seen) {
+DEV void small_scan(const NetDesc &N, const uint64_t *__restrict__ dom, const uint8_t *__restrict__ chg,
+                    unsigned long long *failx, int wave, int nwaves, int lane) {
     constexpr int RPQ = WIDE ? 2 : 4;   // rows per quad
     const GLOBAL u32x4 *rows = as_global(reinterpret_cast<const u32x4 *>(N.rows));
     const GLOBAL int32_t *nbrp = as_global(N.nbrp);
@@ -842,7 +850,6 @@ DEV void small_revise(const NetDesc &N, const uint64_t *__restrict__ dom, const 
     const int64_t ngroups = N.gptr[N.n];
     const int qpa = N.qpa;
     const uint64_t dmask = dmask_of(N.d);
-    unsigned long long seen = 0;
     int64_t g = wave;
     int32_t y_next = -1, x_next = 0;
     if (g < ngroups) {
@@ -858,9 +865,7 @@ DEV void small_revise(const NetDesc &N, const uint64_t *__restrict__ dom, const 
         }
         const int32_t yc = y >= 0 ? y : 0;   // padding arcs read variable 0, unused
         const bool on = y >= 0 && chg[yc];
-        const uint64_t act = __ballot(on);
-        if (!act) continue;
-        seen += __popcll(act);
+        if (!__ballot(on)) continue;
         const uint64_t dy = on ? dom[yc] : ~0ull;   // lanes off: every row has support
         const GLOBAL u32x4 *q = rows + g * qpa * kGroup + lane;
         uint64_t f = 0;
@@ -879,13 +884,57 @@ DEV void small_revise(const NetDesc &N, const uint64_t *__restrict__ dom, const 
             (void)__hip_atomic_fetch_or(failx + x, (unsigned long long)f, __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-    if (lane == 0) *arcs_seen += seen;
+}
+
+template <bool WIDE>
+DEV void small_walk(const NetDesc &N, const uint64_t *__restrict__ dom, const uint16_t *__restrict__ clist,
+                    const uint32_t *__restrict__ cstart, int32_t ncl, int64_t arcs,
+                    unsigned long long *failx, int wave, int nwaves, int lane) {
+    constexpr int RPQ = WIDE ? 2 : 4;
+    const GLOBAL u32x4 *rows = as_global(reinterpret_cast<const u32x4 *>(N.rows));
+    const GLOBAL int32_t *row_ptr = as_global(N.row_ptr);
+    const GLOBAL int32_t *nbr = as_global(N.nbr);
+    const GLOBAL int32_t *rpos = as_global(N.rpos);
+    const int qpa = N.qpa;
+    const uint64_t dmask = dmask_of(N.d);
+    for (int64_t t0 = (int64_t)wave * kWave; t0 < arcs; t0 += (int64_t)nwaves * kWave) {
+        const int64_t t = t0 + lane;
+        if (t >= arcs) continue;
+        // the list entry i with cstart[i] <= t < cstart[i + 1]
+        int32_t lo = 0, hi = ncl - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if ((int64_t)cstart[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const int32_t y = clist[lo];
+        const int32_t j = row_ptr[y] + (int32_t)(t - cstart[lo]);
+        const int32_t x = nbr[j];
+        const int32_t pos = rpos[j];
+        const GLOBAL u32x4 *q = rows + (int64_t)(pos >> 6) * qpa * kGroup + (pos & (kGroup - 1));
+        const uint64_t dy = dom[y];
+        uint64_t f = 0;
+        for (int c0 = 0; c0 < qpa; c0 += 8) {
+            u32x4 v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (c0 + i < qpa) v[i] = q[(int64_t)(c0 + i) * kGroup];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (c0 + i < qpa) f |= (uint64_t)quad_fail<WIDE>(v[i], dy) << ((c0 + i) * RPQ);
+        }
+        f &= dom[x] & dmask;
+        if (f)
+            (void)__hip_atomic_fetch_or(failx + x, (unsigned long long)f, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
 }
 
 __global__ __launch_bounds__(kSmallMaxThreads) void small_fixpoint_kernel(Launch L) {
-    extern __shared__ uint64_t s_lds[];   // dom[2][n], fail[n], then chg[2][n] bytes
-    __shared__ int32_t s_any, s_wipe;
-    __shared__ unsigned long long s_arcs;
+    // dom[2][n] and fail[n] (8 bytes), cstart[2][n] (4), clist[2][n] (2), chg[2][n] (1)
+    extern __shared__ uint64_t s_lds[];
+    __shared__ int32_t s_any[2], s_wipe;
+    __shared__ unsigned long long s_list[2];   // (list length << 32) + arcs of the listed variables
     const int32_t p = blockIdx.x;
     if (p >= problem_count(L)) return;
     const NetDesc &N = net_of(L, p);
@@ -893,48 +942,88 @@ __global__ __launch_bounds__(kSmallMaxThreads) void small_fixpoint_kernel(Launch
     const int64_t off = L.uniform_n > 0 ? (int64_t)p * L.uniform_n : L.prob_off[p];
     uint64_t *dom0 = s_lds, *dom1 = s_lds + n;
     unsigned long long *failx = reinterpret_cast<unsigned long long *>(s_lds + 2 * n);
-    uint8_t *chg0 = reinterpret_cast<uint8_t *>(s_lds + 3 * n), *chg1 = chg0 + n;
+    uint32_t *cst0 = reinterpret_cast<uint32_t *>(s_lds + 3 * n), *cst1 = cst0 + n;
+    uint16_t *cl0 = reinterpret_cast<uint16_t *>(cst1 + n), *cl1 = cl0 + n;
+    uint8_t *chg0 = reinterpret_cast<uint8_t *>(cl1 + n), *chg1 = chg0 + n;
+    const GLOBAL int32_t *deg = as_global(N.deg);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
-    for (int32_t x = tid; x < n; x += blockDim.x) {
-        dom0[x] = L.din[off + x];
-        chg0[x] = L.changed0 ? (L.changed0[off + x] ? 1 : 0) : 1;
-        failx[x] = 0;
-    }
     if (tid == 0) {
-        s_arcs = 0;
+        s_list[0] = 0;
         s_wipe = 0;
     }
+    __syncthreads();
+    for (int32_t x = tid; x < n; x += blockDim.x) {
+        dom0[x] = L.din[off + x];
+        const bool c = L.changed0 ? L.changed0[off + x] != 0 : true;
+        chg0[x] = c ? 1 : 0;
+        failx[x] = 0;
+        if (c && L.changed0) {   // the initial list (all variables: scanned, not listed)
+            const unsigned long long at = __hip_atomic_fetch_add(
+                &s_list[0], (1ull << 32) + (unsigned long long)deg[x], __ATOMIC_RELAXED,
+                __HIP_MEMORY_SCOPE_WORKGROUP);
+            cl0[at >> 32] = (uint16_t)x;
+            cst0[at >> 32] = (uint32_t)at;
+        }
+    }
+    __syncthreads();
+    int32_t ncl = (int32_t)(s_list[0] >> 32);
+    int64_t arcs_cur = L.changed0 ? (int64_t)(s_list[0] & 0xFFFFFFFFull) : N.arcs;
     const int32_t maxs = max_steps(L, N);
-    unsigned long long arcs_total = 0;   // re-examined arcs over all steps (thread 0)
+    long long arcs_total = 0;   // re-examined arcs over all steps
     int32_t k = 0, last_change = 0, wipe_step = 0;
     uint64_t *cur = dom0, *nxt = dom1;
     uint8_t *cin = chg0, *cout = chg1;
     while (k < maxs) {
         ++k;
-        __syncthreads();   // domains, change flags and cleared failures of step k-1 visible
-        unsigned long long seen = 0;
-        if (N.kind == ROW64)
-            small_revise<true>(N, cur, cin, failx, wave, nwaves, lane, &seen);
-        else
-            small_revise<false>(N, cur, cin, failx, wave, nwaves, lane, &seen);
-        if (lane == 0 && seen)
-            (void)__hip_atomic_fetch_add(&s_arcs, seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (tid == 0) s_any = 0;
+        const int li = (k - 1) & 1, lo = k & 1;   // lists: read (step k-1's), written (step k's)
+        // revise: walk the changed variables' arcs when they are listed (every
+        // step but a first one that starts from all variables) and at most a
+        // quarter of the network's arcs; else scan the groups
+        const bool listed = k > 1 || L.changed0 != nullptr;
+        if (N.rpos && listed && arcs_cur * kSmallWalkRatio <= N.arcs) {
+            const uint16_t *cl = li ? cl1 : cl0;
+            const uint32_t *cs = li ? cst1 : cst0;
+            if (N.kind == ROW64)
+                small_walk<true>(N, cur, cl, cs, ncl, arcs_cur, failx, wave, nwaves, lane);
+            else
+                small_walk<false>(N, cur, cl, cs, ncl, arcs_cur, failx, wave, nwaves, lane);
+        } else {
+            if (N.kind == ROW64)
+                small_scan<true>(N, cur, cin, failx, wave, nwaves, lane);
+            else
+                small_scan<false>(N, cur, cin, failx, wave, nwaves, lane);
+        }
+        arcs_total += arcs_cur;
+        if (tid == 0) {
+            s_any[lo] = 0;
+            s_list[lo] = 0;
+        }
         __syncthreads();   // every failure of step k recorded
+        uint16_t *clo = lo ? cl1 : cl0;
+        uint32_t *cso = lo ? cst1 : cst0;
         int any = 0, wiped = 0;
         for (int32_t x = tid; x < n; x += blockDim.x) {
             const uint64_t o = cur[x], nd = o & ~failx[x] & dmask_of(N.d);
             nxt[x] = nd;
-            cout[x] = nd != o ? 1 : 0;
+            const bool c = nd != o;
+            cout[x] = c ? 1 : 0;
             failx[x] = 0;
-            any |= nd != o;
+            any |= c;
             wiped |= nd == 0;
+            if (c) {
+                const unsigned long long at = __hip_atomic_fetch_add(
+                    &s_list[lo], (1ull << 32) + (unsigned long long)deg[x], __ATOMIC_RELAXED,
+                    __HIP_MEMORY_SCOPE_WORKGROUP);
+                clo[at >> 32] = (uint16_t)x;
+                cso[at >> 32] = (uint32_t)at;
+            }
         }
-        if (__ballot(any) && lane == 0) atomicOr(&s_any, 1);
+        if (__ballot(any) && lane == 0) atomicOr(&s_any[lo], 1);
         if (__ballot(wiped) && lane == 0) atomicOr(&s_wipe, 1);
-        __syncthreads();   // the step's change and wipe-out words
-        if (tid == 0) arcs_total = s_arcs;
-        const bool changed = s_any != 0;
+        __syncthreads();   // the step's change and wipe-out words and its list
+        const bool changed = s_any[lo] != 0;
+        ncl = (int32_t)(s_list[lo] >> 32);
+        arcs_cur = (int64_t)(s_list[lo] & 0xFFFFFFFFull);
         if (changed) last_change = k;
         if (s_wipe && wipe_step == 0) wipe_step = k;
         uint64_t *t64 = cur;
@@ -959,7 +1048,7 @@ __global__ __launch_bounds__(kSmallMaxThreads) void small_fixpoint_kernel(Launch
     if (tid == 0) {
         if (L.iters_out) L.iters_out[p] = iters;
         if (L.status_out) L.status_out[p] = wipe_step != 0 ? RAC_WIPEOUT : RAC_CONSISTENT;
-        if (L.checks_out) L.checks_out[p] = (long long)arcs_total * N.d * N.d;
+        if (L.checks_out) L.checks_out[p] = arcs_total * N.d * N.d;
         if (rc && L.rc_out) atomicOr(L.rc_out, 1);
     }
 }
