@@ -428,7 +428,8 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
                         const v16i d0 = mfma8(Aop[u0], ldsb(o0 + t * 512), bias);
                         const v16i d1 = mfma8(Aop[u1], ldsb(o1 + t * 512), bias);
 #pragma unroll
-                        for (int v = 0; v < 16; ++v) rf[t][v] |= (d0[v] & m0) | (d1[v] & lmask);
+                        for (int v = 0; v < 16; ++v)   // two v_and_or each
+                            rf[t][v] = (d1[v] & lmask) | ((d0[v] & m0) | rf[t][v]);
                     }
                 }
             } else {
@@ -442,7 +443,9 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
             }
             load_two(wn, u0);   // this pair's registers now take the next block's operands
         }
-        __syncthreads();   // every wave is done with the stage the next tile goes to
+        // The next tile goes to the stage every wave last read in the previous
+        // block, before the barrier that ended it; one barrier then makes the
+        // tile visible.
         if (more) {
             store((blk - blo + 1) & 1);
             __syncthreads();
