@@ -133,7 +133,7 @@ __device__ __forceinline__ int split_for(const MArgs &A, int active) {
     if (A.force_seg > 0) return A.force_seg < cap ? A.force_seg : cap;
     int sg = tiles > 0 ? A.cus / tiles : 1;
     // workgroups the grid holds for each active tile: those of the idle tiles
-    const int avail = sact > 0 ? (A.words / 4) / sact : 1;
+    const int avail = sact > 0 ? (A.words * 32 / kMS) / sact : 1;
     sg = sg < avail ? sg : avail;
     return sg < 1 ? 1 : (sg > cap ? cap : sg);
 }
@@ -198,7 +198,10 @@ constexpr int kStages = 2;                          // LDS domain tiles (double 
 constexpr int kBTile = kMY * 2 * kMS;               // v4i per domain tile (32 KiB)
 constexpr int kMaxUnits = kMY;                      // operands of a pair in one block: <= 8
 constexpr size_t kMSmem = (size_t)kStages * kBTile * 16;   // 64 KiB
-constexpr int kCopyPerBlock = kMY * 2 * kMS / 64 / kMW;    // 16-byte copies per lane and block: 4
+constexpr int kRowsPerWave = kMY * 2 / kMW;         // domain rows (y, half) each wave copies
+constexpr int kParts = kMS / 64;                     // 64-slot parts of a row
+constexpr int kCopyPerBlock = kRowsPerWave * kParts; // 16-byte copies per lane and block
+static_assert(kMY * 2 % kMW == 0 && kMS % 64 == 0, "the tile copy splits evenly over the waves");
 constexpr int kTabShift = 6;                        // lane tables cover 64 blocks
 
 // Zero-count flags. Domain bytes are 0 or -1 (0xFF). A wave owns the pair of
@@ -334,7 +337,7 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
     auto fetch = [&](int blk) {
 #pragma unroll
         for (int i = 0; i < kCopyPerBlock; ++i) {
-            const int row = wave * 2 + (i >> 1), part = i & 1;
+            const int row = wave * kRowsPerWave + i / kParts, part = i % kParts;
             const int yl = row >> 1, h = row & 1;
             int y = blk * kMY + yl;
             y = y < A.n ? y : A.n - 1;
@@ -345,7 +348,7 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
         v4i *bt = s_lds + stg * kBTile;
 #pragma unroll
         for (int i = 0; i < kCopyPerBlock; ++i) {
-            const int row = wave * 2 + (i >> 1), part = i & 1;
+            const int row = wave * kRowsPerWave + i / kParts, part = i % kParts;
             const int yl = row >> 1, h = row & 1;
             bt[(yl * 2 + h) * kMS + part * 64 + lane] = cp[i];
         }
@@ -626,7 +629,7 @@ __global__ __launch_bounds__(1024) void mfma_finalize_kernel(MArgs A, int k) {
         s_ops = 0;
     }
     // the next step's tile masks start empty (mfma_tile_changed_kernel fills them)
-    for (int64_t i = threadIdx.x; i < (int64_t)A.words / 4 * A.nw32; i += blockDim.x) A.ych[i] = 0u;
+    for (int64_t i = threadIdx.x; i < (int64_t)A.words * 32 / kMS * A.nw32; i += blockDim.x) A.ych[i] = 0u;
     unsigned long long ops = 0;
     __syncthreads();
     for (int c0 = 0; c0 < nact; c0 += 1024) {
