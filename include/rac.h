@@ -225,7 +225,11 @@ int rac_enforce_multi(int32_t k, rac_net *const *nets, uint64_t *const *dom, int
  * A group fixes a list of nets once (device descriptor tables, its own work
  * items, the autotuned choice per net and a captured graph), so repeated
  * calls avoid that set-up. rac_group_enforce has the semantics of
- * rac_enforce_multi. The nets must outlive the group; calls on the member
+ * rac_enforce_multi. With opt's path automatic, item_bytes 0 and tuning not
+ * set to fixed rules, the first rac_group_enforce call measures the group's
+ * work-item size (the one from the group's total work and smaller ones) on
+ * its own inputs and keeps the fastest; rac_group_enforce_device calls use
+ * the size in effect. The nets must outlive the group; calls on the member
  * nets themselves stay valid and do not affect the group.
  */
 int rac_group_create(int32_t k, rac_net *const *nets, const rac_options *opt, rac_group **out);

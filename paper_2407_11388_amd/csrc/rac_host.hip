@@ -252,10 +252,18 @@ struct rac_group {
     NetDesc *d_nets = nullptr;
     int4 *items = nullptr;       // the group's own work-item tables of every net, back to back
     int32_t *pieces = nullptr;
+    int4 *items_inc = nullptr;   // its tables for steps after a full first step (or null: the same)
+    int32_t *pieces_inc = nullptr;
     std::vector<int64_t> h_off;
+    std::vector<int32_t> paths;  // rows of each net (RAC_PATH_BITS / RAC_PATH_INT8)
+    std::vector<NetDesc> descs;  // host copies of d_nets
     Runner run;
     rac_stats last{};
     int64_t total_vars = 0, total_items = 0, rel_bytes = 0, max_n = 0, max_nd = 0, max_groups = 0;
+    int32_t item_target = 0;     // work-item bytes of the item tables of a step over every arc
+    int32_t item_target_inc = 0; // ... of the steps that re-examine arcs into changed variables
+    bool tuned = false;          // the item size is settled (given, measured or by rule)
+    int32_t tune_source = 0;
     bool pending = false;
 };
 
@@ -494,6 +502,9 @@ static int make_items(rac_net *net, PathData &pd, int32_t target) {
     pd.desc.items = pd.items;
     pd.desc.pieces = pd.pieces;
     pd.desc.nitems = pd.nitems;
+    pd.desc.items_inc = pd.items;   // one table for every step
+    pd.desc.pieces_inc = pd.pieces;
+    pd.desc.nitems_inc = pd.nitems;
     if (!pd.d_desc) RAC_TRY(dalloc(&pd.d_desc, 1));
     HIP_TRY(hipMemcpy(pd.d_desc, &pd.desc, sizeof(NetDesc), hipMemcpyHostToDevice));
     return RAC_OK;
@@ -786,7 +797,13 @@ static dim3 grid_init(int64_t nvars) {
 }
 
 // Steps per round: 4, 8, 16, 32, then 64.
-static int32_t round_steps(int round) { return round >= 4 ? 64 : (4 << round); }
+// Steps per round of captured graphs: 4, 4, 8, 8, 16, 32, then 64. Steps past
+// the fixpoint still launch (and return at once), so the early rounds stay
+// short: most calls end within their first 16 to 24 steps.
+static int32_t round_steps(int round) {
+    static const int32_t kSteps[6] = {4, 4, 8, 8, 16, 32};
+    return round < 6 ? kSteps[round] : 64;
+}
 static int32_t round_first_step(int round) {
     int32_t k = 1;
     for (int i = 0; i < round; ++i) k += round_steps(i);
@@ -1944,6 +1961,69 @@ extern "C" int rac_enforce_batch_noalloc(rac_net *net, int32_t B, const uint64_t
 // groups of networks (one state each)
 // ---------------------------------------------------------------------------
 
+// (Re)builds the group's work-item tables for a target item size (the steps
+// that re-examine every arc) and another for the later steps, and uploads
+// them with the net descriptors.
+static int group_items(rac_group *g, int32_t target, int32_t target_inc) {
+    struct Tables {
+        std::vector<int4> items;
+        std::vector<int32_t> pieces;
+        std::vector<size_t> off;
+        std::vector<int32_t> count;
+    };
+    auto build = [&](int32_t t, Tables &T) {
+        std::vector<int4> its;
+        std::vector<int32_t> pcs;
+        T.off.assign((size_t)g->k + 1, 0);
+        T.count.assign((size_t)g->k, 0);
+        for (int32_t i = 0; i < g->k; ++i) {
+            rac_net *net = g->nets[(size_t)i];
+            PathData &pd = g->paths[(size_t)i] == RAC_PATH_INT8 ? net->i8 : net->bits;
+            build_items(net, pd, t, its, pcs);
+            T.items.insert(T.items.end(), its.begin(), its.end());
+            T.pieces.insert(T.pieces.end(), pcs.begin(), pcs.end());
+            T.off[(size_t)i + 1] = T.items.size();
+            T.count[(size_t)i] = (int32_t)its.size();
+        }
+    };
+    Tables A, I;
+    build(target, A);
+    const bool two = target_inc != target;
+    if (two) build(target_inc, I);
+    if (g->stream) HIP_TRY(hipStreamSynchronize(g->stream));   // no launch still reads the old tables
+    dfree(g->items);
+    dfree(g->pieces);
+    dfree(g->items_inc);
+    dfree(g->pieces_inc);
+    RAC_TRY(dalloc(&g->items, A.items.size()));
+    RAC_TRY(dalloc(&g->pieces, A.pieces.size()));
+    HIP_TRY(hipMemcpy(g->items, A.items.data(), A.items.size() * sizeof(int4), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(g->pieces, A.pieces.data(), A.pieces.size() * 4, hipMemcpyHostToDevice));
+    if (two) {
+        RAC_TRY(dalloc(&g->items_inc, I.items.size()));
+        RAC_TRY(dalloc(&g->pieces_inc, I.pieces.size()));
+        HIP_TRY(hipMemcpy(g->items_inc, I.items.data(), I.items.size() * sizeof(int4), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(g->pieces_inc, I.pieces.data(), I.pieces.size() * 4, hipMemcpyHostToDevice));
+    }
+    for (int32_t i = 0; i < g->k; ++i) {
+        rac_net *net = g->nets[(size_t)i];
+        NetDesc &D = g->descs[(size_t)i];
+        D = (g->paths[(size_t)i] == RAC_PATH_INT8 ? net->i8 : net->bits).desc;
+        D.items = g->items + A.off[(size_t)i];
+        D.pieces = g->pieces + A.off[(size_t)i];
+        D.nitems = A.count[(size_t)i];
+        D.items_inc = two ? g->items_inc + I.off[(size_t)i] : D.items;
+        D.pieces_inc = two ? g->pieces_inc + I.off[(size_t)i] : D.pieces;
+        D.nitems_inc = two ? I.count[(size_t)i] : D.nitems;
+    }
+    if (!g->d_nets) RAC_TRY(dalloc(&g->d_nets, (size_t)g->k));
+    HIP_TRY(hipMemcpy(g->d_nets, g->descs.data(), (size_t)g->k * sizeof(NetDesc), hipMemcpyHostToDevice));
+    g->total_items = std::max<int64_t>((int64_t)A.items.size(), two ? (int64_t)I.items.size() : 0);
+    g->item_target = target;
+    g->item_target_inc = target_inc;
+    return RAC_OK;
+}
+
 extern "C" void rac_group_destroy(rac_group *g) {
     if (!g) return;
     (void)hipSetDevice(g->device);
@@ -1953,6 +2033,8 @@ extern "C" void rac_group_destroy(rac_group *g) {
     dfree(g->d_nets);
     dfree(g->items);
     dfree(g->pieces);
+    dfree(g->items_inc);
+    dfree(g->pieces_inc);
     if (g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
 }
@@ -2003,45 +2085,25 @@ extern "C" int rac_group_create(int32_t k, rac_net *const *nets, const rac_optio
             total_bytes += (int64_t)(path == RAC_PATH_INT8 ? net->i8 : net->bits).rows_bytes;
         }
         if (rc) break;
-        // one item size for the whole group, from the group's total work; the
-        // item tables are the group's own (the nets' tables may be rebuilt by
+        // one item size for the whole group, from the group's total work (the
+        // autotuner may measure smaller ones on the first call); the item
+        // tables are the group's own (the nets' tables may be rebuilt by
         // calls on the nets themselves)
-        const int32_t target = o.item_bytes > 0 ? o.item_bytes : default_item_bytes(g->device, total_bytes);
-        std::vector<int4> all_items, its;
-        std::vector<int32_t> all_pieces, pcs;
-        std::vector<size_t> item_off((size_t)k + 1, 0);
+        g->descs = descs;
         for (int32_t i = 0; i < k; ++i) {
             rac_net *net = nets[i];
-            PathData &pd = paths[(size_t)i] == RAC_PATH_INT8 ? net->i8 : net->bits;
-            build_items(net, pd, target, its, pcs);
-            all_items.insert(all_items.end(), its.begin(), its.end());
-            all_pieces.insert(all_pieces.end(), pcs.begin(), pcs.end());
-            item_off[(size_t)i + 1] = all_items.size();
-            descs[(size_t)i] = pd.desc;
-            descs[(size_t)i].nitems = (int32_t)its.size();
             g->h_off[(size_t)i + 1] = g->h_off[(size_t)i] + net->n;
-            g->total_items += (int64_t)its.size();
-            g->rel_bytes += (int64_t)pd.rows_bytes;
+            g->rel_bytes += (int64_t)(paths[(size_t)i] == RAC_PATH_INT8 ? net->i8 : net->bits).rows_bytes;
             g->max_n = std::max<int64_t>(g->max_n, net->n);
             g->max_groups = std::max<int64_t>(g->max_groups, net->groups);
         }
-        if ((rc = dalloc(&g->items, all_items.size()))) break;
-        if ((rc = dalloc(&g->pieces, all_pieces.size()))) break;
-        if (hipMemcpy(g->items, all_items.data(), all_items.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(g->pieces, all_pieces.data(), all_pieces.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
-            rc = set_error(RAC_EHIP, "hipMemcpy of the group's work items");
-            break;
-        }
-        for (int32_t i = 0; i < k; ++i) {
-            descs[(size_t)i].items = g->items + item_off[(size_t)i];
-            descs[(size_t)i].pieces = g->pieces + item_off[(size_t)i];
-        }
         g->total_vars = g->h_off[(size_t)k];
-        if ((rc = dalloc(&g->d_nets, (size_t)k))) break;
-        if (hipMemcpy(g->d_nets, descs.data(), (size_t)k * sizeof(NetDesc), hipMemcpyHostToDevice) != hipSuccess) {
-            rc = set_error(RAC_EHIP, "hipMemcpy of descriptors");
-            break;
+        g->paths = paths;
+        {
+            const int32_t t = o.item_bytes > 0 ? o.item_bytes : default_item_bytes(g->device, total_bytes);
+            if ((rc = group_items(g, t, t))) break;
         }
+        g->tuned = o.item_bytes > 0 || o.path != RAC_PATH_AUTO || effective_tune_mode(o) == kTuneRules;
         if ((rc = ensure_runner(g->run, k, g->total_vars))) break;
         std::vector<int32_t> pn((size_t)k);
         for (int32_t i = 0; i < k; ++i) {
@@ -2092,19 +2154,55 @@ extern "C" int rac_group_enforce(rac_group *g, uint64_t *const *dom, int32_t *it
         memcpy(r.h_dom + g->h_off[(size_t)i], dom[i], (size_t)g->nets[(size_t)i]->n * 8);
     }
     HIP_TRY(hipMemcpyAsync(r.din, r.h_dom, h.size() * 8, hipMemcpyHostToDevice, g->stream));
-    Launch L = group_launch(g, r.din, r.dout, r.iters, r.status);
-    if (g->opt.path == RAC_PATH_FUSED)
-        RAC_TRY(launch_fused(r, g->stream, L, (int32_t)g->max_n, g->max_groups,
-                             g->k == 1 ? kFusedWavesOne : kFusedWavesBatch, g->opt.profile != 0,
-                             g->total_vars));
-    else
-        RAC_TRY(launch_fixpoint(r, g->device, g->stream, L, g->total_vars, g->total_items,
-                                step_cap(g->opt, g->max_nd), g->opt.use_graph != 0,
-                                g->opt.profile != 0, g->total_vars));
     std::vector<int32_t> hi, hs;
     std::vector<long long> hc;
     int32_t hrc = 0;
-    RAC_TRY(read_results(r, g->stream, g->k, g->total_vars, h.data(), hc, hi, hs, &hrc));
+    auto run_once = [&]() -> int {
+        Launch L = group_launch(g, r.din, r.dout, r.iters, r.status);
+        if (g->opt.path == RAC_PATH_FUSED)
+            RAC_TRY(launch_fused(r, g->stream, L, (int32_t)g->max_n, g->max_groups,
+                                 g->k == 1 ? kFusedWavesOne : kFusedWavesBatch, g->opt.profile != 0,
+                                 g->total_vars));
+        else
+            RAC_TRY(launch_fixpoint(r, g->device, g->stream, L, g->total_vars, g->total_items,
+                                    step_cap(g->opt, g->max_nd), g->opt.use_graph != 0,
+                                    g->opt.profile != 0, g->total_vars));
+        return read_results(r, g->stream, g->k, g->total_vars, h.data(), hc, hi, hs, &hrc);
+    };
+    if (!g->tuned) {
+        // the autotuner: the work-item size of the group's later steps,
+        // measured on this call's own inputs (every size gives the same
+        // results). Items sized from the group's total work suit the first
+        // step, where every arc is re-examined, and keep that size; smaller
+        // ones spread the later steps, where a few large instances run on,
+        // over the chip.
+        const int32_t t_all = g->item_target;
+        std::vector<int32_t> cand = {t_all};
+        for (int32_t t : {64 << 10, 16 << 10})
+            if (t < t_all) cand.push_back(t);
+        int32_t best_t = g->item_target_inc;
+        double best = 1e30;
+        for (int32_t t : cand) {
+            if (t != g->item_target_inc) RAC_TRY(group_items(g, t_all, t));
+            double tm = 1e30;
+            for (int rep = 0; rep < 3; ++rep) {
+                const auto t0 = std::chrono::steady_clock::now();
+                const int rc = run_once();
+                if (rc != RAC_OK) return rc;
+                if (rep > 0)
+                    tm = std::min(tm, std::chrono::duration<double, std::milli>(
+                                          std::chrono::steady_clock::now() - t0).count());
+            }
+            if (tm < best) {
+                best = tm;
+                best_t = t;
+            }
+        }
+        if (best_t != g->item_target_inc) RAC_TRY(group_items(g, t_all, best_t));
+        g->tuned = true;
+        g->tune_source = kSourceMeasured;
+    }
+    RAC_TRY(run_once());
     for (int32_t i = 0; i < g->k; ++i)
         memcpy(dom[i], h.data() + g->h_off[(size_t)i], (size_t)g->nets[(size_t)i]->n * 8);
     if (iters) memcpy(iters, hi.data(), (size_t)g->k * 4);
@@ -2119,6 +2217,8 @@ extern "C" int rac_group_enforce(rac_group *g, uint64_t *const *dom, int32_t *it
     g->last.device_ms = ms;
     g->last.path = g->opt.path == RAC_PATH_FUSED ? RAC_PATH_FUSED : RAC_PATH_BITS;
     g->last.relation_bytes = g->rel_bytes;
+    g->last.item_bytes = g->item_target_inc;
+    g->last.tune_source = g->tune_source;
     revise_timing(r, &g->last.kernel_ms, &g->last.kernel_launches,
                  &g->last.first_kernel_ms);
     return rc_from_device(hrc);
@@ -2158,6 +2258,8 @@ extern "C" int rac_group_sync_status(rac_group *g) {
     g->last.device_ms = ms;
     g->last.relation_bytes = g->rel_bytes;
     g->last.path = g->opt.path == RAC_PATH_FUSED ? RAC_PATH_FUSED : RAC_PATH_BITS;
+    g->last.item_bytes = g->item_target_inc;
+    g->last.tune_source = g->tune_source;
     revise_timing(g->run, &g->last.kernel_ms, &g->last.kernel_launches, &g->last.first_kernel_ms);
     return rc_from_device(hrc);
 }
@@ -2175,6 +2277,7 @@ extern "C" int rac_enforce_multi(int32_t k, rac_net *const *nets, uint64_t *cons
     if (o.path == RAC_PATH_MFMA) o.path = RAC_PATH_AUTO;
     rac_group *g = nullptr;
     RAC_TRY(rac_group_create(k, nets, &o, &g));
+    g->tuned = true;   // one call: the item size from the group's total work, unmeasured
     const int rc = rac_group_enforce(g, dom, iters, status);
     rac_group_destroy(g);
     return rc;

@@ -70,6 +70,9 @@ struct NetDesc {
     const int4 *items;        // [nitems] {x_begin, x_end, unit_begin, unit_end}; units are
                               // groups for bit rows, arcs for int8 rows
     const int32_t *pieces;    // [nitems] 0: whole variables; k >= 1: one piece of x split in k
+    const int4 *items_inc;    // [nitems_inc] the items of steps that re-examine only the arcs
+    const int32_t *pieces_inc;// into changed variables (may be finer; else the same table)
+    int32_t nitems_inc;
     int32_t n, d, dp, kind;
     int32_t nitems, qpa;
     int32_t pchunks;          // pieces of 64 arcs of the largest degree (bit rows)

@@ -522,7 +522,9 @@ DEV void plan_problems(const Launch &L, int k, int32_t nprob, int32_t pt, int32_
                 push = (int64_t)C.nchg[0] * N.pchunks * kWave * L.push_ratio <= N.arcs;
         }
         push = push && on;
-        items[i] = !on ? 0 : push ? (int64_t)C.nchg[(k - 1) & 1] * N.pchunks : N.nitems;
+        const bool all = k == 1 && L.changed0 == nullptr;   // every arc re-examined
+        items[i] = !on ? 0 : push ? (int64_t)C.nchg[(k - 1) & 1] * N.pchunks
+                                  : all ? N.nitems : N.nitems_inc;
         on_m |= (uint32_t)on << i;
         push_m |= (uint32_t)push << i;
         tot += items[i];
@@ -684,8 +686,8 @@ __global__ __launch_bounds__(kWave) void revise_kernel(Launch L, int k) {
             else process_push_item<false>(L, N, k, off, y, ci - i * N.pchunks);
             continue;
         }
-        const int4 it = N.items[ci];
-        const int32_t pieces = N.pieces[ci];
+        const int4 it = all ? N.items[ci] : N.items_inc[ci];
+        const int32_t pieces = all ? N.pieces[ci] : N.pieces_inc[ci];
         const uint64_t *gdom = L.ws.dom[(k - 1) & 1] + off;
         const uint32_t *gchg = L.ws.chg[(k - 1) & 1] + off;
         if (N.n <= L.stage_vars) {
