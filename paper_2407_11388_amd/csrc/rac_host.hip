@@ -855,8 +855,12 @@ static int build_round(Runner &r, int round, const Launch &L, const StepGrids &s
     for (int32_t i = 0; i < K; ++i) {
         void *pk[2] = {&args, &ks[(size_t)i]};
         void *pn[2] = {&args, &ks[(size_t)i + 1]};
-        RAC_TRY(add_node(rg.graph, &prev, (const void *)revise_kernel, sg.revise, dim3(kWave),
-                         sg.smem, pk));
+        if (L.shared_rows)
+            RAC_TRY(add_node(rg.graph, &prev, (const void *)revise_shared_kernel, sg.revise,
+                             dim3(kWave), 0, pk));
+        else
+            RAC_TRY(add_node(rg.graph, &prev, (const void *)revise_kernel, sg.revise, dim3(kWave),
+                             sg.smem, pk));
         RAC_TRY(add_node(rg.graph, &prev, (const void *)update_kernel, sg.update, dim3(256), 0, pk));
         RAC_TRY(add_node(rg.graph, &prev, (const void *)plan_kernel, dim3(1), dim3(1024), 0, pn));
     }
@@ -924,7 +928,10 @@ static int launch_fixpoint(Runner &r, int device, hipStream_t stream, const Laun
                 const int32_t kk = k + i;
                 const bool timed = profile && kk <= kProfSteps;
                 if (timed) HIP_TRY(hipEventRecord(r.kev[2 * (kk - 1)], stream));
-                hipLaunchKernelGGL(revise_kernel, sg.revise, dim3(kWave), sg.smem, stream, L, kk);
+                if (L.shared_rows)
+                    hipLaunchKernelGGL(revise_shared_kernel, sg.revise, dim3(kWave), 0, stream, L, kk);
+                else
+                    hipLaunchKernelGGL(revise_kernel, sg.revise, dim3(kWave), sg.smem, stream, L, kk);
                 if (timed) HIP_TRY(hipEventRecord(r.kev[2 * (kk - 1) + 1], stream));
                 hipLaunchKernelGGL(update_kernel, sg.update, dim3(256), 0, stream, L, kk);
                 hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, stream, L, kk + 1);
@@ -1360,6 +1367,13 @@ extern "C" int rac_enforce(rac_net *net, uint64_t *dom, const int32_t *changed, 
     return enforce_one(net, dom, dom, changed, n_changed, iters, status, c);
 }
 
+// The hand-off's bit-row steps read each group's rows once for several
+// states (revise_shared_kernel); RAC_SHARED_ROWS=0 revises state by state.
+static bool shared_rows_on() {
+    const char *e = getenv("RAC_SHARED_ROWS");
+    return !(e && e[0] == '0');
+}
+
 // States still active when at most this many remain leave the matrix-core
 // path and finish on the bit-row path, whose incremental steps
 // touch only arcs into changed variables.
@@ -1397,8 +1411,16 @@ static int run_mfma(rac_net *net, int32_t B, const uint64_t *d_in, uint64_t *d_o
         L.arcs1 = 0;   // the matrix-core finaliser already counted step k+1
         const int32_t maxs = net->opt.max_sweeps > 0 ? net->opt.max_sweeps : net->n * net->d + 1;
         L.max_sweeps = maxs - k;
-        RAC_TRY(launch_fixpoint(r, net->device, s, L, (int64_t)P * net->n, (int64_t)pd.nitems * P,
-                                maxs - k, true, false));
+        // the states left are those with long, dense propagation: each step
+        // reads every group's rows once for up to kSharedStates of them
+        int64_t items = (int64_t)pd.nitems * P;
+        if (shared_rows_on() && pd.desc.kind == ROW32) {
+            L.shared_rows = 1;
+            L.stage_vars = 0;
+            items = net->groups * ((P + kSharedStates - 1) / kSharedStates);
+        }
+        RAC_TRY(launch_fixpoint(r, net->device, s, L, (int64_t)P * net->n, items, maxs - k, true,
+                                false));
         RAC_TRY(mfma_merge(net->mfma, k, r.dout, r.iters, r.status, r.checks, r.rc, s));
     }
     RAC_TRY(mfma_finish(net->mfma, d_it, d_st, s));

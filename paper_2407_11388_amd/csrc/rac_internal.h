@@ -36,6 +36,8 @@ constexpr int kSparseGroups = 16;
 // failing values of the item's variables (kItemVars words) and the compacted
 // active arcs of a sparse batch (kSparseGroups * 64 16-bit codes).
 constexpr int kScratchWords = kItemVars + kSparseGroups * kGroup / 4;
+// States per task of revise_shared_kernel (each task reads one group's rows once).
+constexpr int kSharedStates = 16;
 
 // Small problems in one launch (small_fixpoint_kernel): at most kSmallMaxN
 // variables, one workgroup of up to kSmallMaxThreads per problem; LDS of
@@ -137,6 +139,9 @@ struct Launch {
     const int32_t *nprob_dev; // non-null: the number of problems is *nprob_dev (<= nprob),
                               // read on the device when each kernel starts, so that one
                               // captured graph serves calls with different counts
+    int32_t shared_rows;      // 1: every problem a state of nets[0] (uint32 rows) and the
+                              // steps revise with revise_shared_kernel
+    int32_t pad_;
 };
 
 // Records a message for rac_last_error() and returns `code` (rac_host.hip).
@@ -147,6 +152,7 @@ __global__ void init_kernel(Launch L);
 __global__ void list_changed0_kernel(Launch L);
 __global__ void plan_kernel(Launch L, int k);
 __global__ void revise_kernel(Launch L, int k);
+__global__ void revise_shared_kernel(Launch L, int k);
 __global__ void update_kernel(Launch L, int k);
 __global__ void finish_kernel(Launch L);
 __global__ void small_fixpoint_kernel(Launch L);

@@ -820,6 +820,68 @@ __global__ __launch_bounds__(256) void update_kernel(Launch L, int k) {
     }
 }
 
+// Step k for many states of one network at once (Launch::shared_rows; uint32
+// bit rows, d <= 32): task t covers the 64-arc group g = t mod G of the
+// network and the chunk t div G of kSharedStates listed states. Each lane
+// loads its arc's rows once and tests them against the neighbour's domain in
+// every state of the chunk in which that neighbour changed in step k-1
+// (Prop. 2), so a step reads the rows once per chunk of states instead of
+// once per state. The next state's change flag and domain are loaded while
+// the current one is tested. Failing values go to the accumulators with one
+// atomic per (group, state) that has any.
+__global__ __launch_bounds__(kWave) void revise_shared_kernel(Launch L, int k) {
+    const int32_t nact = L.ws.plan->nact;
+    if (nact == 0) return;
+    const NetDesc &N = L.nets[0];
+    const int64_t G = N.gptr[N.n];
+    const int64_t tasks = G * ((nact + kSharedStates - 1) / kSharedStates);
+    const int lane = threadIdx.x & (kWave - 1);
+    const GLOBAL u32x4 *rows = as_global(reinterpret_cast<const u32x4 *>(N.rows));
+    const GLOBAL uint64_t *dom = as_global(L.ws.dom[(k - 1) & 1]);
+    const GLOBAL uint32_t *chg = as_global(L.ws.chg[(k - 1) & 1]);
+    const GLOBAL int32_t *act = as_global(L.ws.act);
+    const int64_t n = L.uniform_n;
+    const int qpa = N.qpa;   // <= 8 for uint32 rows
+    const uint32_t dmask = (uint32_t)dmask_of(N.d);
+    for (int64_t t = blockIdx.x; t < tasks; t += gridDim.x) {
+        const int64_t g = t % G;
+        const int32_t i0 = (int32_t)(t / G) * kSharedStates;
+        const int32_t i1 = nact < i0 + kSharedStates ? nact : i0 + kSharedStates;
+        const int32_t x = N.gown[g];
+        const int32_t y = N.nbrp[g * kGroup + lane];
+        const int32_t yc = y >= 0 ? y : 0;   // padding arcs read variable 0, unused
+        u32x4 v[8];
+        const GLOBAL u32x4 *q = rows + g * qpa * kGroup + lane;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (i < qpa) v[i] = q[(int64_t)i * kGroup];
+        int64_t off_n = (int64_t)act[i0] * n;
+        uint32_t cy_n = chg[off_n + yc];
+        uint64_t dy_n = dom[off_n + yc];
+        for (int32_t i = i0; i < i1; ++i) {
+            const int64_t off = off_n;
+            const uint32_t cy = cy_n;
+            const uint64_t dy = dy_n;
+            if (i + 1 < i1) {
+                off_n = (int64_t)act[i + 1] * n;
+                cy_n = chg[off_n + yc];
+                dy_n = dom[off_n + yc];
+            }
+            const bool on = y >= 0 && cy != 0;
+            if (!__ballot(on)) continue;
+            uint32_t f = 0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (c < qpa) f |= quad_fail<false>(v[c], dy) << (4 * c);
+            if (!on) f = 0;
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) f |= (uint32_t)__shfl_xor((int)f, o, kWave);
+            f &= (uint32_t)dom[off + x] & dmask;
+            if (lane == 0 && f) or_fail(L, off + x, f);
+        }
+    }
+}
+
 // Small problems in one launch: one workgroup per problem runs every step of
 // Eq. (1) with the problem's domains in LDS (double-buffered), so a step
 // costs two workgroup barriers instead of three dependent kernel launches.
