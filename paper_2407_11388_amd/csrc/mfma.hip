@@ -12,16 +12,17 @@
 // accumulator (two arcs per accumulator chain, see kBias below) and ORs the
 // flags over y.
 //
-// Tiling. A workgroup of 8 waves owns 16 variables x (two per wave) and 128
-// states (4 sub-tiles of 32). It walks y = 0..n-1 in blocks of 8. The domain
-// bytes of the block for its 128 states (stored per variable in the order of
-// the active-state slots, so one (y, half) row of 128 slots is 2 KiB of
-// consecutive memory) and the relation rows of its 16 variables for the
-// block's arcs (arcs sorted by y) are copied straight from global memory into
-// a 3-stage LDS ring, two blocks ahead of the products; every wave then
-// multiplies each of its x's arcs in the block with the staged bytes, one
-// v_mfma_i32_32x32x32_i8 per (arc, sub-tile). Workgroups of one x-tile are
-// placed on one XCD so that the relation rows they share meet in that XCD's
+// Tiling. A workgroup of 8 waves owns 16 variables x (a pair per wave) and
+// 128 states (4 sub-tiles of 32). It walks y = 0..n-1 in blocks of 8. The
+// domain bytes of the block for its 128 states (stored per variable in the
+// order of the active-state slots, so one (y, half) row of 128 slots is
+// 2 KiB of consecutive memory) are loaded into registers one block ahead and
+// written to the other half of a 2-stage LDS buffer at the end of the block;
+// each wave loads its pair's relation operands for the block's neighbours
+// (packed once per network, see mfma_pack_ops_kernel) into registers, also a
+// block ahead, and multiplies them with the staged bytes, one
+// v_mfma_i32_32x32x32_i8 per (operand, sub-tile). Workgroups of one x-tile
+// are placed on one XCD so that the operands they share meet in that XCD's
 // L2.
 //
 // Steps. Each step writes the new domain bytes (double buffer), and per
