@@ -796,17 +796,19 @@ static dim3 grid_init(int64_t nvars) {
     return dim3((unsigned)b);
 }
 
-// Steps per round: 4, 8, 16, 32, then 64.
-// Steps per round of captured graphs: 4, 4, 8, 8, 16, 32, then 64. Steps past
-// the fixpoint still launch (and return at once), so the early rounds stay
-// short: most calls end within their first 16 to 24 steps.
-static int32_t round_steps(int round) {
+// Steps per round of captured graphs: 4, 4, 8, 8, 16, 32, then 64 (one
+// problem: 2, 4, 8, 8, ...). Steps past the fixpoint still launch (and return
+// at once), so the early rounds stay short: most calls end within their first
+// 16 to 24 steps, and a single state that is already arc consistent or
+// nearly so (one or two steps) runs no empty step at all or only one.
+static int32_t round_steps(int round, bool single) {
     static const int32_t kSteps[6] = {4, 4, 8, 8, 16, 32};
+    if (round == 0 && single) return 2;
     return round < 6 ? kSteps[round] : 64;
 }
-static int32_t round_first_step(int round) {
+static int32_t round_first_step(int round, bool single) {
     int32_t k = 1;
-    for (int i = 0; i < round; ++i) k += round_steps(i);
+    for (int i = 0; i < round; ++i) k += round_steps(i, single);
     return k;
 }
 
@@ -849,7 +851,7 @@ static int build_round(Runner &r, int round, const Launch &L, const StepGrids &s
         void *pp[2] = {&args, &one};
         RAC_TRY(add_node(rg.graph, &prev, (const void *)plan_kernel, dim3(1), dim3(1024), 0, pp));
     }
-    const int32_t k0 = round_first_step(round), K = round_steps(round);
+    const int32_t k0 = round_first_step(round, L.nprob == 1), K = round_steps(round, L.nprob == 1);
     std::vector<int32_t> ks((size_t)K + 1);
     for (int32_t i = 0; i <= K; ++i) ks[(size_t)i] = k0 + i;
     for (int32_t i = 0; i < K; ++i) {
@@ -912,7 +914,7 @@ static int launch_fixpoint(Runner &r, int device, hipStream_t stream, const Laun
     HIP_TRY(hipEventRecord(r.ev0, stream));
     int32_t k = 0;   // steps enqueued
     for (int round = 0;; ++round) {
-        const int32_t K = round_steps(round);
+        const int32_t K = round_steps(round, L.nprob == 1);
         if (graphs) {
             if ((int)r.rounds.size() <= round || !r.rounds[(size_t)round].exec)
                 RAC_TRY(build_round(r, round, L, sg));
@@ -1958,7 +1960,7 @@ extern "C" int rac_enforce_batch_noalloc(rac_net *net, int32_t B, const uint64_t
     hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, L, 1);
     int32_t k = 0;
     for (int round = 0;; ++round) {
-        const int32_t K = round_steps(round);
+        const int32_t K = round_steps(round, B == 1);
         for (int32_t i = 1; i <= K; ++i) {
             hipLaunchKernelGGL(revise_kernel, dim3((unsigned)g), dim3(kWave), smem, s, L, k + i);
             hipLaunchKernelGGL(update_kernel, gupd, dim3(256), 0, s, L, k + i);
