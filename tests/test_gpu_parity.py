@@ -187,6 +187,10 @@ def test_group_of_networks(use_graph, path):
     grp = rac.Group(nets, use_graph=use_graph, path=path)
     for rep in range(2):
         outs, iters, status = grp.enforce(doms)
+        if path == rac.PATH_AUTO:
+            # the first call measured the work-item size of the later steps
+            st = grp.stats()
+            assert st.tune_source == 3 and st.item_bytes >= 16 << 10
         for i, inst in enumerate(insts):
             exp, e_it, e_st, _, _ = oracle_expect(inst.n, inst.d, inst.edges, inst.rel_u8(), doms[i])
             assert np.array_equal(outs[i], exp), f"instance {i}"
@@ -278,6 +282,19 @@ def test_batch_states_mfma(n, d, B, p1, p2, handoff, monkeypatch):
                 total_checks += e_ch
             assert st.support_checks == total_checks
         net.close()
+
+
+@pytest.mark.parametrize("n,d,B,p1,p2", [(45, 10, 130, 0.8, 0.5), (100, 32, 257, 0.8, 0.25),
+                                         (70, 17, 129, 0.4, 0.7)])
+def test_batch_states_mfma_handoff_state_by_state(n, d, B, p1, p2, monkeypatch):
+    # The hand-off's bit-row steps normally read each group's rows once for
+    # up to 16 states (revise_shared_kernel); RAC_SHARED_ROWS=0 revises the
+    # handed-over states one by one. Both equal the oracle, with every state
+    # handed over after the first matrix-core steps and with the default
+    # threshold.
+    monkeypatch.setenv("RAC_SHARED_ROWS", "0")
+    for handoff in ("100000", "32"):
+        test_batch_states_mfma(n, d, B, p1, p2, handoff, monkeypatch)
 
 
 @pytest.mark.parametrize("segments", ["2", "3", "4"])
