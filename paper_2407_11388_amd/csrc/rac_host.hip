@@ -218,6 +218,8 @@ struct Runner {
     size_t graph_smem = 0;
 };
 
+struct SearchWork;   // rac_search's device workspace, kept between searches
+
 struct rac_net {
     int32_t n = 0, d = 0;
     int64_t m = 0, arcs = 0;
@@ -241,6 +243,7 @@ struct rac_net {
     rac_stats last{};
     bool pending = false;      // a device-pointer call awaiting rac_sync_status
     int32_t tune_source = 0;   // of the last call (rac_stats.tune_source)
+    SearchWork *search = nullptr;
 };
 
 struct rac_group {
@@ -400,11 +403,14 @@ static void release_path(PathData &pd) {
 static int settle(rac_net *net) { return net->pending ? rac_sync_status(net) : RAC_OK; }
 static int settle(rac_group *g) { return g->pending ? rac_group_sync_status(g) : RAC_OK; }
 
+static void release_search(rac_net *net);
+
 extern "C" void rac_destroy(rac_net *net) {
     if (!net) return;
     (void)hipSetDevice(net->device);
     (void)settle(net);
     if (net->stream) (void)hipStreamSynchronize(net->stream);
+    release_search(net);
     release_runner(net->run);
     release_path(net->bits);
     release_path(net->i8);
@@ -1433,16 +1439,18 @@ static int run_mfma(rac_net *net, int32_t B, const uint64_t *d_in, uint64_t *d_o
 // batched MAC search (Algorithm 2)
 // ---------------------------------------------------------------------------
 
-namespace {
-struct SearchBufs {
+// The search's device buffers: the node stack and the per-round lists, kept
+// on the net and grown on demand, so that repeated searches allocate nothing.
+struct SearchWork {
     uint64_t *stack = nullptr, *best = nullptr;
     int32_t *bvar = nullptr, *nchild = nullptr, *coff = nullptr, *has_best = nullptr;
     long long *stats = nullptr;
     int32_t *is_sol = nullptr, *is_open = nullptr, *sol_off = nullptr, *open_off = nullptr,
             *sol_list = nullptr;
     long long *h_stats = nullptr;   // pinned: a round's summary
-    int64_t cap = 0;   // stack capacity in nodes
-    ~SearchBufs() {
+    int64_t cap = 0;                // stack capacity in nodes
+    int32_t cap_batch = 0, cap_children = 0, cap_n = 0;
+    ~SearchWork() {
         if (h_stats) (void)hipHostFree(h_stats);
         dfree(stack);
         dfree(best);
@@ -1459,6 +1467,40 @@ struct SearchBufs {
     }
 };
 
+static void release_search(rac_net *net) {
+    delete net->search;
+    net->search = nullptr;
+}
+
+// Buffers for rounds of up to `batch` open nodes with up to `cmax` children
+// on a network of n variables, and a stack of at least `min_cap` nodes.
+static int ensure_search_work(rac_net *net, int32_t batch, int32_t cmax, int32_t n, int64_t min_cap) {
+    SearchWork *w = net->search;
+    if (w && w->cap_batch >= batch && w->cap_children >= cmax && w->cap_n == n && w->cap >= min_cap)
+        return RAC_OK;
+    release_search(net);
+    w = net->search = new SearchWork();
+    w->cap = min_cap;
+    RAC_TRY(dalloc(&w->stack, (size_t)(w->cap * n)));
+    RAC_TRY(dalloc(&w->best, (size_t)n));
+    RAC_TRY(dalloc(&w->bvar, (size_t)batch));
+    RAC_TRY(dalloc(&w->nchild, (size_t)batch));
+    RAC_TRY(dalloc(&w->coff, (size_t)batch + 1));
+    RAC_TRY(dalloc(&w->has_best, 1));
+    RAC_TRY(dalloc(&w->is_sol, (size_t)cmax));
+    RAC_TRY(dalloc(&w->is_open, (size_t)cmax));
+    RAC_TRY(dalloc(&w->sol_off, (size_t)cmax + 1));
+    RAC_TRY(dalloc(&w->open_off, (size_t)cmax + 1));
+    RAC_TRY(dalloc(&w->sol_list, (size_t)cmax));
+    RAC_TRY(dalloc(&w->stats, 8));
+    HIP_TRY(hipHostMalloc((void **)&w->h_stats, 8 * sizeof(long long), hipHostMallocDefault));
+    w->cap_batch = batch;
+    w->cap_children = cmax;
+    w->cap_n = n;
+    return RAC_OK;
+}
+
+namespace {
 bool all_singletons(const uint64_t *dom, int32_t n) {
     for (int32_t x = 0; x < n; ++x)
         if (__builtin_popcountll(dom[x]) != 1) return false;
@@ -1531,23 +1573,10 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
         return finish();
     }
 
-    // device buffers: the stack and the per-round lists
+    // device buffers: the stack and the per-round lists (kept on the net)
     const int32_t cmax = batch * d;
-    SearchBufs b;
-    b.cap = std::max<int64_t>(4 * (int64_t)cmax, 1024);
-    RAC_TRY(dalloc(&b.stack, (size_t)(b.cap * n)));
-    RAC_TRY(dalloc(&b.best, (size_t)n));
-    RAC_TRY(dalloc(&b.bvar, (size_t)batch));
-    RAC_TRY(dalloc(&b.nchild, (size_t)batch));
-    RAC_TRY(dalloc(&b.coff, (size_t)batch + 1));
-    RAC_TRY(dalloc(&b.has_best, 1));
-    RAC_TRY(dalloc(&b.is_sol, (size_t)cmax));
-    RAC_TRY(dalloc(&b.is_open, (size_t)cmax));
-    RAC_TRY(dalloc(&b.sol_off, (size_t)cmax + 1));
-    RAC_TRY(dalloc(&b.open_off, (size_t)cmax + 1));
-    RAC_TRY(dalloc(&b.sol_list, (size_t)cmax));
-    RAC_TRY(dalloc(&b.stats, 8));
-    HIP_TRY(hipHostMalloc((void **)&b.h_stats, 8 * sizeof(long long), hipHostMallocDefault));
+    RAC_TRY(ensure_search_work(net, batch, cmax, n, std::max<int64_t>(4 * (int64_t)cmax, 1024)));
+    SearchWork &b = *net->search;
     HIP_TRY(hipMemsetAsync(b.has_best, 0, 4, s));
     HIP_TRY(hipMemcpyAsync(b.stack, root.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
     RAC_TRY(ensure_path(net, path, call_target(net, cmax)));

@@ -180,12 +180,14 @@ def test_bench_search_workloads(which):
     net.close()
 
 
-@pytest.mark.parametrize("n,p1", [(100, 0.5), (100, 0.75), (100, 1.0)])
+@pytest.mark.parametrize("n,p1", [(100, 0.5), (100, 0.75), (100, 1.0), (250, 0.5), (500, 0.5),
+                                  (1000, 1.0)])
 def test_table1_cells_complete(n, p1):
     # Cells of the Table 1 grid (model-B stand-ins, d = 10, p2 = 0.3) whose
     # whole search tree the oracle explores in seconds: the GPU search's
     # recurrence steps per assignment (and nodes, failures, solutions) equal
-    # the oracle's, at the batch the grid is run with.
+    # the oracle's, at the batch the grid is run with (n = 100 and 250: the
+    # fused path's rounds; n = 500 and 1000: the bit-row path's).
     import bench
     inst = bench.table1_instance(n, p1)
     d = bench.TABLE1_D
