@@ -986,7 +986,8 @@ static int launch_fixpoint(Runner &r, int device, hipStream_t stream, const Laun
 // Outputs and read-back as launch_fixpoint.
 enum { kFusedWavesOne = 16, kFusedWavesBatch = 8, kFusedWavesSearch = 4 };
 static int launch_fused(Runner &r, hipStream_t stream, const Launch &L, int32_t max_n,
-                        int64_t max_groups, int max_waves, bool profile, int64_t rb_vars = -1) {
+                        int64_t max_groups, int max_waves, bool profile, int64_t rb_vars = -1,
+                        int32_t grid = 0) {
     if (max_n > kSmallMaxN)
         return set_error(RAC_EUNSUPPORTED, "the fused path holds at most %d variables per state",
                          kSmallMaxN);
@@ -994,7 +995,9 @@ static int launch_fused(Runner &r, hipStream_t stream, const Launch &L, int32_t 
     hipLaunchKernelGGL(clear_word_kernel, dim3(1), dim3(64), 0, stream, L.rc_out);
     if (profile) HIP_TRY(hipEventRecord(r.kev[0], stream));
     if (L.nprob > 0)
-        hipLaunchKernelGGL(small_fixpoint_kernel, dim3((unsigned)L.nprob), dim3(small_threads(max_groups, max_waves)),
+        hipLaunchKernelGGL(small_fixpoint_kernel,
+                           dim3((unsigned)(grid > 0 ? std::min<int32_t>(grid, L.nprob) : L.nprob)),
+                           dim3(small_threads(max_groups, max_waves)),
                            small_lds_bytes(max_n), stream, L);
     if (profile) HIP_TRY(hipEventRecord(r.kev[1], stream));
     HIP_TRY(hipGetLastError());
@@ -1133,7 +1136,8 @@ static int32_t stage_vars_for(int64_t max_n) {
 // Bit / int8 path for B states already in r.din (host waits between rounds).
 // item_bytes > 0 fixes the work-item size (else the default for B states).
 // d_count non-null: the first *d_count of the B states run (a device count,
-// see Launch::nprob_dev), which is at most count_bound (> 0) if given.
+// see Launch::nprob_dev); on the fused path count_bound (> 0) bounds the grid,
+// whose workgroups stride over those states.
 static int run_states(rac_net *net, int32_t B, int32_t path, const uint8_t *d_changed,
                       long long arcs1, bool allow_graph = true, bool readback = false,
                       int32_t item_bytes = 0, const int32_t *d_count = nullptr,
@@ -1154,14 +1158,11 @@ static int run_states(rac_net *net, int32_t B, int32_t path, const uint8_t *d_ch
     L.changed0 = d_changed;
     L.arcs1 = arcs1;
     L.nprob_dev = d_count;
-    if (fused) {
-        // no captured graph here: the grid needs only the states that can run
-        if (d_count && count_bound > 0 && count_bound < L.nprob) L.nprob = count_bound;
+    if (fused)   // the grid strides over the states that run (at most count_bound)
         return launch_fused(r, net->stream, L, net->n, net->groups,
                             d_count ? kFusedWavesSearch : B == 1 ? kFusedWavesOne : kFusedWavesBatch,
-                            net->opt.profile != 0,
-                            readback ? (int64_t)B * net->n : -1);
-    }
+                            net->opt.profile != 0, readback ? (int64_t)B * net->n : -1,
+                            d_count ? count_bound : 0);
     RAC_TRY(launch_fixpoint(r, net->device, net->stream, L, (int64_t)B * net->n,
                             (int64_t)pd.nitems * B, step_cap(net->opt, (int64_t)net->n * net->d),
                             allow_graph && net->opt.use_graph != 0, net->opt.profile != 0,
@@ -1439,6 +1440,10 @@ static int run_mfma(rac_net *net, int32_t B, const uint64_t *d_in, uint64_t *d_o
 // batched MAC search (Algorithm 2)
 // ---------------------------------------------------------------------------
 
+// Rounds the device-driven search enqueues between reads of its control block
+// (1, 2, 4, then this many).
+constexpr int32_t kSearchRoundsMax = 8;
+
 // The search's device buffers: the node stack and the per-round lists, kept
 // on the net and grown on demand, so that repeated searches allocate nothing.
 struct SearchWork {
@@ -1448,10 +1453,28 @@ struct SearchWork {
     int32_t *is_sol = nullptr, *is_open = nullptr, *sol_off = nullptr, *open_off = nullptr,
             *sol_list = nullptr;
     long long *h_stats = nullptr;   // pinned: a round's summary
+    SearchCtl *ctl = nullptr;       // the search's control block (device)
+    SearchCtl *h_ctl = nullptr;     // pinned mirror
     int64_t cap = 0;                // stack capacity in nodes
     int32_t cap_batch = 0, cap_children = 0, cap_n = 0;
+    // captured batches of 1, 2, 4 and 8 device-driven rounds, valid for `key`
+    hipGraph_t graph[4] = {};
+    hipGraphExec_t exec[4] = {};
+    std::vector<unsigned char> key;
+    void drop_graphs() {
+        for (int i = 0; i < 4; ++i) {
+            if (exec[i]) (void)hipGraphExecDestroy(exec[i]);
+            if (graph[i]) (void)hipGraphDestroy(graph[i]);
+            exec[i] = nullptr;
+            graph[i] = nullptr;
+        }
+        key.clear();
+    }
     ~SearchWork() {
+        drop_graphs();
         if (h_stats) (void)hipHostFree(h_stats);
+        if (h_ctl) (void)hipHostFree(h_ctl);
+        dfree(ctl);
         dfree(stack);
         dfree(best);
         dfree(bvar);
@@ -1494,9 +1517,65 @@ static int ensure_search_work(rac_net *net, int32_t batch, int32_t cmax, int32_t
     RAC_TRY(dalloc(&w->sol_list, (size_t)cmax));
     RAC_TRY(dalloc(&w->stats, 8));
     HIP_TRY(hipHostMalloc((void **)&w->h_stats, 8 * sizeof(long long), hipHostMallocDefault));
+    RAC_TRY(dalloc(&w->ctl, 1));
+    HIP_TRY(hipHostMalloc((void **)&w->h_ctl, sizeof(SearchCtl), hipHostMallocDefault));
     w->cap_batch = batch;
     w->cap_children = cmax;
     w->cap_n = n;
+    return RAC_OK;
+}
+
+// Everything the kernels of a device-driven round take as arguments.
+struct SearchRoundArgs {
+    Launch L;   // the fused enforcement of the round's children
+    uint64_t *stack;
+    int32_t batch, n, gnode, gc, gfused, threads;
+    size_t lds;
+    long long max_solutions, max_nodes;
+};
+
+// A graph of K device-driven rounds: begin, branch, offsets (which also
+// clears the enforcement's flag word), expand, the fused enforcement, classify,
+// lists, push, best, end (kernel arguments are copied into the nodes).
+static int build_search_graph(SearchWork &b, Runner &r, const SearchRoundArgs &a, int32_t K,
+                              hipGraph_t *graph, hipGraphExec_t *exec) {
+    HIP_TRY(hipGraphCreate(graph, 0));
+    hipGraphNode_t prev = nullptr;
+    SearchRoundArgs v = a;
+    SearchCtl *ctl = b.ctl;
+    int32_t *count = r.count, *rc = r.rc;
+    uint8_t *changed = r.changed;
+    uint64_t *din = r.din, *dout = r.dout;
+    int32_t *status = r.status, *iters = r.iters;
+    void *p_begin[4] = {&ctl, &v.batch, &v.max_solutions, &v.max_nodes};
+    void *p_branch[5] = {&v.stack, &ctl, &v.n, &b.bvar, &b.nchild};
+    void *p_off[5] = {&b.nchild, &ctl, &b.coff, &count, &rc};
+    void *p_expand[7] = {&v.stack, &ctl, &v.n, &b.bvar, &b.coff, &din, &changed};
+    void *p_fused[1] = {&v.L};
+    void *p_class[6] = {&dout, &status, &v.n, &count, &b.is_sol, &b.is_open};
+    void *p_lists[8] = {&b.is_sol, &b.is_open, &iters, &count, &rc, &b.sol_off, &b.open_off, &b.stats};
+    void *p_push[10] = {&dout, &v.n, &count, &b.is_sol, &b.is_open, &b.sol_off, &b.open_off,
+                        &v.stack, &ctl, &b.sol_list};
+    void *p_best[7] = {&dout, &v.n, &b.sol_list, &b.sol_off, &count, &b.best, &b.has_best};
+    void *p_end[2] = {&ctl, &b.stats};
+    for (int32_t i = 0; i < K; ++i) {
+        RAC_TRY(add_node(*graph, &prev, (const void *)search_begin_kernel, dim3(1), dim3(64), 0, p_begin));
+        RAC_TRY(add_node(*graph, &prev, (const void *)search_branch_kernel, dim3((unsigned)v.gnode),
+                         dim3(64), 0, p_branch));
+        RAC_TRY(add_node(*graph, &prev, (const void *)search_offsets_kernel, dim3(1), dim3(1024), 0, p_off));
+        RAC_TRY(add_node(*graph, &prev, (const void *)search_expand_kernel, dim3((unsigned)v.gnode),
+                         dim3(256), 0, p_expand));
+        RAC_TRY(add_node(*graph, &prev, (const void *)small_fixpoint_kernel, dim3((unsigned)v.gfused),
+                         dim3((unsigned)v.threads), v.lds, p_fused));
+        RAC_TRY(add_node(*graph, &prev, (const void *)search_classify_kernel, dim3((unsigned)v.gc),
+                         dim3(64), 0, p_class));
+        RAC_TRY(add_node(*graph, &prev, (const void *)search_lists_kernel, dim3(1), dim3(1024), 0, p_lists));
+        RAC_TRY(add_node(*graph, &prev, (const void *)search_push_kernel, dim3((unsigned)v.gc),
+                         dim3(256), 0, p_push));
+        RAC_TRY(add_node(*graph, &prev, (const void *)search_best_kernel, dim3(1), dim3(1024), 0, p_best));
+        RAC_TRY(add_node(*graph, &prev, (const void *)search_end_kernel, dim3(1), dim3(64), 0, p_end));
+    }
+    HIP_TRY(hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0));
     return RAC_OK;
 }
 
@@ -1573,12 +1652,27 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
         return finish();
     }
 
-    // device buffers: the stack and the per-round lists (kept on the net)
+    // device buffers: the stack and the per-round lists (kept on the net).
+    // On the fused path every round is one launch, so rounds follow each
+    // other on the device (the control block decides each round's nodes):
+    // the host enqueues 1, 2, 4, 8, 8, ... rounds and reads the control block
+    // once per batch of rounds. The bit-row path's enforcement waits on the
+    // host between its rounds of steps, so there the host reads it per round.
     const int32_t cmax = batch * d;
-    RAC_TRY(ensure_search_work(net, batch, cmax, n, std::max<int64_t>(4 * (int64_t)cmax, 1024)));
+    const bool device_rounds = fused;
+    const int64_t grow = (int64_t)kSearchRoundsMax * cmax;   // stack growth bound of a batch of rounds
+    RAC_TRY(ensure_search_work(net, batch, cmax, n, std::max<int64_t>(grow + cmax, 1024)));
     SearchWork &b = *net->search;
     HIP_TRY(hipMemsetAsync(b.has_best, 0, 4, s));
     HIP_TRY(hipMemcpyAsync(b.stack, root.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+    {
+        SearchCtl &c0 = *b.h_ctl;
+        memset(&c0, 0, sizeof(c0));
+        c0.ssize = 1;
+        c0.nodes = 1;   // the root
+        c0.sweeps = root_iters;
+        HIP_TRY(hipMemcpyAsync(b.ctl, &c0, sizeof(SearchCtl), hipMemcpyHostToDevice, s));
+    }
     RAC_TRY(ensure_path(net, path, call_target(net, cmax)));
     // one work-item size for every round (the one for cmax states), so that
     // rounds of different sizes reuse the item table
@@ -1586,21 +1680,20 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
     // problem tables for cmax states once: a round with C <= cmax children uses
     // their prefix (problem s at s*n)
     RAC_TRY(prepare_net_runner(net, cmax, pd));
-    int64_t ssize = 1;
-    while (true) {
-        if (ssize == 0) {
-            out->complete = 1;
-            break;
-        }
-        if (max_solutions > 0 && out->solutions >= max_solutions) break;
-        if (max_nodes > 0 && out->nodes >= max_nodes) break;
-        const int32_t P = (int32_t)std::min<int64_t>(ssize, batch);
-        const int64_t base = ssize - P;   // the top P nodes
-        // at most P*d children, so at most that many open ones go back above
-        // base: grow the stack first (device copy of the live part)
-        const int32_t cbound = P * d;
-        if (base + cbound > b.cap) {
-            const int64_t ncap = std::max<int64_t>(2 * b.cap, base + cbound);
+    // workgroups of the per-node and per-child kernels on the device-driven
+    // path (they stride over the nodes and children; 4096 fused workgroups
+    // of 4 waves measured best: 2048 leave CUs idle, one per child launches
+    // tens of thousands that mostly return)
+    const int32_t gchild = std::min<int32_t>(cmax, 4096);
+    const int32_t gnodes = std::min<int32_t>(batch, 1024);
+    int64_t ssize = 1;   // stack size after the last read of the control block
+    for (int32_t batch_i = 0;; ++batch_i) {
+        const int32_t K = device_rounds ? std::min(1 << std::min(batch_i, 3), kSearchRoundsMax) : 1;
+        static_assert(kSearchRoundsMax == 8, "graphs of 1, 2, 4 and 8 rounds");
+        // every round pops before it pushes, and pushes at most P * d nodes
+        // above its base: grow the stack first (device copy of the live part)
+        if (ssize + (int64_t)K * cmax > b.cap) {
+            const int64_t ncap = std::max<int64_t>(2 * b.cap, ssize + (int64_t)K * cmax);
             uint64_t *ns = nullptr;
             RAC_TRY(dalloc(&ns, (size_t)(ncap * n)));
             HIP_TRY(hipMemcpyAsync(ns, b.stack, (size_t)(ssize * n) * 8, hipMemcpyDeviceToDevice, s));
@@ -1609,43 +1702,92 @@ extern "C" int rac_search(rac_net *net, const uint64_t *dom, int64_t max_solutio
             b.stack = ns;
             b.cap = ncap;
         }
-        const uint64_t *top = b.stack + base * n;
-        // the child count C stays on the device (r.count): the kernels below
-        // read it, and the host learns it with the round's summary
-        hipLaunchKernelGGL(search_branch_kernel, dim3((unsigned)P), dim3(64), 0, s, top, n, b.bvar,
-                           b.nchild);
-        hipLaunchKernelGGL(search_offsets_kernel, dim3(1), dim3(1024), 0, s, b.nchild, P, b.coff,
-                           r.count);
-        hipLaunchKernelGGL(search_expand_kernel, dim3((unsigned)P), dim3(256), 0, s, top, n, b.bvar,
-                           b.coff, r.din, r.changed);
-        HIP_TRY(hipGetLastError());
-        ssize = base;
-        // launched for cmax states with the count on the device: the same
-        // arguments every round, so the captured step graphs are reused
-        RAC_TRY(run_states(net, cmax, run_path, r.changed, -1, true, false, item_bytes, r.count,
-                           cbound));
-        hipLaunchKernelGGL(search_classify_kernel, dim3((unsigned)cbound), dim3(64), 0, s, r.dout,
-                           r.status, n, r.count, b.is_sol, b.is_open);
-        hipLaunchKernelGGL(search_lists_kernel, dim3(1), dim3(1024), 0, s, b.is_sol, b.is_open,
-                           r.iters, r.count, r.rc, b.sol_off, b.open_off, b.stats);
-        hipLaunchKernelGGL(search_push_kernel, dim3((unsigned)cbound), dim3(256), 0, s, r.dout, n,
-                           r.count, b.is_sol, b.is_open, b.sol_off, b.open_off, b.stack, ssize,
-                           b.sol_list);
-        hipLaunchKernelGGL(search_best_kernel, dim3(1), dim3(1024), 0, s, r.dout, n, b.sol_list,
-                           b.sol_off, r.count, b.best, b.has_best);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(b.h_stats, b.stats, 5 * sizeof(long long), hipMemcpyDeviceToHost, s));
+        // the host knows P on the round-by-round path: exact grids there
+        const int32_t P = (int32_t)std::min<int64_t>(ssize, batch);
+        const int32_t gnode = device_rounds ? gnodes : std::max(P, 1);
+        const int32_t gc = device_rounds ? gchild : std::max(P * d, 1);
+        if (device_rounds && net->opt.use_graph != 0 && !net->opt.profile) {
+            // K rounds as one captured graph (built once per network and shape)
+            SearchRoundArgs a;
+            memset(&a, 0, sizeof(a));
+            a.L = base_launch(r, cmax, net->opt);
+            a.L.nets = pd.d_desc;
+            a.L.uniform_n = n;
+            a.L.din = r.din;
+            a.L.dout = r.dout;
+            a.L.iters_out = r.iters;
+            a.L.status_out = r.status;
+            a.L.changed0 = r.changed;
+            a.L.arcs1 = -1;
+            a.L.nprob_dev = r.count;
+            a.stack = b.stack;
+            a.batch = batch;
+            a.n = n;
+            a.gnode = gnodes;
+            a.gc = gchild;
+            a.gfused = gchild;
+            a.threads = small_threads(net->groups, kFusedWavesSearch);
+            a.lds = small_lds_bytes(n);
+            a.max_solutions = max_solutions;
+            a.max_nodes = max_nodes;
+            std::vector<unsigned char> key(sizeof(a));
+            memcpy(key.data(), &a, sizeof(a));
+            if (key != b.key) {
+                b.drop_graphs();
+                b.key = key;
+            }
+            const int gi = K >= 8 ? 3 : K >= 4 ? 2 : K >= 2 ? 1 : 0;
+            if (!b.exec[gi]) RAC_TRY(build_search_graph(b, r, a, 1 << gi, &b.graph[gi], &b.exec[gi]));
+            HIP_TRY(hipGraphLaunch(b.exec[gi], s));
+        } else
+        for (int32_t i = 0; i < K; ++i) {
+            hipLaunchKernelGGL(search_begin_kernel, dim3(1), dim3(64), 0, s, b.ctl, batch,
+                               (long long)max_solutions, (long long)max_nodes);
+            hipLaunchKernelGGL(search_branch_kernel, dim3((unsigned)gnode), dim3(64), 0, s, b.stack,
+                               b.ctl, n, b.bvar, b.nchild);
+            // the child count C stays on the device (r.count): the kernels
+            // below read it, and the host learns it with the round's summary
+            hipLaunchKernelGGL(search_offsets_kernel, dim3(1), dim3(1024), 0, s, b.nchild, b.ctl,
+                               b.coff, r.count, r.rc);
+            hipLaunchKernelGGL(search_expand_kernel, dim3((unsigned)gnode), dim3(256), 0, s,
+                               b.stack, b.ctl, n, b.bvar, b.coff, r.din, r.changed);
+            HIP_TRY(hipGetLastError());
+            // launched for cmax states with the count on the device: the same
+            // arguments every round, so the captured step graphs are reused
+            RAC_TRY(run_states(net, cmax, run_path, r.changed, -1, true, false, item_bytes, r.count,
+                               gc));
+            hipLaunchKernelGGL(search_classify_kernel, dim3((unsigned)gc), dim3(64), 0, s, r.dout,
+                               r.status, n, r.count, b.is_sol, b.is_open);
+            hipLaunchKernelGGL(search_lists_kernel, dim3(1), dim3(1024), 0, s, b.is_sol, b.is_open,
+                               r.iters, r.count, r.rc, b.sol_off, b.open_off, b.stats);
+            hipLaunchKernelGGL(search_push_kernel, dim3((unsigned)gc), dim3(256), 0, s, r.dout, n,
+                               r.count, b.is_sol, b.is_open, b.sol_off, b.open_off, b.stack, b.ctl,
+                               b.sol_list);
+            hipLaunchKernelGGL(search_best_kernel, dim3(1), dim3(1024), 0, s, r.dout, n,
+                               b.sol_list, b.sol_off, r.count, b.best, b.has_best);
+            hipLaunchKernelGGL(search_end_kernel, dim3(1), dim3(64), 0, s, b.ctl, b.stats);
+            HIP_TRY(hipGetLastError());
+        }
+        HIP_TRY(hipMemcpyAsync(b.h_ctl, b.ctl, sizeof(SearchCtl), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        RAC_TRY(rc_from_device((int32_t)b.h_stats[3]));
-        const long long steps = b.h_stats[0];
-        const int32_t nsol = (int32_t)b.h_stats[1], nopen = (int32_t)b.h_stats[2];
-        const int32_t C = (int32_t)b.h_stats[4];
-        out->nodes += C;
-        out->sweeps += steps;
-        out->solutions += nsol;
-        out->failures += C - nsol - nopen;
-        ssize += nopen;
-        out->rounds += 1;
+        const SearchCtl &c = *b.h_ctl;
+        ssize = c.ssize;
+        out->nodes = c.nodes;
+        out->sweeps = c.sweeps;
+        out->solutions = c.solutions;
+        out->failures = c.failures;
+        out->rounds = c.rounds;
+        out->complete = c.complete;
+        RAC_TRY(rc_from_device(c.rc));
+        if (c.done) break;
+        // what the next round's begin kernel would find, without launching it
+        if (ssize == 0) {
+            out->complete = 1;
+            break;
+        }
+        if ((max_solutions > 0 && out->solutions >= max_solutions) ||
+            (max_nodes > 0 && out->nodes >= max_nodes))
+            break;
     }
     int32_t has = 0;
     HIP_TRY(hipMemcpyAsync(&has, b.has_best, 4, hipMemcpyDeviceToHost, s));

@@ -162,13 +162,27 @@ __global__ void pack_bits_kernel(const uint64_t *rel, const int32_t *src_p, int6
 __global__ void pack_i8_kernel(const uint64_t *rel, const int32_t *arc_src, int64_t arcs,
                                int32_t d, int32_t rows_per_arc, int32_t dp, int8_t *out);
 
-// Batched MAC search (search.hip).
-__global__ void search_branch_kernel(const uint64_t *nodes, int32_t n, int32_t *bvar,
-                                     int32_t *nchild);
-__global__ void search_offsets_kernel(const int32_t *nchild, int32_t P, int32_t *coff,
-                                      int32_t *total);
-__global__ void search_expand_kernel(const uint64_t *nodes, int32_t n, const int32_t *bvar,
-                                     const int32_t *coff, uint64_t *cdom, uint8_t *cchg);
+// Batched MAC search (search.hip). The control block of a search on the
+// device: the stack size and the current round's nodes, and the counts so far.
+struct SearchCtl {
+    long long ssize;      // nodes on the stack
+    long long base;       // stack index of the round's first node (ssize - P)
+    long long nodes, solutions, failures, sweeps, rounds;
+    int32_t P;            // nodes of the current round (0: none)
+    int32_t done;         // 1: the search has ended (stack empty, limit reached, or rc)
+    int32_t complete;     // 1: the stack emptied (the whole tree was explored)
+    int32_t rc;           // OR of the enforcements' return flags (1: step cap reached)
+};
+__global__ void search_begin_kernel(SearchCtl *ctl, int32_t batch, long long max_solutions,
+                                    long long max_nodes);
+__global__ void search_end_kernel(SearchCtl *ctl, const long long *stats);
+__global__ void search_branch_kernel(const uint64_t *stack, const SearchCtl *ctl, int32_t n,
+                                     int32_t *bvar, int32_t *nchild);
+__global__ void search_offsets_kernel(const int32_t *nchild, const SearchCtl *ctl, int32_t *coff,
+                                      int32_t *total, int32_t *rc);
+__global__ void search_expand_kernel(const uint64_t *stack, const SearchCtl *ctl, int32_t n,
+                                     const int32_t *bvar, const int32_t *coff, uint64_t *cdom,
+                                     uint8_t *cchg);
 __global__ void search_classify_kernel(const uint64_t *cres, const int32_t *status, int32_t n,
                                        const int32_t *count, int32_t *is_sol, int32_t *is_open);
 __global__ void search_lists_kernel(const int32_t *is_sol, const int32_t *is_open,
@@ -177,7 +191,7 @@ __global__ void search_lists_kernel(const int32_t *is_sol, const int32_t *is_ope
 __global__ void search_push_kernel(const uint64_t *cres, int32_t n, const int32_t *count,
                                    const int32_t *is_sol, const int32_t *is_open,
                                    const int32_t *sol_off, const int32_t *open_off, uint64_t *stack,
-                                   int64_t base, int32_t *sol_list);
+                                   const SearchCtl *ctl, int32_t *sol_list);
 __global__ void search_best_kernel(const uint64_t *cres, int32_t n, const int32_t *sol_list,
                                    const int32_t *sol_off, const int32_t *count, uint64_t *best,
                                    int32_t *has_best);

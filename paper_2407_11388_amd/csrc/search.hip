@@ -1,9 +1,12 @@
 // Kernels of the batched MAC search (Algorithm 2: depth-first search that
 // enforces arc consistency after every assignment). A round takes the top P
 // nodes of the device stack, branches each on one variable, enforces all
-// children together (the bit-row step kernels, @changed = the assigned
-// variable, Proposition 2), and sorts the children into failures, solutions
-// and nodes pushed back onto the stack.
+// children together (@changed = the assigned variable, Proposition 2), and
+// sorts the children into failures, solutions and nodes pushed back onto the
+// stack. The round's sizes live in a device control block (SearchCtl): the
+// begin kernel sets P and the base of the popped nodes from the stack size,
+// the end kernel adds the round's counts and sets the new stack size, so that
+// rounds can follow each other with no host read in between.
 #include "rac.h"
 #include "rac_internal.h"
 
@@ -49,31 +52,78 @@ __device__ void block_scan(const int32_t *cnt, int32_t N, int32_t *off) {
 
 }  // namespace
 
+// Start of a round: the search ends when the stack is empty (complete) or a
+// limit is reached (checked before each round, as the round in progress
+// completes); else the round takes the top min(stack, batch) nodes.
+__global__ void search_begin_kernel(SearchCtl *ctl, int32_t batch, long long max_solutions,
+                                    long long max_nodes) {
+    if (threadIdx.x != 0) return;
+    SearchCtl &c = *ctl;
+    c.P = 0;
+    if (c.done) return;
+    if (c.ssize == 0) {
+        c.done = 1;
+        c.complete = 1;
+        return;
+    }
+    if ((max_solutions > 0 && c.solutions >= max_solutions) || (max_nodes > 0 && c.nodes >= max_nodes)) {
+        c.done = 1;
+        return;
+    }
+    c.P = (int32_t)(c.ssize < batch ? c.ssize : batch);
+    c.base = c.ssize - c.P;
+}
+
+// End of a round: the counts of its C children (stats from
+// search_lists_kernel) and the new stack size; an enforcement that reports
+// the step cap ends the search.
+__global__ void search_end_kernel(SearchCtl *ctl, const long long *stats) {
+    if (threadIdx.x != 0) return;
+    SearchCtl &c = *ctl;
+    if (c.P == 0) return;
+    const long long C = stats[4];
+    c.nodes += C;
+    c.sweeps += stats[0];
+    c.solutions += stats[1];
+    c.failures += C - stats[1] - stats[2];
+    c.ssize = c.base + stats[2];
+    c.rounds += 1;
+    c.rc |= (int32_t)stats[3];
+    if (c.rc) c.done = 1;
+}
+
 // Branching choice of node i (one wave per node): the variable with the
 // smallest domain of size > 1 (lowest index on ties), and its domain size
 // (the node's number of children). Nodes on the stack are arc consistent,
 // not wiped out and not yet solutions, so such a variable exists.
-__global__ __launch_bounds__(64) void search_branch_kernel(const uint64_t *nodes, int32_t n,
+__global__ __launch_bounds__(64) void search_branch_kernel(const uint64_t *stack,
+                                                           const SearchCtl *ctl, int32_t n,
                                                            int32_t *bvar, int32_t *nchild) {
-    const int32_t i = blockIdx.x;
+    const int32_t P = ctl->P;
     const int lane = threadIdx.x;
-    const uint64_t *dom = nodes + (int64_t)i * n;
-    int best = 0x7FFFFFFF;   // (size << 20) | variable, sizes <= 64, n < 2^20
-    for (int32_t x = lane; x < n; x += 64) {
-        const int s = __popcll(dom[x]);
-        if (s > 1) best = min(best, (s << 20) | x);
-    }
-    best = wave_min_int(best);
-    if (lane == 0) {
-        bvar[i] = best & 0xFFFFF;
-        nchild[i] = best >> 20;
+    for (int32_t i = blockIdx.x; i < P; i += gridDim.x) {
+        const uint64_t *dom = stack + (ctl->base + i) * n;
+        int best = 0x7FFFFFFF;   // (size << 20) | variable, sizes <= 64, n < 2^20
+        for (int32_t x = lane; x < n; x += 64) {
+            const int s = __popcll(dom[x]);
+            if (s > 1) best = min(best, (s << 20) | x);
+        }
+        best = wave_min_int(best);
+        if (lane == 0) {
+            bvar[i] = best & 0xFFFFF;
+            nchild[i] = best >> 20;
+        }
     }
 }
 
 // Child offsets: coff[i] = children of nodes 0..i-1, coff[P] = all children,
-// also stored in *total (the problem count of the round's enforcement).
-__global__ __launch_bounds__(1024) void search_offsets_kernel(const int32_t *nchild, int32_t P,
-                                                              int32_t *coff, int32_t *total) {
+// also stored in *total (the problem count of the round's enforcement); the
+// enforcement's step-cap flag starts clear.
+__global__ __launch_bounds__(1024) void search_offsets_kernel(const int32_t *nchild,
+                                                              const SearchCtl *ctl, int32_t *coff,
+                                                              int32_t *total, int32_t *rc) {
+    const int32_t P = ctl->P;
+    if (threadIdx.x == 0) *rc = 0;   // the round's enforcement ORs its step-cap flag here
     block_scan(nchild, P, coff);
     // thread 0 wrote coff[P] itself
     if (threadIdx.x == 0) *total = coff[P];
@@ -81,23 +131,26 @@ __global__ __launch_bounds__(1024) void search_offsets_kernel(const int32_t *nch
 
 // Children of node i (one workgroup per node): child j takes the j-th value
 // of the branching variable (ascending); its @changed set is that variable.
-__global__ __launch_bounds__(256) void search_expand_kernel(const uint64_t *nodes, int32_t n,
+__global__ __launch_bounds__(256) void search_expand_kernel(const uint64_t *stack,
+                                                            const SearchCtl *ctl, int32_t n,
                                                             const int32_t *bvar,
                                                             const int32_t *coff, uint64_t *cdom,
                                                             uint8_t *cchg) {
-    const int32_t i = blockIdx.x;
-    const int32_t xb = bvar[i];
-    const uint64_t *dom = nodes + (int64_t)i * n;
-    const int32_t c0 = coff[i], c1 = coff[i + 1];
-    uint64_t rest = dom[xb];
-    for (int32_t c = c0; c < c1; ++c) {
-        const uint64_t v = rest & (~rest + 1ull);   // lowest remaining value
-        rest &= rest - 1ull;
-        uint64_t *out = cdom + (int64_t)c * n;
-        uint8_t *chg = cchg + (int64_t)c * n;
-        for (int32_t x = threadIdx.x; x < n; x += blockDim.x) {
-            out[x] = x == xb ? v : dom[x];
-            chg[x] = x == xb ? 1 : 0;
+    const int32_t P = ctl->P;
+    for (int32_t i = blockIdx.x; i < P; i += gridDim.x) {
+        const int32_t xb = bvar[i];
+        const uint64_t *dom = stack + (ctl->base + i) * n;
+        const int32_t c0 = coff[i], c1 = coff[i + 1];
+        uint64_t rest = dom[xb];
+        for (int32_t c = c0; c < c1; ++c) {
+            const uint64_t v = rest & (~rest + 1ull);   // lowest remaining value
+            rest &= rest - 1ull;
+            uint64_t *out = cdom + (int64_t)c * n;
+            uint8_t *chg = cchg + (int64_t)c * n;
+            for (int32_t x = threadIdx.x; x < n; x += blockDim.x) {
+                out[x] = x == xb ? v : dom[x];
+                chg[x] = x == xb ? 1 : 0;
+            }
         }
     }
 }
@@ -105,22 +158,23 @@ __global__ __launch_bounds__(256) void search_expand_kernel(const uint64_t *node
 // Kind of each enforced child, as 0/1 flags for the list scans that follow:
 // a solution (not wiped out, every domain a singleton) or open (not wiped
 // out, some domain larger); neither means a failure. One wave per child,
-// *count children (the grid may be larger).
+// *count children (the workgroups stride over them).
 __global__ __launch_bounds__(64) void search_classify_kernel(const uint64_t *cres,
                                                              const int32_t *status, int32_t n,
                                                              const int32_t *count,
                                                              int32_t *is_sol, int32_t *is_open) {
-    const int32_t c = blockIdx.x;
-    if (c >= *count) return;
+    const int32_t C = *count;
     const int lane = threadIdx.x;
-    const uint64_t *dom = cres + (int64_t)c * n;
-    int multi = 0;
-    for (int32_t x = lane; x < n; x += 64) multi |= __popcll(dom[x]) > 1;
-    multi = __any(multi) ? 1 : 0;
-    if (lane == 0) {
-        const bool wiped = status[c] == RAC_WIPEOUT;
-        is_sol[c] = (!wiped && !multi) ? 1 : 0;
-        is_open[c] = (!wiped && multi) ? 1 : 0;
+    for (int32_t c = blockIdx.x; c < C; c += gridDim.x) {
+        const uint64_t *dom = cres + (int64_t)c * n;
+        int multi = 0;
+        for (int32_t x = lane; x < n; x += 64) multi |= __popcll(dom[x]) > 1;
+        multi = __any(multi) ? 1 : 0;
+        if (lane == 0) {
+            const bool wiped = status[c] == RAC_WIPEOUT;
+            is_sol[c] = (!wiped && !multi) ? 1 : 0;
+            is_open[c] = (!wiped && multi) ? 1 : 0;
+        }
     }
 }
 
@@ -156,27 +210,29 @@ __global__ __launch_bounds__(1024) void search_lists_kernel(const int32_t *is_so
     if (threadIdx.x == 0) stats[0] = s_steps;
 }
 
-// Open children go onto the stack above `base`, the last child lowest, so
-// that the first child (the smallest value of the first node) ends on top;
-// solutions are listed in child order. One workgroup per child, C = *count
-// children (the grid may be larger).
+// Open children go onto the stack above the round's base, the last child
+// lowest, so that the first child (the smallest value of the first node)
+// ends on top; solutions are listed in child order. One workgroup per child,
+// C = *count children (the workgroups stride over them).
 __global__ __launch_bounds__(256) void search_push_kernel(const uint64_t *cres, int32_t n,
                                                           const int32_t *count,
                                                           const int32_t *is_sol,
                                                           const int32_t *is_open,
                                                           const int32_t *sol_off,
                                                           const int32_t *open_off, uint64_t *stack,
-                                                          int64_t base, int32_t *sol_list) {
-    const int32_t c = blockIdx.x;
+                                                          const SearchCtl *ctl, int32_t *sol_list) {
     const int32_t C = *count;
-    if (c >= C) return;
-    if (is_sol[c] && threadIdx.x == 0) sol_list[sol_off[c]] = c;
-    if (!is_open[c]) return;
-    const int32_t nopen = open_off[C];
-    const int64_t at = base + (nopen - 1 - open_off[c]);
-    const uint64_t *src = cres + (int64_t)c * n;
-    uint64_t *dst = stack + at * n;
-    for (int32_t x = threadIdx.x; x < n; x += blockDim.x) dst[x] = src[x];
+    if (ctl->P == 0) return;
+    const long long base = ctl->base;
+    for (int32_t c = blockIdx.x; c < C; c += gridDim.x) {
+        if (is_sol[c] && threadIdx.x == 0) sol_list[sol_off[c]] = c;
+        if (!is_open[c]) continue;
+        const int32_t nopen = open_off[C];
+        const int64_t at = base + (nopen - 1 - open_off[c]);
+        const uint64_t *src = cres + (int64_t)c * n;
+        uint64_t *dst = stack + at * n;
+        for (int32_t x = threadIdx.x; x < n; x += blockDim.x) dst[x] = src[x];
+    }
 }
 
 namespace {

@@ -999,8 +999,10 @@ __global__ __launch_bounds__(kSmallMaxThreads) void small_fixpoint_kernel(Launch
     extern __shared__ uint64_t s_lds[];
     __shared__ int32_t s_any[2], s_wipe;
     __shared__ unsigned long long s_list[2];   // (list length << 32) + arcs of the listed variables
-    const int32_t p = blockIdx.x;
-    if (p >= problem_count(L)) return;
+    const int32_t nprob = problem_count(L);
+    // one problem at a time per workgroup (the grid may be smaller than the
+    // problem count: the search launches one grid for every round)
+    for (int32_t p = blockIdx.x; p < nprob; p += gridDim.x) {
     const NetDesc &N = net_of(L, p);
     const int32_t n = N.n;
     const int64_t off = L.uniform_n > 0 ? (int64_t)p * L.uniform_n : L.prob_off[p];
@@ -1114,6 +1116,8 @@ __global__ __launch_bounds__(kSmallMaxThreads) void small_fixpoint_kernel(Launch
         if (L.status_out) L.status_out[p] = wipe_step != 0 ? RAC_WIPEOUT : RAC_CONSISTENT;
         if (L.checks_out) L.checks_out[p] = arcs_total * N.d * N.d;
         if (rc && L.rc_out) atomicOr(L.rc_out, 1);
+    }
+    __syncthreads();   // the LDS is free for the next problem
     }
 }
 

@@ -26,9 +26,9 @@ def full_masks(n, d):
     return np.full(n, (1 << d) - 1 if d < 64 else 0xFFFFFFFFFFFFFFFF, dtype=np.uint64)
 
 
-def check(name, n, d, edges, rel, dom_masks, batches=(1, 5, 256), path=None):
+def check(name, n, d, edges, rel, dom_masks, batches=(1, 5, 256), path=None, **opts):
     exp = mac_search(n, d, edges, rel, masks_to_u8(dom_masks, d))
-    kw = {} if path is None else dict(path=path)
+    kw = dict(opts) if path is None else dict(path=path, **opts)
     net = rac.Net.from_u8(n, d, edges, rel, **kw)
     for b in batches:
         say(f"[gpu] search {name} n={n} d={d} batch={b}")
@@ -80,6 +80,38 @@ def test_random(n, d, p1, p2, seed):
 def test_int8_path():
     edges, rel = queens(6)
     check("queens6-int8", 6, 6, edges, rel, full_masks(6, 6), batches=(4,), path=rac.PATH_INT8)
+
+
+def test_fused_rounds_without_graphs():
+    # The device-driven rounds of the fused path enqueued kernel by kernel
+    # (use_graph=0) instead of as captured batches of rounds.
+    edges, rel = queens(7)
+    check("queens7-fused-direct", 7, 7, edges, rel, full_masks(7, 7), batches=(1, 5, 256),
+          path=rac.PATH_FUSED, use_graph=False)
+
+
+def test_search_limits_device_rounds():
+    # max_nodes / max_solutions are checked before each device-driven round:
+    # the search stops at the first round boundary past the limit, as on the
+    # round-by-round path.
+    edges, rel = queens(8)
+    for path in (rac.PATH_FUSED, rac.PATH_BITS):
+        net = rac.Net.from_u8(8, 8, edges, rel, path=path)
+        say(f"[gpu] search limits path={path}")
+        full, _ = net.search(full_masks(8, 8), batch=4)
+        res, _ = net.search(full_masks(8, 8), batch=4, max_nodes=50)
+        assert res.complete == 0 and 50 <= res.nodes < full.nodes
+        res2, sol = net.search(full_masks(8, 8), batch=4, max_solutions=3)
+        assert res2.complete == 0 and res2.solutions >= 3 and sol is not None
+        net.close()
+    # both paths stop at the same round
+    got = []
+    for path in (rac.PATH_FUSED, rac.PATH_BITS):
+        net = rac.Net.from_u8(8, 8, edges, rel, path=path)
+        r, _ = net.search(full_masks(8, 8), batch=4, max_nodes=50)
+        got.append((r.nodes, r.solutions, r.rounds, r.sweeps))
+        net.close()
+    assert got[0] == got[1]
 
 
 @pytest.mark.parametrize("which", ["queens7", "random-n25", "random-n16-d33"])
