@@ -803,13 +803,16 @@ static dim3 grid_init(int64_t nvars) {
 }
 
 // Steps per round of captured graphs: 4, 4, 8, 8, 16, 32, then 64 (one
-// problem: 2, 4, 8, 8, ...). Steps past the fixpoint still launch (and return
-// at once), so the early rounds stay short: most calls end within their first
-// 16 to 24 steps, and a single state that is already arc consistent or
-// nearly so (one or two steps) runs no empty step at all or only one.
+// problem: 3, 4, 8, 8, ...). Steps past the fixpoint still launch (and return
+// at once, about 7 µs a step), and each further round costs a host read
+// (about 40 µs of a call), so the early rounds stay short: most calls end
+// within their first 16 to 24 steps. For one problem, a first round of 3
+// steps measured best overall: single-mid (1 step) 83 µs per call against 91
+// with 4 and 68 with 2, calls of 3 steps 178 µs against 173 with 4 and 210
+// with 2.
 static int32_t round_steps(int round, bool single) {
     static const int32_t kSteps[6] = {4, 4, 8, 8, 16, 32};
-    if (round == 0 && single) return 2;
+    if (round == 0 && single) return 3;
     return round < 6 ? kSteps[round] : 64;
 }
 static int32_t round_first_step(int round, bool single) {
