@@ -1003,121 +1003,121 @@ __global__ __launch_bounds__(kSmallMaxThreads) void small_fixpoint_kernel(Launch
     // one problem at a time per workgroup (the grid may be smaller than the
     // problem count: the search launches one grid for every round)
     for (int32_t p = blockIdx.x; p < nprob; p += gridDim.x) {
-    const NetDesc &N = net_of(L, p);
-    const int32_t n = N.n;
-    const int64_t off = L.uniform_n > 0 ? (int64_t)p * L.uniform_n : L.prob_off[p];
-    uint64_t *dom0 = s_lds, *dom1 = s_lds + n;
-    unsigned long long *failx = reinterpret_cast<unsigned long long *>(s_lds + 2 * n);
-    uint32_t *cst0 = reinterpret_cast<uint32_t *>(s_lds + 3 * n), *cst1 = cst0 + n;
-    uint16_t *cl0 = reinterpret_cast<uint16_t *>(cst1 + n), *cl1 = cl0 + n;
-    uint8_t *chg0 = reinterpret_cast<uint8_t *>(cl1 + n), *chg1 = chg0 + n;
-    const GLOBAL int32_t *deg = as_global(N.deg);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
-    if (tid == 0) {
-        s_list[0] = 0;
-        s_wipe = 0;
-    }
-    __syncthreads();
-    for (int32_t x = tid; x < n; x += blockDim.x) {
-        dom0[x] = L.din[off + x];
-        const bool c = L.changed0 ? L.changed0[off + x] != 0 : true;
-        chg0[x] = c ? 1 : 0;
-        failx[x] = 0;
-        if (c && L.changed0) {   // the initial list (all variables: scanned, not listed)
-            const unsigned long long at = __hip_atomic_fetch_add(
-                &s_list[0], (1ull << 32) + (unsigned long long)deg[x], __ATOMIC_RELAXED,
-                __HIP_MEMORY_SCOPE_WORKGROUP);
-            cl0[at >> 32] = (uint16_t)x;
-            cst0[at >> 32] = (uint32_t)at;
-        }
-    }
-    __syncthreads();
-    int32_t ncl = (int32_t)(s_list[0] >> 32);
-    int64_t arcs_cur = L.changed0 ? (int64_t)(s_list[0] & 0xFFFFFFFFull) : N.arcs;
-    const int32_t maxs = max_steps(L, N);
-    long long arcs_total = 0;   // re-examined arcs over all steps
-    int32_t k = 0, last_change = 0, wipe_step = 0;
-    uint64_t *cur = dom0, *nxt = dom1;
-    uint8_t *cin = chg0, *cout = chg1;
-    while (k < maxs) {
-        ++k;
-        const int li = (k - 1) & 1, lo = k & 1;   // lists: read (step k-1's), written (step k's)
-        // revise: walk the changed variables' arcs when they are listed (every
-        // step but a first one that starts from all variables) and at most a
-        // quarter of the network's arcs; else scan the groups
-        const bool listed = k > 1 || L.changed0 != nullptr;
-        if (N.rpos && listed && arcs_cur * kSmallWalkRatio <= N.arcs) {
-            const uint16_t *cl = li ? cl1 : cl0;
-            const uint32_t *cs = li ? cst1 : cst0;
-            if (N.kind == ROW64)
-                small_walk<true>(N, cur, cl, cs, ncl, arcs_cur, failx, wave, nwaves, lane);
-            else
-                small_walk<false>(N, cur, cl, cs, ncl, arcs_cur, failx, wave, nwaves, lane);
-        } else {
-            if (N.kind == ROW64)
-                small_scan<true>(N, cur, cin, failx, wave, nwaves, lane);
-            else
-                small_scan<false>(N, cur, cin, failx, wave, nwaves, lane);
-        }
-        arcs_total += arcs_cur;
+        const NetDesc &N = net_of(L, p);
+        const int32_t n = N.n;
+        const int64_t off = L.uniform_n > 0 ? (int64_t)p * L.uniform_n : L.prob_off[p];
+        uint64_t *dom0 = s_lds, *dom1 = s_lds + n;
+        unsigned long long *failx = reinterpret_cast<unsigned long long *>(s_lds + 2 * n);
+        uint32_t *cst0 = reinterpret_cast<uint32_t *>(s_lds + 3 * n), *cst1 = cst0 + n;
+        uint16_t *cl0 = reinterpret_cast<uint16_t *>(cst1 + n), *cl1 = cl0 + n;
+        uint8_t *chg0 = reinterpret_cast<uint8_t *>(cl1 + n), *chg1 = chg0 + n;
+        const GLOBAL int32_t *deg = as_global(N.deg);
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
         if (tid == 0) {
-            s_any[lo] = 0;
-            s_list[lo] = 0;
+            s_list[0] = 0;
+            s_wipe = 0;
         }
-        __syncthreads();   // every failure of step k recorded
-        uint16_t *clo = lo ? cl1 : cl0;
-        uint32_t *cso = lo ? cst1 : cst0;
-        int any = 0, wiped = 0;
+        __syncthreads();
         for (int32_t x = tid; x < n; x += blockDim.x) {
-            const uint64_t o = cur[x], nd = o & ~failx[x] & dmask_of(N.d);
-            nxt[x] = nd;
-            const bool c = nd != o;
-            cout[x] = c ? 1 : 0;
+            dom0[x] = L.din[off + x];
+            const bool c = L.changed0 ? L.changed0[off + x] != 0 : true;
+            chg0[x] = c ? 1 : 0;
             failx[x] = 0;
-            any |= c;
-            wiped |= nd == 0;
-            if (c) {
+            if (c && L.changed0) {   // the initial list (all variables: scanned, not listed)
                 const unsigned long long at = __hip_atomic_fetch_add(
-                    &s_list[lo], (1ull << 32) + (unsigned long long)deg[x], __ATOMIC_RELAXED,
+                    &s_list[0], (1ull << 32) + (unsigned long long)deg[x], __ATOMIC_RELAXED,
                     __HIP_MEMORY_SCOPE_WORKGROUP);
-                clo[at >> 32] = (uint16_t)x;
-                cso[at >> 32] = (uint32_t)at;
+                cl0[at >> 32] = (uint16_t)x;
+                cst0[at >> 32] = (uint32_t)at;
             }
         }
-        if (__ballot(any) && lane == 0) atomicOr(&s_any[lo], 1);
-        if (__ballot(wiped) && lane == 0) atomicOr(&s_wipe, 1);
-        __syncthreads();   // the step's change and wipe-out words and its list
-        const bool changed = s_any[lo] != 0;
-        ncl = (int32_t)(s_list[lo] >> 32);
-        arcs_cur = (int64_t)(s_list[lo] & 0xFFFFFFFFull);
-        if (changed) last_change = k;
-        if (s_wipe && wipe_step == 0) wipe_step = k;
-        uint64_t *t64 = cur;
-        cur = nxt;
-        nxt = t64;
-        uint8_t *t8 = cin;
-        cin = cout;
-        cout = t8;
-        if (!changed) break;
-        if (L.mode == RAC_STOP_ON_WIPEOUT && wipe_step != 0) break;
-    }
-    int32_t iters, rc = 0;
-    if (L.mode == RAC_STOP_ON_WIPEOUT && wipe_step != 0) {
-        iters = wipe_step;
-    } else if (last_change < maxs) {
-        iters = last_change + 1;
-    } else {
-        iters = maxs;
-        rc = 1;
-    }
-    for (int32_t x = tid; x < n; x += blockDim.x) L.dout[off + x] = cur[x];
-    if (tid == 0) {
-        if (L.iters_out) L.iters_out[p] = iters;
-        if (L.status_out) L.status_out[p] = wipe_step != 0 ? RAC_WIPEOUT : RAC_CONSISTENT;
-        if (L.checks_out) L.checks_out[p] = arcs_total * N.d * N.d;
-        if (rc && L.rc_out) atomicOr(L.rc_out, 1);
-    }
-    __syncthreads();   // the LDS is free for the next problem
+        __syncthreads();
+        int32_t ncl = (int32_t)(s_list[0] >> 32);
+        int64_t arcs_cur = L.changed0 ? (int64_t)(s_list[0] & 0xFFFFFFFFull) : N.arcs;
+        const int32_t maxs = max_steps(L, N);
+        long long arcs_total = 0;   // re-examined arcs over all steps
+        int32_t k = 0, last_change = 0, wipe_step = 0;
+        uint64_t *cur = dom0, *nxt = dom1;
+        uint8_t *cin = chg0, *cout = chg1;
+        while (k < maxs) {
+            ++k;
+            const int li = (k - 1) & 1, lo = k & 1;   // lists: read (step k-1's), written (step k's)
+            // revise: walk the changed variables' arcs when they are listed (every
+            // step but a first one that starts from all variables) and at most a
+            // quarter of the network's arcs; else scan the groups
+            const bool listed = k > 1 || L.changed0 != nullptr;
+            if (N.rpos && listed && arcs_cur * kSmallWalkRatio <= N.arcs) {
+                const uint16_t *cl = li ? cl1 : cl0;
+                const uint32_t *cs = li ? cst1 : cst0;
+                if (N.kind == ROW64)
+                    small_walk<true>(N, cur, cl, cs, ncl, arcs_cur, failx, wave, nwaves, lane);
+                else
+                    small_walk<false>(N, cur, cl, cs, ncl, arcs_cur, failx, wave, nwaves, lane);
+            } else {
+                if (N.kind == ROW64)
+                    small_scan<true>(N, cur, cin, failx, wave, nwaves, lane);
+                else
+                    small_scan<false>(N, cur, cin, failx, wave, nwaves, lane);
+            }
+            arcs_total += arcs_cur;
+            if (tid == 0) {
+                s_any[lo] = 0;
+                s_list[lo] = 0;
+            }
+            __syncthreads();   // every failure of step k recorded
+            uint16_t *clo = lo ? cl1 : cl0;
+            uint32_t *cso = lo ? cst1 : cst0;
+            int any = 0, wiped = 0;
+            for (int32_t x = tid; x < n; x += blockDim.x) {
+                const uint64_t o = cur[x], nd = o & ~failx[x] & dmask_of(N.d);
+                nxt[x] = nd;
+                const bool c = nd != o;
+                cout[x] = c ? 1 : 0;
+                failx[x] = 0;
+                any |= c;
+                wiped |= nd == 0;
+                if (c) {
+                    const unsigned long long at = __hip_atomic_fetch_add(
+                        &s_list[lo], (1ull << 32) + (unsigned long long)deg[x], __ATOMIC_RELAXED,
+                        __HIP_MEMORY_SCOPE_WORKGROUP);
+                    clo[at >> 32] = (uint16_t)x;
+                    cso[at >> 32] = (uint32_t)at;
+                }
+            }
+            if (__ballot(any) && lane == 0) atomicOr(&s_any[lo], 1);
+            if (__ballot(wiped) && lane == 0) atomicOr(&s_wipe, 1);
+            __syncthreads();   // the step's change and wipe-out words and its list
+            const bool changed = s_any[lo] != 0;
+            ncl = (int32_t)(s_list[lo] >> 32);
+            arcs_cur = (int64_t)(s_list[lo] & 0xFFFFFFFFull);
+            if (changed) last_change = k;
+            if (s_wipe && wipe_step == 0) wipe_step = k;
+            uint64_t *t64 = cur;
+            cur = nxt;
+            nxt = t64;
+            uint8_t *t8 = cin;
+            cin = cout;
+            cout = t8;
+            if (!changed) break;
+            if (L.mode == RAC_STOP_ON_WIPEOUT && wipe_step != 0) break;
+        }
+        int32_t iters, rc = 0;
+        if (L.mode == RAC_STOP_ON_WIPEOUT && wipe_step != 0) {
+            iters = wipe_step;
+        } else if (last_change < maxs) {
+            iters = last_change + 1;
+        } else {
+            iters = maxs;
+            rc = 1;
+        }
+        for (int32_t x = tid; x < n; x += blockDim.x) L.dout[off + x] = cur[x];
+        if (tid == 0) {
+            if (L.iters_out) L.iters_out[p] = iters;
+            if (L.status_out) L.status_out[p] = wipe_step != 0 ? RAC_WIPEOUT : RAC_CONSISTENT;
+            if (L.checks_out) L.checks_out[p] = arcs_total * N.d * N.d;
+            if (rc && L.rc_out) atomicOr(L.rc_out, 1);
+        }
+        __syncthreads();   // the LDS is free for the next problem
     }
 }
 
