@@ -259,7 +259,12 @@ void rac_group_destroy(rac_group *g);
  *     smallest solution found (value of variable 0 first), if any.
  * With no limit hit (out->complete = 1) the explored tree, the counts and the
  * returned solution do not depend on `batch`. Domains and relations as for
- * rac_enforce; uses the net's bit-row path (int8 if that is the net's path).
+ * rac_enforce. The children are enforced on the fused path (RAC_PATH_FUSED,
+ * or RAC_PATH_AUTO when a state's bit rows take at most 2 MiB), where the
+ * rounds run from the device and the host reads their counts once per batch
+ * of up to 8 rounds; else on the net's bit-row path (int8 if that is the
+ * net's path), one host read per round. Limits are checked before each round
+ * either way.
  */
 typedef struct rac_search_result {
     int64_t solutions;   /* solutions found */
