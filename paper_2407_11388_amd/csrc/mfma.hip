@@ -432,8 +432,13 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
                         const v16i d0 = mfma8(Aop[u0], ldsb(o0 + t * 512), bias);
                         const v16i d1 = mfma8(Aop[u1], ldsb(o1 + t * 512), bias);
 #pragma unroll
-                        for (int v = 0; v < 16; ++v)   // two v_and_or each
-                            rf[t][v] = (d1[v] & lmask) | ((d0[v] & m0) | rf[t][v]);
+                        for (int v = 0; v < 16; ++v) {
+                            // two v_and_or (the compiler would otherwise form
+                            // two v_and and a v_or3: 5 % slower at step 1)
+                            int r = (d0[v] & m0) | rf[t][v];
+                            asm volatile("" : "+v"(r));
+                            rf[t][v] = (d1[v] & lmask) | r;
+                        }
                     }
                 }
             } else {
