@@ -405,7 +405,16 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
             const uint32_t o0 = stage_off + ((desc >> (3 * u0)) & 7u) * (2u * kMS * 16u) + lane_off;
             const uint32_t o1 = stage_off + ((desc >> (3 * u1)) & 7u) * (2u * kMS * 16u) + lane_off;
             if (u0 >= nu) {
-                // no unit
+                // No unit. The words still pass through one VALU operation
+                // each: a path that left them where they are would make the
+                // compiler copy every path's results back (32 v_mov_b64 per
+                // pair of units).
+                int z = 0;
+                asm volatile("" : "+v"(z));
+#pragma unroll
+                for (int t = 0; t < kMSub; ++t)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) rf[t][v] |= z;
             } else if (q < nc) {
                 // chained: a neighbour of only x0, then one of only x1
 #pragma unroll
