@@ -286,9 +286,7 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
     // and the first operand / unit count of block 64c + l. One copy follows
     // the blocks whose operands are being loaded (one ahead), one the block
     // being multiplied.
-    // A third word per lane (lanes 0..15) holds this state tile's change
-    // bits of the chunk's variables (32 per word: blocks 4l .. 4l+3).
-    uint32_t tdI = 0, tbI = 0, tdC = 0, tbC = 0, tyI = 0xFFFFFFFFu, tyC = 0xFFFFFFFFu;
+    uint32_t tdI = 0, tbI = 0, tdC = 0, tbC = 0;
     int chunkI = -1;
     auto load_tab = [&](int c) {
         const int b = (c << kTabShift) + lane;
@@ -297,12 +295,49 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
         const uint32_t dsc = A.udesc[o], bs = A.ubase[o];
         tdI = ok ? dsc : 0u;
         tbI = ok ? bs : 0u;
-        if (skip_on) {
-            const int w = (c << (kTabShift - 2)) + lane;
-            const bool okw = lane < (1 << (kTabShift - 2)) && w < A.nw32;
-            const uint32_t yw = A.ych[(int64_t)stile * A.nw32 + (okw ? w : 0)];
-            tyI = okw ? yw : 0u;
+    };
+    // Proposition 2: after step 1 the workgroup visits only the blocks with a
+    // neighbour that changed in the previous step in some state of its state
+    // tile. Bit i of mask_of(c) is set iff block 64c + i is such a block
+    // (lanes 0..15 read the tile's change words of the chunk, 32 variables
+    // = 4 blocks each). Every wave computes the same blocks, so the
+    // workgroup's barriers match.
+    auto mask_of = [&](int c) -> uint64_t {
+        const int w = (c << (kTabShift - 2)) + lane;
+        const bool okw = lane < (1 << (kTabShift - 2)) && w < A.nw32;
+        const uint32_t yw = okw ? A.ych[(int64_t)stile * A.nw32 + w] : 0u;
+        uint64_t m = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            // bit l of b: block 4l + r of the chunk; spread to bit 4l + r
+            uint64_t b = __ballot(((yw >> (8 * r)) & 0xFFu) != 0) & 0xFFFFull;
+            b = (b | (b << 24)) & 0x000000FF000000FFull;
+            b = (b | (b << 12)) & 0x000F000F000F000Full;
+            b = (b | (b << 6)) & 0x0303030303030303ull;
+            b = (b | (b << 3)) & 0x1111111111111111ull;
+            m |= b << r;
         }
+        return m;
+    };
+    int mchunk = -1;
+    uint64_t mbits = 0;
+    // the first block >= from in [blo, bhi) the workgroup visits, or bhi
+    auto next_block = [&](int from) -> int {
+        if (!skip_on) return from < bhi ? from : bhi;
+        while (from < bhi) {
+            const int c = from >> kTabShift;
+            if (c != mchunk) {
+                mchunk = c;
+                mbits = mask_of(c);
+            }
+            const uint64_t m = mbits & (~0ull << (from & 63));
+            if (m) {
+                const int b = (c << kTabShift) + __builtin_ctzll(m);
+                return b < bhi ? b : bhi;
+            }
+            from = (c + 1) << kTabShift;
+        }
+        return bhi;
     };
     auto lane_word = [&](uint32_t t, int b) -> uint32_t {
         return (uint32_t)__builtin_amdgcn_readlane((int)t, b & 63);
@@ -368,35 +403,36 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
     const char *lds = reinterpret_cast<const char *>(s_lds);
     auto ldsb = [&](uint32_t off) { return *reinterpret_cast<const v4i *>(lds + off); };
 
-    {
-        const uint32_t w0 = ops_word(blo);
+    int blk = next_block(blo);
+    if (blk < bhi) {
+        const uint32_t w0 = ops_word(blk);
 #pragma unroll
         for (int q = 0; q < kMaxUnits / 2; ++q) load_two(w0, 2 * q);
+        fetch(blk);
+        store(0);
     }
-    fetch(blo);
-    store(0);
     __syncthreads();
-    for (int blk = blo; blk < bhi; ++blk) {
-        if (blk == blo || (blk & ((1 << kTabShift) - 1)) == 0) {
-            // the operand pointer (one block ahead, in the same chunk) loaded it
+    int cchunk = -1, stage = 0;
+    while (blk < bhi) {
+        if ((blk >> kTabShift) != cchunk) {
+            // the operand loads (one block ahead) moved the lane tables to
+            // this block's chunk
+            cchunk = blk >> kTabShift;
             tdC = tdI;
             tbC = tbI;
-            tyC = tyI;
         }
         const uint32_t desc = lane_word(tdC, blk), wb = lane_word(tbC, blk);
         // the next block's domain tile (stored after this block's products),
         // and its operands, loaded into the registers of each unit pair once
         // it is done
-        const bool more = blk + 1 < bhi;
-        if (more) fetch(blk + 1);
-        const uint32_t wn = ops_word(more ? blk + 1 : blk);
+        const int nxt = next_block(blk + 1);
+        const bool more = nxt < bhi;
+        if (more) fetch(nxt);
+        const uint32_t wn = ops_word(more ? nxt : blk);
 
-        int nu = (int)(wb >> 27);
+        const int nu = (int)(wb >> 27);
         const int nc = (int)((desc >> 24) & 7u), nbe = 2 * nc + (int)((desc >> 27) & 15u);
-        // Proposition 2: after step 1 a block none of whose neighbours changed
-        // in the previous step (in any state of this tile) is skipped
-        if (skip_on && ((lane_word(tyC, (blk & 63) >> 2) >> (8 * (blk & 3))) & 0xFFu) == 0) nu = 0;
-        const uint32_t stage_off = (uint32_t)(((blk - blo) & 1) * kBTile) * 16u;
+        const uint32_t stage_off = (uint32_t)(stage * kBTile) * 16u;
         // a leftover's word has a real flag for its own variable only
         const int lmask = (desc >> 31) ? kFlag1 : kFlag0;
 #pragma unroll
@@ -465,9 +501,11 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
         // block, before the barrier that ended it; one barrier then makes the
         // tile visible.
         if (more) {
-            store((blk - blo + 1) & 1);
+            store(stage ^ 1);
             __syncthreads();
         }
+        stage ^= 1;
+        blk = nxt;
     }
 
     if (nseg > 1) {
