@@ -453,29 +453,42 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
                     for (int v = 0; v < 16; ++v) rf[t][v] |= z;
             } else if (q < nc) {
                 // chained: a neighbour of only x0, then one of only x1
+                v16i e = mfma8(Aop[u1], ldsb(o1), mfma8(Aop[u0], ldsb(o0), bias));
 #pragma unroll
                 for (int t = 0; t < kMSub; ++t) {
-                    const v16i dd = mfma8(Aop[u1], ldsb(o1 + t * 512),
-                                          mfma8(Aop[u0], ldsb(o0 + t * 512), bias));
+                    const v16i dd = e;
+                    if (t + 1 < kMSub)
+                        e = mfma8(Aop[u1], ldsb(o1 + (t + 1) * 512),
+                                  mfma8(Aop[u0], ldsb(o0 + (t + 1) * 512), bias));
 #pragma unroll
                     for (int v = 0; v < 16; ++v) rf[t][v] |= dd[v];
                 }
             } else if (u1 < nu) {
                 // two units: shared neighbours, or leftovers (from index nbe)
                 if (u1 < nbe) {
+                    v16i e0 = mfma8(Aop[u0], ldsb(o0), bias);
+                    v16i e1 = mfma8(Aop[u1], ldsb(o1), bias);
 #pragma unroll
                     for (int t = 0; t < kMSub; ++t) {
-                        const v16i d0 = mfma8(Aop[u0], ldsb(o0 + t * 512), bias);
-                        const v16i d1 = mfma8(Aop[u1], ldsb(o1 + t * 512), bias);
+                        v16i f0 = e0, f1 = e1;
+                        if (t + 1 < kMSub) {
+                            e0 = mfma8(Aop[u0], ldsb(o0 + (t + 1) * 512), bias);
+                            e1 = mfma8(Aop[u1], ldsb(o1 + (t + 1) * 512), bias);
+                        }
 #pragma unroll
-                        for (int v = 0; v < 16; ++v) rf[t][v] = rf[t][v] | d0[v] | d1[v];
+                        for (int v = 0; v < 16; ++v) rf[t][v] = rf[t][v] | f0[v] | f1[v];
                     }
                 } else {
                     const int m0 = u0 < nbe ? -1 : lmask;
+                    v16i e0 = mfma8(Aop[u0], ldsb(o0), bias);
+                    v16i e1 = mfma8(Aop[u1], ldsb(o1), bias);
 #pragma unroll
                     for (int t = 0; t < kMSub; ++t) {
-                        const v16i d0 = mfma8(Aop[u0], ldsb(o0 + t * 512), bias);
-                        const v16i d1 = mfma8(Aop[u1], ldsb(o1 + t * 512), bias);
+                        const v16i d0 = e0, d1 = e1;
+                        if (t + 1 < kMSub) {
+                            e0 = mfma8(Aop[u0], ldsb(o0 + (t + 1) * 512), bias);
+                            e1 = mfma8(Aop[u1], ldsb(o1 + (t + 1) * 512), bias);
+                        }
 #pragma unroll
                         for (int v = 0; v < 16; ++v) {
                             // two v_and_or (the compiler would otherwise form
@@ -488,9 +501,11 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
                 }
             } else {
                 const int m0 = u0 < nbe ? -1 : lmask;
+                v16i e0 = mfma8(Aop[u0], ldsb(o0), bias);
 #pragma unroll
                 for (int t = 0; t < kMSub; ++t) {
-                    const v16i d0 = mfma8(Aop[u0], ldsb(o0 + t * 512), bias);
+                    const v16i d0 = e0;
+                    if (t + 1 < kMSub) e0 = mfma8(Aop[u0], ldsb(o0 + (t + 1) * 512), bias);
 #pragma unroll
                     for (int v = 0; v < 16; ++v) rf[t][v] |= d0[v] & m0;   // one v_and_or each
                 }
