@@ -641,41 +641,61 @@ __global__ void mfma_split_finish_kernel(MArgs A, int k) {
 // Per slot word: OR of the change and wipe-out masks over all variables, and
 // the sum of deg(x) over the variables that changed (support checks of the
 // next step: every arc into a changed variable is re-examined).
-__global__ void mfma_reduce_kernel(MArgs A, int k) {
-    __shared__ uint32_t s_or, s_wp;
-    __shared__ unsigned long long s_deg[32];
+// Block w (1024 threads): 32 groups of 32 lanes, lane b of a group summing
+// for state bit b over the variables x = group, group + 32, ... (every lane
+// of a group reads the same mask words, four variables' words in flight),
+// then the groups' sums are added.
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void mfma_reduce_kernel(MArgs A, int k) {
+    constexpr int kGroups = kReduceThreads / 32;
+    __shared__ uint32_t s_or[kGroups], s_wp[kGroups];
+    __shared__ unsigned long long s_deg[kGroups][32];
     if (step_off(A, k)) return;
     const int nact = A.cnt[(k - 1) & 1];
     const int w = blockIdx.x;
     if (w * 32 >= nact) return;
-    if (threadIdx.x == 0) {
-        s_or = 0;
-        s_wp = 0;
-    }
-    if (threadIdx.x < 32) s_deg[threadIdx.x] = 0;
-    __syncthreads();
+    const int g = threadIdx.x >> 5, b = threadIdx.x & 31;
     uint32_t c_or = 0, w_or = 0;
-    for (int x = threadIdx.x; x < A.n; x += blockDim.x) {
-        const uint32_t c = A.chg[(int64_t)x * A.words + w];
-        c_or |= c;
-        w_or |= A.wipe[(int64_t)x * A.words + w];
-        uint32_t m = c;
-        while (m) {
-            const int b = __ffs(m) - 1;
-            m &= m - 1;
-            atomicAdd(&s_deg[b], (unsigned long long)A.deg[x]);
+    unsigned long long dsum = 0;
+    for (int x0 = g; x0 < A.n; x0 += 4 * kGroups) {
+        uint32_t c[4], wp[4];
+        int32_t dg[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int x = x0 + i * kGroups;
+            const bool in = x < A.n;
+            c[i] = in ? A.chg[(int64_t)x * A.words + w] : 0u;
+            wp[i] = in ? A.wipe[(int64_t)x * A.words + w] : 0u;
+            dg[i] = in ? A.deg[x] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            c_or |= c[i];
+            w_or |= wp[i];
+            dsum += ((c[i] >> b) & 1u) ? (unsigned long long)dg[i] : 0ull;
         }
     }
-    if (c_or) atomicOr(&s_or, c_or);
-    if (w_or) atomicOr(&s_wp, w_or);
+    s_deg[g][b] = dsum;
+    if (b == 0) {
+        s_or[g] = c_or;
+        s_wp[g] = w_or;
+    }
     __syncthreads();
     if (threadIdx.x < 32) {
         const int slot = w * 32 + threadIdx.x;
         if (slot < nact) {
+            uint32_t o = 0, wp = 0;
+            unsigned long long d = 0;
+#pragma unroll
+            for (int i = 0; i < kGroups; ++i) {
+                o |= s_or[i];
+                wp |= s_wp[i];
+                d += s_deg[i][threadIdx.x];
+            }
             MState &m = A.st[A.act[(k - 1) & 1][slot]];
-            m.changed = (s_or >> threadIdx.x) & 1u;
-            m.wiped |= (int32_t)((s_wp >> threadIdx.x) & 1u);
-            m.degsum = s_deg[threadIdx.x];
+            m.changed = (o >> threadIdx.x) & 1u;
+            m.wiped |= (int32_t)((wp >> threadIdx.x) & 1u);
+            m.degsum = d;
         }
     }
 }
@@ -757,28 +777,37 @@ __global__ __launch_bounds__(1024) void mfma_finalize_kernel(MArgs A, int k) {
 
 // After the gather of step k: for each state tile of step k+1 (new slots) and
 // variable y, whether y changed in step k in some state of the tile (bit y of
-// the tile's words, cleared by the finalise kernel). A wave covers 64
-// consecutive new slots of one variable, all in one tile.
+// the tile's words). A wave writes one word, 32 variables of one tile: lane l
+// looks at the tile's new slots l, l + 64, ... through their old slots.
 __global__ void mfma_tile_changed_kernel(MArgs A, int k) {
     if (step_off(A, k)) return;
     const int nnext = A.cnt[k & 1];
-    const int64_t s64 = ((int64_t)nnext + 63) / 64 * 64;
-    const int64_t total = s64 * A.n;
-    const int lane = threadIdx.x & 63;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total;
-         base += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = base + threadIdx.x;
-        const bool in = i < total;
-        const int32_t y = in ? (int32_t)(i / s64) : 0;
-        const int32_t j = in ? (int32_t)(i - (int64_t)y * s64) : 0;
-        bool c = false;
-        if (in && j < nnext) {
-            const int32_t old = A.prev_slot[k & 1][j];
-            c = (A.chg[(int64_t)y * A.words + (old >> 5)] >> (old & 31)) & 1u;
+    const int64_t nwork = (int64_t)((nnext + kMS - 1) / kMS) * A.nw32;
+    const int lane = threadIdx.x & 63, wpb = blockDim.x >> 6;
+    const int32_t *prev = A.prev_slot[k & 1];
+    for (int64_t wk = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); wk < nwork;
+         wk += (int64_t)gridDim.x * wpb) {
+        const int t = (int)(wk / A.nw32), wy = (int)(wk - (int64_t)t * A.nw32);
+        int32_t old[kParts];
+        bool ok[kParts];
+#pragma unroll
+        for (int h = 0; h < kParts; ++h) {
+            const int j = t * kMS + h * 64 + lane;
+            ok[h] = j < nnext;
+            old[h] = ok[h] ? prev[j] : 0;
         }
-        const uint64_t m = __ballot(c);
-        if (lane == 0 && m)
-            atomicOr(A.ych + (int64_t)(j / kMS) * A.nw32 + (y >> 5), 1u << (y & 31));
+        uint32_t word = 0;
+        for (int yi = 0; yi < 32; ++yi) {
+            const int y = wy * 32 + yi;
+            if (y >= A.n) break;
+            const uint32_t *row = A.chg + (int64_t)y * A.words;
+            bool c = false;
+#pragma unroll
+            for (int h = 0; h < kParts; ++h)
+                c |= ok[h] && ((row[old[h] >> 5] >> (old[h] & 31)) & 1u);
+            if (__ballot(c)) word |= 1u << yi;
+        }
+        if (lane == 0) A.ych[(int64_t)t * A.nw32 + wy] = word;
     }
 }
 
@@ -1329,7 +1358,7 @@ static int run_steps(MfmaData &md, const MArgs &A, bool profile, hipStream_t str
                                        dim3(small_blocks), dim3(256), 0, p2));
                     if (timed) RC_OK(round_event(rd.graph, &prev, m->kev[2 * (kk - 1) + 1]));
                     RC_OK(round_node(rd.graph, &prev, (const void *)mfma_reduce_kernel,
-                                       dim3((A.B + 31) / 32), dim3(256), 0, p2));
+                                       dim3((A.B + 31) / 32), dim3(kReduceThreads), 0, p2));
                     RC_OK(round_node(rd.graph, &prev, (const void *)mfma_finalize_kernel, dim3(1),
                                        dim3(1024), 0, p2));
                     RC_OK(round_node(rd.graph, &prev, (const void *)mfma_gather_kernel, dim3(init_blocks),
@@ -1351,7 +1380,7 @@ static int run_steps(MfmaData &md, const MArgs &A, bool profile, hipStream_t str
                                    A, k, fgrid);
                 hipLaunchKernelGGL(mfma_split_finish_kernel, dim3(small_blocks), dim3(256), 0, stream, A, k);
                 if (timed) HIP_OK(hipEventRecord(m->kev[2 * (k - 1) + 1], stream));
-                hipLaunchKernelGGL(mfma_reduce_kernel, dim3((A.B + 31) / 32), dim3(256), 0, stream, A, k);
+                hipLaunchKernelGGL(mfma_reduce_kernel, dim3((A.B + 31) / 32), dim3(kReduceThreads), 0, stream, A, k);
                 hipLaunchKernelGGL(mfma_finalize_kernel, dim3(1), dim3(1024), 0, stream, A, k);
                 hipLaunchKernelGGL(mfma_gather_kernel, dim3(init_blocks), dim3(256), 0, stream, A, k);
                 if (A.skip)
