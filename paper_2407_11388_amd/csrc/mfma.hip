@@ -52,6 +52,7 @@ constexpr int kMX = kMW * kXW;    // variables per workgroup
 constexpr int kMSub = 4;          // 32-state sub-tiles per wave
 constexpr int kMS = 32 * kMSub;   // states per workgroup
 constexpr int kMY = 8;            // neighbours per LDS block
+constexpr int kSB = 2;            // neighbour blocks per LDS stage (a superblock)
 constexpr int kMThreads = 64 * kMW;
 constexpr int kMaxTrackedSteps = 256;   // steps whose re-examined arcs are counted
 constexpr int kNsegMax = 4;             // workgroups per tile of a split step, at most
@@ -130,7 +131,8 @@ __device__ __forceinline__ bool step_off(const MArgs &A, int k) {
 __device__ __forceinline__ int split_for(const MArgs &A, int active) {
     const int sact = (active + kMS - 1) / kMS;
     const int tiles = A.ntiles_x * sact;
-    const int cap = A.nblk < kNsegMax ? A.nblk : kNsegMax;
+    const int nsb = (A.nblk + kSB - 1) / kSB;   // superblocks (the unit of a split)
+    const int cap = nsb < kNsegMax ? nsb : kNsegMax;
     if (A.force_seg > 0) return A.force_seg < cap ? A.force_seg : cap;
     int sg = tiles > 0 ? A.cus / tiles : 1;
     // workgroups the grid holds for each active tile: those of the idle tiles
@@ -195,10 +197,10 @@ __global__ void mfma_init_kernel(MArgs A) {
 }
 
 
-constexpr int kStages = 2;                          // LDS domain tiles (double buffer)
-constexpr int kBTile = kMY * 2 * kMS;               // v4i per domain tile (32 KiB)
+constexpr int kStages = 2;                          // LDS stages (double buffer)
+constexpr int kBTile = kMY * 2 * kMS;               // v4i per block's domain tile (32 KiB)
 constexpr int kMaxUnits = kMY;                      // operands of a pair in one block: <= 8
-constexpr size_t kMSmem = (size_t)kStages * kBTile * 16;   // 64 KiB
+constexpr size_t kMSmem = (size_t)kStages * kSB * kBTile * 16;   // 128 KiB
 constexpr int kRowsPerWave = kMY * 2 / kMW;         // domain rows (y, half) each wave copies
 constexpr int kParts = kMS / 64;                     // 64-slot parts of a row
 constexpr int kCopyPerBlock = kRowsPerWave * kParts; // 16-byte copies per lane and block
@@ -266,8 +268,11 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
     if (sact == 0 || xt * kMX >= A.n) return;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    // this workgroup's neighbour blocks [blo, bhi) (all of them unless split)
-    const int blo = (int)((int64_t)seg * A.nblk / nseg), bhi = (int)((int64_t)(seg + 1) * A.nblk / nseg);
+    // this workgroup's superblocks [sblo, sbhi) of kSB neighbour blocks (all
+    // of them unless split), which end at block bhi
+    const int nsb = (A.nblk + kSB - 1) / kSB;
+    const int sblo = (int)((int64_t)seg * nsb / nseg), sbhi = (int)((int64_t)(seg + 1) * nsb / nseg);
+    const int bhi = sbhi * kSB < A.nblk ? sbhi * kSB : A.nblk;
     // this wave's pair p and its variables x = 2p + i
     const int pr = xt * kMW + wave;
     int xs[kXW];
@@ -296,9 +301,10 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
         tdI = ok ? dsc : 0u;
         tbI = ok ? bs : 0u;
     };
-    // Proposition 2: after step 1 the workgroup visits only the blocks with a
-    // neighbour that changed in the previous step in some state of its state
-    // tile. Bit i of mask_of(c) is set iff block 64c + i is such a block
+    // Proposition 2: after step 1 the workgroup visits only the superblocks
+    // with a neighbour that changed in the previous step in some state of its
+    // state tile. Bit i of mask_of(c) is set iff block 64c + i has such a
+    // neighbour
     // (lanes 0..15 read the tile's change words of the chunk, 32 variables
     // = 4 blocks each). Every wave computes the same blocks, so the
     // workgroup's barriers match.
@@ -321,23 +327,26 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
     };
     int mchunk = -1;
     uint64_t mbits = 0;
-    // the first block >= from in [blo, bhi) the workgroup visits, or bhi
-    auto next_block = [&](int from) -> int {
-        if (!skip_on) return from < bhi ? from : bhi;
-        while (from < bhi) {
-            const int c = from >> kTabShift;
+    static_assert(kSB == 2 && (1 << kTabShift) % kSB == 0, "superblocks of two blocks, within a chunk");
+    // the first superblock >= from in [sblo, sbhi) the workgroup visits, or sbhi
+    auto next_sb = [&](int from) -> int {
+        if (!skip_on) return from < sbhi ? from : sbhi;
+        while (from < sbhi) {
+            const int b0 = from * kSB, c = b0 >> kTabShift;
             if (c != mchunk) {
                 mchunk = c;
                 mbits = mask_of(c);
             }
-            const uint64_t m = mbits & (~0ull << (from & 63));
+            // bit 2i: superblock i of the chunk has a block to visit
+            const uint64_t sm = (mbits | (mbits >> 1)) & 0x5555555555555555ull;
+            const uint64_t m = sm & (~0ull << (b0 & 63));
             if (m) {
-                const int b = (c << kTabShift) + __builtin_ctzll(m);
-                return b < bhi ? b : bhi;
+                const int sbn = ((c << kTabShift) + __builtin_ctzll(m)) / kSB;
+                return sbn < sbhi ? sbn : sbhi;
             }
-            from = (c + 1) << kTabShift;
+            from = ((c + 1) << kTabShift) / kSB;
         }
-        return bhi;
+        return sbhi;
     };
     auto lane_word = [&](uint32_t t, int b) -> uint32_t {
         return (uint32_t)__builtin_amdgcn_readlane((int)t, b & 63);
@@ -365,10 +374,11 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
     // The domain tile of block `blk`: 16 rows (neighbour yl, half h) of 128
     // consecutive slots, 2 KiB each in both memories; wave w copies rows 2w
     // and 2w+1 as 1 KiB halves, loaded into registers (fetch) and written to
-    // an LDS stage (store). A neighbour past n copies variable n-1's row
-    // (never a neighbour of anything); slots past the active ones are in the
-    // buffer and never used. (Registers rather than direct-to-LDS copies: the
-    // compiler then waits for each operand load precisely.)
+    // block position sh of an LDS stage (store). A neighbour past n copies
+    // variable n-1's row (never a neighbour of anything); slots past the
+    // active ones are in the buffer and never used. (Registers rather than
+    // direct-to-LDS copies: the compiler then waits for each operand load
+    // precisely.)
     v4i cp[kCopyPerBlock];
     auto fetch = [&](int blk) {
 #pragma unroll
@@ -380,8 +390,8 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
             cp[i] = *reinterpret_cast<const v4i *>(din + dom_off(A, y, h, st0 + part * 64 + lane));
         }
     };
-    auto store = [&](int stg) {
-        v4i *bt = s_lds + stg * kBTile;
+    auto store = [&](int stg, int sh) {
+        v4i *bt = s_lds + (stg * kSB + sh) * kBTile;
 #pragma unroll
         for (int i = 0; i < kCopyPerBlock; ++i) {
             const int row = wave * kRowsPerWave + i / kParts, part = i % kParts;
@@ -403,17 +413,28 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
     const char *lds = reinterpret_cast<const char *>(s_lds);
     auto ldsb = [&](uint32_t off) { return *reinterpret_cast<const v4i *>(lds + off); };
 
-    int blk = next_block(blo);
-    if (blk < bhi) {
-        const uint32_t w0 = ops_word(blk);
+    // A stage holds the tiles of a superblock's kSB blocks. While block h of
+    // superblock sb is multiplied, block h of the next visited superblock is
+    // loaded into registers and then written to the other stage; one barrier
+    // per superblock makes both visible.
+    int sb = next_sb(sblo);
+    if (sb < sbhi) {
+        const uint32_t w0 = ops_word(sb * kSB);
 #pragma unroll
         for (int q = 0; q < kMaxUnits / 2; ++q) load_two(w0, 2 * q);
-        fetch(blk);
-        store(0);
+        for (int h = 0; h < kSB; ++h) {
+            fetch(sb * kSB + h);
+            store(0, h);
+        }
     }
     __syncthreads();
     int cchunk = -1, stage = 0;
-    while (blk < bhi) {
+    while (sb < sbhi) {
+      const int sbn = next_sb(sb + 1);
+      const bool more = sbn < sbhi;
+      for (int h = 0; h < kSB; ++h) {
+        const int blk = sb * kSB + h;
+        if (blk >= bhi) break;   // the last superblock of an odd block count
         if ((blk >> kTabShift) != cchunk) {
             // the operand loads (one block ahead) moved the lane tables to
             // this block's chunk
@@ -422,17 +443,16 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
             tbC = tbI;
         }
         const uint32_t desc = lane_word(tdC, blk), wb = lane_word(tbC, blk);
-        // the next block's domain tile (stored after this block's products),
-        // and its operands, loaded into the registers of each unit pair once
-        // it is done
-        const int nxt = next_block(blk + 1);
-        const bool more = nxt < bhi;
-        if (more) fetch(nxt);
-        const uint32_t wn = ops_word(more ? nxt : blk);
+        // block h of the next superblock's domain tile (stored after this
+        // block's products), and the operands of the next block multiplied,
+        // loaded into the registers of each unit pair once it is done
+        const int nxt = (h + 1 < kSB && blk + 1 < bhi) ? blk + 1 : (more ? sbn * kSB : blk);
+        if (more) fetch(sbn * kSB + h);
+        const uint32_t wn = ops_word(nxt);
 
         const int nu = (int)(wb >> 27);
         const int nc = (int)((desc >> 24) & 7u), nbe = 2 * nc + (int)((desc >> 27) & 15u);
-        const uint32_t stage_off = (uint32_t)(stage * kBTile) * 16u;
+        const uint32_t stage_off = (uint32_t)((stage * kSB + h) * kBTile) * 16u;
         // a leftover's word has a real flag for its own variable only
         const int lmask = (desc >> 31) ? kFlag1 : kFlag0;
 #pragma unroll
@@ -512,15 +532,13 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
             }
             load_two(wn, u0);   // this pair's registers now take the next block's operands
         }
-        // The next tile goes to the stage every wave last read in the previous
-        // block, before the barrier that ended it; one barrier then makes the
-        // tile visible.
-        if (more) {
-            store(stage ^ 1);
-            __syncthreads();
-        }
-        stage ^= 1;
-        blk = nxt;
+        // The next superblock's tile goes to the stage every wave last read
+        // in the previous superblock, before the barrier that ended it.
+        if (more) store(stage ^ 1, h);
+      }
+      if (more) __syncthreads();
+      stage ^= 1;
+      sb = sbn;
     }
 
     if (nseg > 1) {
