@@ -13,11 +13,12 @@
 // flags over y.
 //
 // Tiling. A workgroup of 8 waves owns 16 variables x (a pair per wave) and
-// 128 states (4 sub-tiles of 32). It walks y = 0..n-1 in blocks of 8. The
-// domain bytes of the block for its 128 states (stored per variable in the
-// order of the active-state slots, so one (y, half) row of 128 slots is
-// 2 KiB of consecutive memory) are loaded into registers one block ahead and
-// written to the other half of a 2-stage LDS buffer at the end of the block;
+// 128 states (4 sub-tiles of 32). It walks y = 0..n-1 in blocks of 8, two
+// blocks (a superblock) per stage of a 2-stage LDS buffer. The domain bytes
+// of a block for its 128 states (stored per variable in the order of the
+// active-state slots, so one (y, half) row of 128 slots is 2 KiB of
+// consecutive memory) are loaded into registers one superblock ahead and
+// written to the other stage at the end of the block;
 // each wave loads its pair's relation operands for the block's neighbours
 // (packed once per network, see mfma_pack_ops_kernel) into registers, also a
 // block ahead, and multiplies them with the staged bytes, one
