@@ -93,7 +93,9 @@ typedef struct rac_options {
                              size are chosen: 0 (default) the autotuner's table for the call's
                              shape, measured on the call's own inputs the first time a shape is
                              seen (the environment variable RAC_TUNE=rules or =measure overrides
-                             this default); 1: fixed rules, no measurement; 2: measure again */
+                             this default); 1: fixed rules, no measurement; 2: measure again.
+                             A call with max_sweeps > 0 is never measured: it uses the table
+                             entry when there is one, else the fixed rules */
     int32_t reserved;     /* must be zero */
 } rac_options;
 

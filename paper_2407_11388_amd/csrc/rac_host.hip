@@ -1275,6 +1275,9 @@ static CallChoice lookup_choice(rac_net *net, int kind, int32_t B, bool *measure
         c.source = t.source;
         return c;
     }
+    // a call capped below the step bound (max_sweeps > 0) is no sample of
+    // the shape's own runs: it takes the rules and stores nothing
+    if (net->opt.max_sweeps > 0) return c;
     *measure = true;
     return c;
 }

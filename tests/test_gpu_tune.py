@@ -95,6 +95,31 @@ def test_rules_mode_does_not_measure(n, expect):
     net.close()
 
 
+def test_capped_call_does_not_measure():
+    # A call capped below the step bound is no sample of the shape's full
+    # runs: it takes the fixed rules and stores nothing; the next uncapped
+    # call of the shape is measured.
+    inst = gen.model_b(330, 140, 12, 0.6, 0.3)
+    doms, _ = gen.partial_assign_states(331, 140, 12, 72, 8)
+    before = len(table_lines("batch"))
+    say("[gpu] tuner: capped call, not measured")
+    net = rac.Net.from_instance(inst, max_sweeps=1)
+    try:
+        net.enforce_batch(doms)
+    except rac.RacError as e:
+        assert e.code == rac.RAC_ENOTCONVERGED
+    assert net.stats().tune_source == 0
+    assert len(table_lines("batch")) == before
+    net.close()
+    say("[gpu] tuner: the same shape uncapped, measured")
+    net2 = rac.Net.from_instance(inst)
+    got, iters, status = net2.enforce_batch(doms)
+    assert net2.stats().tune_source == 3
+    assert len(table_lines("batch")) == before + 1
+    check_states(inst, doms, got, iters, status)
+    net2.close()
+
+
 # every candidate the tuner can pick, forced: bit rows and int8 rows with
 # small, default and large work items, the matrix cores with hand-off at 32
 # states and never, the fused path
