@@ -431,115 +431,115 @@ __global__ __launch_bounds__(kMThreads) void mfma_sweep_kernel(MArgs A, int k, i
     __syncthreads();
     int cchunk = -1, stage = 0;
     while (sb < sbhi) {
-      const int sbn = next_sb(sb + 1);
-      const bool more = sbn < sbhi;
-      for (int h = 0; h < kSB; ++h) {
-        const int blk = sb * kSB + h;
-        if (blk >= bhi) break;   // the last superblock of an odd block count
-        if ((blk >> kTabShift) != cchunk) {
-            // the operand loads (one block ahead) moved the lane tables to
-            // this block's chunk
-            cchunk = blk >> kTabShift;
-            tdC = tdI;
-            tbC = tbI;
-        }
-        const uint32_t desc = lane_word(tdC, blk), wb = lane_word(tbC, blk);
-        // block h of the next superblock's domain tile (stored after this
-        // block's products), and the operands of the next block multiplied,
-        // loaded into the registers of each unit pair once it is done
-        const int nxt = (h + 1 < kSB && blk + 1 < bhi) ? blk + 1 : (more ? sbn * kSB : blk);
-        if (more) fetch(sbn * kSB + h);
-        const uint32_t wn = ops_word(nxt);
+        const int sbn = next_sb(sb + 1);
+        const bool more = sbn < sbhi;
+        for (int h = 0; h < kSB; ++h) {
+            const int blk = sb * kSB + h;
+            if (blk >= bhi) break;   // the last superblock of an odd block count
+            if ((blk >> kTabShift) != cchunk) {
+                // the operand loads (one block ahead) moved the lane tables to
+                // this block's chunk
+                cchunk = blk >> kTabShift;
+                tdC = tdI;
+                tbC = tbI;
+            }
+            const uint32_t desc = lane_word(tdC, blk), wb = lane_word(tbC, blk);
+            // block h of the next superblock's domain tile (stored after this
+            // block's products), and the operands of the next block multiplied,
+            // loaded into the registers of each unit pair once it is done
+            const int nxt = (h + 1 < kSB && blk + 1 < bhi) ? blk + 1 : (more ? sbn * kSB : blk);
+            if (more) fetch(sbn * kSB + h);
+            const uint32_t wn = ops_word(nxt);
 
-        const int nu = (int)(wb >> 27);
-        const int nc = (int)((desc >> 24) & 7u), nbe = 2 * nc + (int)((desc >> 27) & 15u);
-        const uint32_t stage_off = (uint32_t)((stage * kSB + h) * kBTile) * 16u;
-        // a leftover's word has a real flag for its own variable only
-        const int lmask = (desc >> 31) ? kFlag1 : kFlag0;
+            const int nu = (int)(wb >> 27);
+            const int nc = (int)((desc >> 24) & 7u), nbe = 2 * nc + (int)((desc >> 27) & 15u);
+            const uint32_t stage_off = (uint32_t)((stage * kSB + h) * kBTile) * 16u;
+            // a leftover's word has a real flag for its own variable only
+            const int lmask = (desc >> 31) ? kFlag1 : kFlag0;
 #pragma unroll
-        for (int q = 0; q < kMaxUnits / 2; ++q) {
-            const int u0 = 2 * q, u1 = 2 * q + 1;
-            const uint32_t o0 = stage_off + ((desc >> (3 * u0)) & 7u) * (2u * kMS * 16u) + lane_off;
-            const uint32_t o1 = stage_off + ((desc >> (3 * u1)) & 7u) * (2u * kMS * 16u) + lane_off;
-            if (u0 >= nu) {
-                // No unit. The words still pass through one VALU operation
-                // each: a path that left them where they are would make the
-                // compiler copy every path's results back (32 v_mov_b64 per
-                // pair of units).
-                int z = 0;
-                asm volatile("" : "+v"(z));
+            for (int q = 0; q < kMaxUnits / 2; ++q) {
+                const int u0 = 2 * q, u1 = 2 * q + 1;
+                const uint32_t o0 = stage_off + ((desc >> (3 * u0)) & 7u) * (2u * kMS * 16u) + lane_off;
+                const uint32_t o1 = stage_off + ((desc >> (3 * u1)) & 7u) * (2u * kMS * 16u) + lane_off;
+                if (u0 >= nu) {
+                    // No unit. The words still pass through one VALU operation
+                    // each: a path that left them where they are would make the
+                    // compiler copy every path's results back (32 v_mov_b64 per
+                    // pair of units).
+                    int z = 0;
+                    asm volatile("" : "+v"(z));
 #pragma unroll
-                for (int t = 0; t < kMSub; ++t)
+                    for (int t = 0; t < kMSub; ++t)
 #pragma unroll
-                    for (int v = 0; v < 16; ++v) rf[t][v] |= z;
-            } else if (q < nc) {
-                // chained: a neighbour of only x0, then one of only x1
-                v16i e = mfma8(Aop[u1], ldsb(o1), mfma8(Aop[u0], ldsb(o0), bias));
-#pragma unroll
-                for (int t = 0; t < kMSub; ++t) {
-                    const v16i dd = e;
-                    if (t + 1 < kMSub)
-                        e = mfma8(Aop[u1], ldsb(o1 + (t + 1) * 512),
-                                  mfma8(Aop[u0], ldsb(o0 + (t + 1) * 512), bias));
-#pragma unroll
-                    for (int v = 0; v < 16; ++v) rf[t][v] |= dd[v];
-                }
-            } else if (u1 < nu) {
-                // two units: shared neighbours, or leftovers (from index nbe)
-                if (u1 < nbe) {
-                    v16i e0 = mfma8(Aop[u0], ldsb(o0), bias);
-                    v16i e1 = mfma8(Aop[u1], ldsb(o1), bias);
+                        for (int v = 0; v < 16; ++v) rf[t][v] |= z;
+                } else if (q < nc) {
+                    // chained: a neighbour of only x0, then one of only x1
+                    v16i e = mfma8(Aop[u1], ldsb(o1), mfma8(Aop[u0], ldsb(o0), bias));
 #pragma unroll
                     for (int t = 0; t < kMSub; ++t) {
-                        v16i f0 = e0, f1 = e1;
-                        if (t + 1 < kMSub) {
-                            e0 = mfma8(Aop[u0], ldsb(o0 + (t + 1) * 512), bias);
-                            e1 = mfma8(Aop[u1], ldsb(o1 + (t + 1) * 512), bias);
-                        }
+                        const v16i dd = e;
+                        if (t + 1 < kMSub)
+                            e = mfma8(Aop[u1], ldsb(o1 + (t + 1) * 512),
+                                      mfma8(Aop[u0], ldsb(o0 + (t + 1) * 512), bias));
 #pragma unroll
-                        for (int v = 0; v < 16; ++v) rf[t][v] = rf[t][v] | f0[v] | f1[v];
+                        for (int v = 0; v < 16; ++v) rf[t][v] |= dd[v];
+                    }
+                } else if (u1 < nu) {
+                    // two units: shared neighbours, or leftovers (from index nbe)
+                    if (u1 < nbe) {
+                        v16i e0 = mfma8(Aop[u0], ldsb(o0), bias);
+                        v16i e1 = mfma8(Aop[u1], ldsb(o1), bias);
+#pragma unroll
+                        for (int t = 0; t < kMSub; ++t) {
+                            v16i f0 = e0, f1 = e1;
+                            if (t + 1 < kMSub) {
+                                e0 = mfma8(Aop[u0], ldsb(o0 + (t + 1) * 512), bias);
+                                e1 = mfma8(Aop[u1], ldsb(o1 + (t + 1) * 512), bias);
+                            }
+#pragma unroll
+                            for (int v = 0; v < 16; ++v) rf[t][v] = rf[t][v] | f0[v] | f1[v];
+                        }
+                    } else {
+                        const int m0 = u0 < nbe ? -1 : lmask;
+                        v16i e0 = mfma8(Aop[u0], ldsb(o0), bias);
+                        v16i e1 = mfma8(Aop[u1], ldsb(o1), bias);
+#pragma unroll
+                        for (int t = 0; t < kMSub; ++t) {
+                            const v16i d0 = e0, d1 = e1;
+                            if (t + 1 < kMSub) {
+                                e0 = mfma8(Aop[u0], ldsb(o0 + (t + 1) * 512), bias);
+                                e1 = mfma8(Aop[u1], ldsb(o1 + (t + 1) * 512), bias);
+                            }
+#pragma unroll
+                            for (int v = 0; v < 16; ++v) {
+                                // two v_and_or (the compiler would otherwise form
+                                // two v_and and a v_or3: 5 % slower at step 1)
+                                int r = (d0[v] & m0) | rf[t][v];
+                                asm volatile("" : "+v"(r));
+                                rf[t][v] = (d1[v] & lmask) | r;
+                            }
+                        }
                     }
                 } else {
                     const int m0 = u0 < nbe ? -1 : lmask;
                     v16i e0 = mfma8(Aop[u0], ldsb(o0), bias);
-                    v16i e1 = mfma8(Aop[u1], ldsb(o1), bias);
 #pragma unroll
                     for (int t = 0; t < kMSub; ++t) {
-                        const v16i d0 = e0, d1 = e1;
-                        if (t + 1 < kMSub) {
-                            e0 = mfma8(Aop[u0], ldsb(o0 + (t + 1) * 512), bias);
-                            e1 = mfma8(Aop[u1], ldsb(o1 + (t + 1) * 512), bias);
-                        }
+                        const v16i d0 = e0;
+                        if (t + 1 < kMSub) e0 = mfma8(Aop[u0], ldsb(o0 + (t + 1) * 512), bias);
 #pragma unroll
-                        for (int v = 0; v < 16; ++v) {
-                            // two v_and_or (the compiler would otherwise form
-                            // two v_and and a v_or3: 5 % slower at step 1)
-                            int r = (d0[v] & m0) | rf[t][v];
-                            asm volatile("" : "+v"(r));
-                            rf[t][v] = (d1[v] & lmask) | r;
-                        }
+                        for (int v = 0; v < 16; ++v) rf[t][v] |= d0[v] & m0;   // one v_and_or each
                     }
                 }
-            } else {
-                const int m0 = u0 < nbe ? -1 : lmask;
-                v16i e0 = mfma8(Aop[u0], ldsb(o0), bias);
-#pragma unroll
-                for (int t = 0; t < kMSub; ++t) {
-                    const v16i d0 = e0;
-                    if (t + 1 < kMSub) e0 = mfma8(Aop[u0], ldsb(o0 + (t + 1) * 512), bias);
-#pragma unroll
-                    for (int v = 0; v < 16; ++v) rf[t][v] |= d0[v] & m0;   // one v_and_or each
-                }
+                load_two(wn, u0);   // this pair's registers now take the next block's operands
             }
-            load_two(wn, u0);   // this pair's registers now take the next block's operands
+            // The next superblock's tile goes to the stage every wave last read
+            // in the previous superblock, before the barrier that ended it.
+            if (more) store(stage ^ 1, h);
         }
-        // The next superblock's tile goes to the stage every wave last read
-        // in the previous superblock, before the barrier that ended it.
-        if (more) store(stage ^ 1, h);
-      }
-      if (more) __syncthreads();
-      stage ^= 1;
-      sb = sbn;
+        if (more) __syncthreads();
+        stage ^= 1;
+        sb = sbn;
     }
 
     if (nseg > 1) {
