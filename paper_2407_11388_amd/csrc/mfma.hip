@@ -1334,6 +1334,12 @@ static int run_steps(MfmaData &md, const MArgs &A, bool profile, hipStream_t str
     const int init_blocks = (int)std::min<int64_t>(4096, ((int64_t)A.B * A.n + 255) / 256);
     const int64_t thr64 = ((int64_t)A.B + 63) / 64 * 64 * A.n;
     const unsigned small_blocks = (unsigned)std::min<int64_t>(4096, (thr64 + 255) / 256);
+    // a split step's finish kernel strides over its states (no step of the
+    // batch's first rounds splits, and an idle grid still costs its launch);
+    // the tile-change kernel has one wave per word of a state tile
+    const unsigned split_blocks = std::min<unsigned>(small_blocks, 1024u);
+    const unsigned tc_blocks = (unsigned)std::max<int64_t>(
+        1, (((int64_t)A.B + kMS - 1) / kMS * A.nw32 + 3) / 4);
     const int32_t maxs = A.max_sweeps > 0 ? A.max_sweeps : A.n * A.d + 1;
     // rounds are replayed graphs, also when profiling: the timing events are
     // nodes of the graphs (RAC_MFMA_GRAPHS=0: direct launches)
@@ -1374,7 +1380,7 @@ static int run_steps(MfmaData &md, const MArgs &A, bool profile, hipStream_t str
                     RC_OK(round_node(rd.graph, &prev, (const void *)mfma_sweep_kernel, dim3(sweep_blocks),
                                        dim3(kMThreads), kMSmem, p3));
                     RC_OK(round_node(rd.graph, &prev, (const void *)mfma_split_finish_kernel,
-                                       dim3(small_blocks), dim3(256), 0, p2));
+                                       dim3(split_blocks), dim3(256), 0, p2));
                     if (timed) RC_OK(round_event(rd.graph, &prev, m->kev[2 * (kk - 1) + 1]));
                     RC_OK(round_node(rd.graph, &prev, (const void *)mfma_reduce_kernel,
                                        dim3((A.B + 31) / 32), dim3(kReduceThreads), 0, p2));
@@ -1384,7 +1390,7 @@ static int run_steps(MfmaData &md, const MArgs &A, bool profile, hipStream_t str
                                        dim3(256), 0, p2));
                     if (A.skip)
                         RC_OK(round_node(rd.graph, &prev, (const void *)mfma_tile_changed_kernel,
-                                           dim3(small_blocks), dim3(256), 0, p2));
+                                           dim3(tc_blocks), dim3(256), 0, p2));
                 }
                 HIP_OK(hipGraphInstantiate(&rd.exec, rd.graph, nullptr, nullptr, 0));
             }
@@ -1397,13 +1403,13 @@ static int run_steps(MfmaData &md, const MArgs &A, bool profile, hipStream_t str
                 if (timed) HIP_OK(hipEventRecord(m->kev[2 * (k - 1)], stream));
                 hipLaunchKernelGGL(mfma_sweep_kernel, dim3(sweep_blocks), dim3(kMThreads), kMSmem, stream,
                                    A, k, fgrid);
-                hipLaunchKernelGGL(mfma_split_finish_kernel, dim3(small_blocks), dim3(256), 0, stream, A, k);
+                hipLaunchKernelGGL(mfma_split_finish_kernel, dim3(split_blocks), dim3(256), 0, stream, A, k);
                 if (timed) HIP_OK(hipEventRecord(m->kev[2 * (k - 1) + 1], stream));
                 hipLaunchKernelGGL(mfma_reduce_kernel, dim3((A.B + 31) / 32), dim3(kReduceThreads), 0, stream, A, k);
                 hipLaunchKernelGGL(mfma_finalize_kernel, dim3(1), dim3(1024), 0, stream, A, k);
                 hipLaunchKernelGGL(mfma_gather_kernel, dim3(init_blocks), dim3(256), 0, stream, A, k);
                 if (A.skip)
-                    hipLaunchKernelGGL(mfma_tile_changed_kernel, dim3(small_blocks), dim3(256), 0, stream,
+                    hipLaunchKernelGGL(mfma_tile_changed_kernel, dim3(tc_blocks), dim3(256), 0, stream,
                                        A, k);
             }
         }
