@@ -246,6 +246,29 @@ def parse():
     return ap.parse_args()
 
 
+def copy_rate(dev, nbytes: int = 1 << 30, reps: int = 5) -> dict:
+    """The box's achievable HBM rate: a device-to-device copy of nbytes
+    (read plus write bytes per second, best of reps, HIP events), beside the
+    8 TB/s specification the fractions are quoted against."""
+    import torch
+    src = torch.ones(nbytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = 1e9
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    gbs = 2 * nbytes / (best * 1e-3) / 1e9
+    del src, dst
+    return dict(bytes=nbytes, ms=best, read_write_GBs=gbs, frac_of_spec=gbs / HBM_PEAK_GBS,
+                note="torch copy_ on the current stream; read + write bytes")
+
+
 def algo_row_bytes(inst, path: str = "bits") -> int:
     """Relation bytes a full sweep of one state must read, without layout
     padding: per arc, d rows of ceil(d/32) 32-bit words (bit rows; 8-byte rows
@@ -806,6 +829,7 @@ def main():
                 nt.close()
         if not args.no_search:
             sec.update(search_lines())
+        sec["hbm copy (context for the HBM fractions)"] = copy_rate(dev)
         out["secondary"] = sec
 
     print(json.dumps(out), flush=True)
