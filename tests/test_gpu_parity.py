@@ -318,6 +318,39 @@ def test_batch_states_mfma_split_steps(n, d, B, p1, p2, segments, monkeypatch):
     net.close()
 
 
+def test_batch_states_mfma_random_shapes(monkeypatch):
+    # Seeded random shapes on the matrix-core path (n 8..319, d 2..32, B
+    # 1..299, density and tightness across their range), each with a random
+    # hand-off, forced split, Proposition 2 skip setting and mode; every
+    # state against the oracle. Odd block counts, partial superblocks and
+    # partial state tiles all occur.
+    rng = np.random.default_rng(2024)
+    for c in range(24):
+        n = int(rng.integers(8, 320))
+        d = int(rng.integers(2, 33))
+        B = int(rng.integers(1, 300))
+        p1, p2 = float(rng.uniform(0.05, 1.0)), float(rng.uniform(0.05, 0.6))
+        mode = int(rng.integers(0, 2))
+        handoff = str(rng.choice(["0", "32", "100000"]))
+        seg = str(rng.choice(["0", "0", "2", "3", "4"]))
+        skip = str(rng.choice(["1", "1", "0"]))
+        monkeypatch.setenv("RAC_MFMA_HANDOFF", handoff)
+        monkeypatch.setenv("RAC_MFMA_SEGMENTS", seg)
+        monkeypatch.setenv("RAC_MFMA_SKIP", skip)
+        inst = gen.model_b(1000 + c, n, d, p1, p2)
+        doms, _ = gen.partial_assign_states(2000 + c, n, d, B, min(n, int(rng.integers(0, 25))))
+        rel = inst.rel_u8()
+        say(f"[gpu] batch mfma random {c}: n={n} d={d} B={B} p1={p1:.2f} p2={p2:.2f} "
+            f"mode={mode} handoff={handoff} seg={seg} skip={skip}")
+        net = rac.Net.from_u8(n, d, inst.edges, rel, path=rac.PATH_MFMA, mode=mode)
+        got, iters, status = net.enforce_batch(doms)
+        net.close()
+        for s in range(B):
+            exp, e_it, e_st, _, _ = oracle_expect(n, d, inst.edges, rel, doms[s], mode)
+            assert np.array_equal(got[s], exp), f"case {c} state {s}"
+            assert iters[s] == e_it and status[s] == e_st, f"case {c} state {s}"
+
+
 def frontier_states(inst, doms, seed):
     """States one removal away from arc consistency: the closure of each
     state (the oracle's), then one value of one variable with at least two
