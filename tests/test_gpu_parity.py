@@ -318,6 +318,38 @@ def test_batch_states_mfma_split_steps(n, d, B, p1, p2, segments, monkeypatch):
     net.close()
 
 
+def test_random_shapes_bits_int8_fused(monkeypatch):
+    # Seeded random shapes on the bit, int8 and fused paths (n 10..399, d up
+    # to 64 on bit rows and 32 otherwise, one state or a batch, both modes,
+    # the sparse-step ratio varied); every state against the oracle.
+    rng = np.random.default_rng(2025)
+    for c in range(30):
+        path = int(rng.choice([rac.PATH_BITS, rac.PATH_INT8, rac.PATH_FUSED]))
+        n = int(rng.integers(10, 400))
+        d = int(rng.integers(1, 65 if path == rac.PATH_BITS else 33))
+        B = int(rng.integers(1, 80))
+        p1, p2 = float(rng.uniform(0.02, 1.0)), float(rng.uniform(0.05, 0.7))
+        mode = int(rng.integers(0, 2))
+        push = str(rng.choice(["16", "0", "4", "64"]))
+        monkeypatch.setenv("RAC_PUSH_RATIO", push)
+        inst = gen.model_b(3000 + c, n, d, p1, p2)
+        doms, _ = gen.partial_assign_states(4000 + c, n, d, B, min(n, int(rng.integers(0, 20))))
+        rel = inst.rel_u8()
+        say(f"[gpu] random {c}: path={path} n={n} d={d} B={B} p1={p1:.2f} p2={p2:.2f} "
+            f"mode={mode} push={push}")
+        net = rac.Net.from_u8(n, d, inst.edges, rel, path=path, mode=mode)
+        if B == 1 or c % 3 == 0:
+            one, it, st = net.enforce(doms[0])
+            got, iters, status, B = one[None], np.array([it]), np.array([st]), 1
+        else:
+            got, iters, status = net.enforce_batch(doms)
+        net.close()
+        for s in range(B):
+            exp, e_it, e_st, _, _ = oracle_expect(n, d, inst.edges, rel, doms[s], mode)
+            assert np.array_equal(got[s], exp), f"case {c} state {s}"
+            assert iters[s] == e_it and status[s] == e_st, f"case {c} state {s}"
+
+
 def test_batch_states_mfma_random_shapes(monkeypatch):
     # Seeded random shapes on the matrix-core path (n 8..319, d 2..32, B
     # 1..299, density and tightness across their range), each with a random
