@@ -350,6 +350,40 @@ def test_random_shapes_bits_int8_fused(monkeypatch):
             assert iters[s] == e_it and status[s] == e_st, f"case {c} state {s}"
 
 
+def test_random_groups_with_member_calls():
+    # Seeded random groups (2..23 uneven networks, d up to 64), each enforced
+    # twice with a single-state call on one member net in between (the member
+    # rebuilds its own work items; the group keeps its tables); everything
+    # against the oracle.
+    rng = np.random.default_rng(2026)
+    for c in range(8):
+        k = int(rng.integers(2, 24))
+        insts, doms = [], []
+        for i in range(k):
+            n, d = int(rng.integers(10, 300)), int(rng.integers(2, 65))
+            inst = gen.model_b(5000 + 100 * c + i, n, d, float(rng.uniform(0.05, 1.0)),
+                               float(rng.uniform(0.05, 0.6)))
+            dd, _ = gen.partial_assign_states(6000 + 100 * c + i, n, d, 1,
+                                              min(n, int(rng.integers(0, 15))))
+            insts.append(inst)
+            doms.append(dd[0])
+        say(f"[gpu] random group {c}: {k} nets")
+        nets = [rac.Net.from_instance(i) for i in insts]
+        exps = [oracle_expect(i.n, i.d, i.edges, i.rel_u8(), doms[j])[:3] for j, i in enumerate(insts)]
+        grp = rac.Group(nets)
+        for rep in range(2):
+            got, iters, status = grp.enforce(doms)
+            for j, (exp, e_it, e_st) in enumerate(exps):
+                assert np.array_equal(got[j], exp), f"group {c} rep {rep} net {j}"
+                assert iters[j] == e_it and status[j] == e_st, f"group {c} rep {rep} net {j}"
+            j = int(rng.integers(0, k))
+            one, it, st = nets[j].enforce(doms[j])
+            assert np.array_equal(one, exps[j][0]) and (it, st) == exps[j][1:], f"net {j}"
+        grp.close()
+        for nt in nets:
+            nt.close()
+
+
 def test_batch_states_mfma_random_shapes(monkeypatch):
     # Seeded random shapes on the matrix-core path (n 8..319, d 2..32, B
     # 1..299, density and tightness across their range), each with a random
