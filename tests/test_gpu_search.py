@@ -234,3 +234,21 @@ def test_table1_cells_complete(n, p1):
     assert (res.solutions, res.nodes, res.failures, res.sweeps) == \
         (exp["solutions"], exp["nodes"], exp["failures"], exp["steps"])
     assert res.sweeps / res.nodes == exp["steps"] / exp["nodes"]   # steps per assignment
+
+
+def test_random_instances_random_batches():
+    # Seeded small model-B instances (n 4..12, d 2..4, d^n <= 2e5, density
+    # and tightness across their range) searched completely with a random path and batch
+    # size; counts, recurrence steps and the smallest solution against the
+    # oracle's MAC search.
+    rng = np.random.default_rng(2027)
+    for c in range(16):
+        n, d = int(rng.integers(4, 13)), int(rng.integers(2, 5))
+        while d ** n > 200000:   # keeps the oracle's tree small
+            n -= 1
+        p1, p2 = float(rng.uniform(0.1, 0.9)), float(rng.uniform(0.1, 0.5))
+        path = int(rng.choice([rac.PATH_AUTO, rac.PATH_BITS, rac.PATH_FUSED]))
+        b = int(rng.choice([1, 3, 64, 4096]))
+        inst = gen.model_b(7000 + c, n, d, p1, p2)
+        check(f"random{c}", n, d, inst.edges, inst.rel_u8(), full_masks(n, d), batches=(b,),
+              path=path)
